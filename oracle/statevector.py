@@ -1,0 +1,277 @@
+"""complex128 gate-at-a-time state-vector simulator -- the oracle.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring): never imported by the
+product path.
+
+What it follows
+---------------
+* Sec. II.B: the state of an n-qubit system is a vector of 2^n complex
+  amplitudes (16 bytes each, i.e. complex128); simulating a circuit applies
+  each gate of the sequence, in order, to that vector.
+* Sec. III.A and the Fig. 1 caption: amplitudes are indexed little-endian,
+  so bit q of the index is the value of qubit q; a one-qubit gate on qubit i
+  pairs the amplitudes whose indices differ only in bit i (stride s = 2^i)
+  and multiplies each pair by the 2x2 gate matrix -- 2^(n-1) independent
+  matrix-vector products per gate.
+* Sec. II.A: the matrices of X, Y, Z and H are the ones printed there.  The
+  paper names CX and SWAP without matrices and uses rotation/phase gates
+  only through its benchmark circuits; the readings used for RX, RY, RZ, P,
+  U3, S, T, CX, CZ, CP and SWAP are the standard OpenQASM-2 ones, listed in
+  the design notes (rotation RZ keeps its global phase:
+  RZ(t) = diag(e^{-it/2}, e^{it/2})).
+* Sec. II.A: probabilities are |amplitude|^2 (the paper writes alpha^2).
+* Alg. 1 (Sec. III.C): ``simulate_alg1`` executes a given partition literally
+  -- for every setting of the qubits outside a part, gather the 2^w
+  amplitudes addressed by the part's qubits into a small inner vector, run
+  the part's gates on it, scatter back.  The inner slots take the part's
+  qubits in ascending global order, which matches the worked example of
+  Sec. III.C (S0 = {q1, q0} -> in_sv[q1, q0]).
+
+Two-qubit gates are written by what they do to amplitudes, so no 4x4
+basis-ordering convention is needed:
+  CX(c, t):  for indices with bit c = 1, swap the pair differing in bit t;
+  CZ(a, b):  negate amplitudes with bit a = bit b = 1;
+  CP(l)(a,b): multiply amplitudes with bit a = bit b = 1 by e^{il};
+  SWAP(a, b): exchange amplitudes with (bit a, bit b) = (1, 0) and (0, 1).
+
+Everything is float64 / complex128 numpy; no blocking, fusion or reordering.
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+ONE_QUBIT = ("h", "x", "y", "z", "s", "t", "rx", "ry", "rz", "p", "u3")
+TWO_QUBIT = ("cx", "cz", "cp", "swap")
+
+
+def gate_matrix_1q(name: str, params=()) -> np.ndarray:
+    """2x2 complex128 matrix of a one-qubit gate (Sec. II.A; readings above)."""
+    p = tuple(float(v) for v in params)
+    if name == "h":
+        return np.array([[1, 1], [1, -1]], dtype=np.complex128) / math.sqrt(2.0)
+    if name == "x":
+        return np.array([[0, 1], [1, 0]], dtype=np.complex128)
+    if name == "y":
+        return np.array([[0, -1j], [1j, 0]], dtype=np.complex128)
+    if name == "z":
+        return np.array([[1, 0], [0, -1]], dtype=np.complex128)
+    if name == "s":
+        return np.array([[1, 0], [0, 1j]], dtype=np.complex128)
+    if name == "t":
+        return np.array([[1, 0], [0, np.exp(1j * math.pi / 4)]], dtype=np.complex128)
+    if name == "rx":
+        c, s = math.cos(p[0] / 2), math.sin(p[0] / 2)
+        return np.array([[c, -1j * s], [-1j * s, c]], dtype=np.complex128)
+    if name == "ry":
+        c, s = math.cos(p[0] / 2), math.sin(p[0] / 2)
+        return np.array([[c, -s], [s, c]], dtype=np.complex128)
+    if name == "rz":
+        return np.array([[np.exp(-0.5j * p[0]), 0], [0, np.exp(0.5j * p[0])]],
+                        dtype=np.complex128)
+    if name == "p":
+        return np.array([[1, 0], [0, np.exp(1j * p[0])]], dtype=np.complex128)
+    if name == "u3":
+        th, ph, la = p[0], p[1], p[2]
+        c, s = math.cos(th / 2), math.sin(th / 2)
+        return np.array([[c, -np.exp(1j * la) * s],
+                         [np.exp(1j * ph) * s, np.exp(1j * (ph + la)) * c]],
+                        dtype=np.complex128)
+    raise ValueError(f"not a one-qubit gate: {name!r}")
+
+
+def num_qubits_of(psi: np.ndarray) -> int:
+    n = int(psi.size).bit_length() - 1
+    if psi.ndim != 1 or (1 << n) != psi.size:
+        raise ValueError("state must be a 1-D vector of length 2^n")
+    return n
+
+
+def basis_state(n: int, x: int = 0) -> np.ndarray:
+    """|x> as complex128 (Sec. II.B); x = 0 is |0...0>."""
+    psi = np.zeros(1 << n, dtype=np.complex128)
+    psi[x] = 1.0
+    return psi
+
+
+def apply_1q(psi: np.ndarray, q: int, u: np.ndarray) -> None:
+    """In place: the 2^(n-1) scoped 2x2 products of Sec. III.A on qubit q.
+
+    Viewing the vector as (high, bit q, low) puts the two members of every
+    pair (index with bit q = 0, the same index with bit q = 1) at [:, 0, :]
+    and [:, 1, :].
+    """
+    v = psi.reshape(-1, 2, 1 << q)
+    a0 = v[:, 0, :].copy()
+    a1 = v[:, 1, :].copy()
+    v[:, 0, :] = u[0, 0] * a0 + u[0, 1] * a1
+    v[:, 1, :] = u[1, 0] * a0 + u[1, 1] * a1
+
+
+def _view2(psi: np.ndarray, n: int, a: int, b: int) -> tuple[np.ndarray, bool]:
+    """View psi as [high, bit hi, mid, bit lo, low] for qubits a != b.
+
+    Returns the view and whether ``a`` is the higher of the two qubits.
+    """
+    hi, lo = (a, b) if a > b else (b, a)
+    v = psi.reshape(1 << (n - hi - 1), 2, 1 << (hi - lo - 1), 2, 1 << lo)
+    return v, a > b
+
+
+def apply_2q(psi: np.ndarray, name: str, a: int, b: int, params=()) -> None:
+    """In place: CX(control a, target b), CZ, CP(lambda), SWAP on qubits a, b."""
+    n = num_qubits_of(psi)
+    v, a_is_hi = _view2(psi, n, a, b)
+
+    def sl(bit_a: int, bit_b: int):
+        # index into the 5-D view with the bits of qubits a and b fixed
+        if a_is_hi:
+            return (slice(None), bit_a, slice(None), bit_b, slice(None))
+        return (slice(None), bit_b, slice(None), bit_a, slice(None))
+
+    if name == "cx":
+        t0 = v[sl(1, 0)].copy()
+        v[sl(1, 0)] = v[sl(1, 1)]
+        v[sl(1, 1)] = t0
+    elif name == "cz":
+        v[sl(1, 1)] *= -1.0
+    elif name == "cp":
+        v[sl(1, 1)] *= np.exp(1j * float(params[0]))
+    elif name == "swap":
+        t0 = v[sl(1, 0)].copy()
+        v[sl(1, 0)] = v[sl(0, 1)]
+        v[sl(0, 1)] = t0
+    else:
+        raise ValueError(f"not a two-qubit gate: {name!r}")
+
+
+def check_gate(n: int, gate) -> None:
+    name, q0, q1, _ = gate
+    if name in ONE_QUBIT:
+        if not (0 <= q0 < n) or q1 != -1:
+            raise ValueError(f"bad one-qubit gate {gate!r} for n={n}")
+    elif name in TWO_QUBIT:
+        if not (0 <= q0 < n and 0 <= q1 < n) or q0 == q1:
+            raise ValueError(f"bad two-qubit gate {gate!r} for n={n}")
+    else:
+        raise ValueError(f"unknown gate {name!r}")
+
+
+def apply_gate(psi: np.ndarray, gate) -> None:
+    name, q0, q1, params = gate
+    n = num_qubits_of(psi)
+    check_gate(n, gate)
+    if name in ONE_QUBIT:
+        apply_1q(psi, q0, gate_matrix_1q(name, params))
+    else:
+        apply_2q(psi, name, q0, q1, params)
+
+
+def simulate(n: int, gates, init=0) -> np.ndarray:
+    """Apply ``gates`` in circuit order to |init> (an int) or to a given vector.
+
+    Sec. II.B: the simulation applies each gate of the sequence to the state.
+    """
+    if isinstance(init, np.ndarray):
+        psi = np.array(init, dtype=np.complex128, copy=True)
+        if psi.size != (1 << n):
+            raise ValueError("initial vector has the wrong length")
+    else:
+        psi = basis_state(n, int(init))
+    for g in gates:
+        apply_gate(psi, g)
+    return psi
+
+
+def probabilities(psi: np.ndarray) -> np.ndarray:
+    """|a|^2 per amplitude (Sec. II.A, read as the squared modulus)."""
+    return psi.real * psi.real + psi.imag * psi.imag
+
+
+def norm(psi: np.ndarray) -> float:
+    """Sum of |a|^2 over the whole state (1 for a normalised state)."""
+    return float(math.fsum(probabilities(psi).tolist())) if psi.size <= (1 << 16) \
+        else float(np.sum(probabilities(psi), dtype=np.float64))
+
+
+def inverse_gate(gate):
+    """The gate whose matrix is the adjoint of ``gate``'s (for round trips)."""
+    name, q0, q1, p = gate
+    p = tuple(p)
+    if name in ("h", "x", "y", "z", "cx", "cz", "swap"):
+        return gate
+    if name == "s":
+        return ("p", q0, q1, (-math.pi / 2,))
+    if name == "t":
+        return ("p", q0, q1, (-math.pi / 4,))
+    if name in ("rx", "ry", "rz", "p", "cp"):
+        return (name, q0, q1, (-p[0],))
+    if name == "u3":
+        # U3(t, f, l)^dagger = U3(-t, -l, -f)
+        return ("u3", q0, q1, (-p[0], -p[2], -p[1]))
+    raise ValueError(name)
+
+
+def inverse_circuit(gates):
+    return [inverse_gate(g) for g in reversed(list(gates))]
+
+
+# ---------------------------------------------------------------------------
+# Alg. 1 executed literally (small n only: pure-Python loop over settings)
+# ---------------------------------------------------------------------------
+
+def gather_addresses(n: int, part_qubits) -> np.ndarray:
+    """Alg. 1 gather map: row r = outer setting r, column j = inner slot j.
+
+    Entry [r, j] is the index in out_sv of the amplitude that lands in
+    in_sv[j] for the r-th setting of the qubits outside the part.  Bit b of r
+    is the value of the b-th smallest outer qubit; bit b of j is the value of
+    the b-th smallest part qubit (Sec. III.C: S0 = {q1, q0} -> in_sv[q1, q0]).
+    """
+    qubits = sorted(int(q) for q in part_qubits)
+    outer = [q for q in range(n) if q not in qubits]
+    w = len(qubits)
+    addr = np.zeros((1 << len(outer), 1 << w), dtype=np.int64)
+    for r in range(1 << len(outer)):
+        base = 0
+        for bit, q in enumerate(outer):
+            if (r >> bit) & 1:
+                base |= 1 << q
+        for j in range(1 << w):
+            a = base
+            for bit, q in enumerate(qubits):
+                if (j >> bit) & 1:
+                    a |= 1 << q
+            addr[r, j] = a
+    return addr
+
+
+def simulate_alg1(n: int, gates, part_of_gate, init=0) -> np.ndarray:
+    """Gather-Execute-Scatter over a given partition (Alg. 1, Sec. III.C).
+
+    Parts run in increasing part id (the ids must already be a topological
+    order of the part-graph); within a part the gates keep circuit order
+    (Sec. IV.A, last paragraph of the model).  For every setting of the
+    t = n - w qubits outside the part, the 2^w amplitudes addressed by the
+    part's qubits are gathered into ``in_sv`` (inner slot j <- the j-th
+    smallest part qubit), the part's gates -- renamed to inner slots -- run on
+    it gate by gate, and the result is scattered back.
+    """
+    psi = simulate(n, [], init)
+    parts = {}
+    for gi, p in enumerate(part_of_gate):
+        parts.setdefault(int(p), []).append(gi)
+    for p in sorted(parts):
+        gate_list = [gates[i] for i in parts[p]]
+        qubits = sorted({q for g in gate_list for q in (g[1], g[2]) if q >= 0})
+        slot = {q: j for j, q in enumerate(qubits)}
+        inner_gates = [(g[0], slot[g[1]], slot[g[2]] if g[2] >= 0 else -1, g[3])
+                       for g in gate_list]
+        for addr in gather_addresses(n, qubits):
+            in_sv = psi[addr].copy()            # Gather
+            for g in inner_gates:               # Execute
+                apply_gate(in_sv, g)
+            psi[addr] = in_sv                   # Scatter
+    return psi
