@@ -1,0 +1,285 @@
+/*
+ * hisv.h -- C ABI of the partitioned state-vector library (libhisv.so).
+ *
+ * Method: Fang et al., "Efficient Hierarchical State Vector Simulation of
+ * Quantum Circuits via Acyclic Graph Partitioning" (arXiv 2205.06973).
+ *
+ *   - Sec. II.B: given an initial n-qubit state (2^n complex amplitudes) and
+ *     a sequence of gates, apply every gate in order.
+ *   - Sec. IV.A: the circuit is a DAG of gates; an acyclic partition splits it
+ *     into parts whose working set (distinct qubits) is at most L_m (called k
+ *     here), with an acyclic part-graph; the output is a part id per gate and
+ *     the gates of a part keep circuit order.
+ *   - Alg. 1 (Sec. III.C): each part is applied to the whole state by
+ *     Gather-Execute-Scatter: for every setting of the qubits outside the
+ *     part, the 2^w amplitudes addressed by the part's qubits are gathered,
+ *     the part's gates run on them, and they are scattered back -- one sweep
+ *     of the state per part instead of one per gate.
+ *
+ * Conventions (all entry points)
+ *   - State layout: 2^n interleaved complex numbers (re, im) in device memory,
+ *     complex64 (2 x float) or complex128 (2 x double); amplitude index bit q
+ *     is the value of qubit q (little-endian, Fig. 1 caption; a one-qubit gate
+ *     on qubit i pairs amplitudes 2^i apart, Sec. III.A).
+ *   - Every call returns an hs_status; nothing throws across the ABI.  On a
+ *     non-OK status, hs_last_error() returns a message for the calling thread.
+ *   - Handles are opaque and owned by the library; each has a *_destroy.
+ *     Host arrays passed in are copied; host output buffers belong to the
+ *     caller.  Device memory passed to hs_state_wrap stays the caller's.
+ *   - Work on a state is enqueued, in order, on the HIP stream given when the
+ *     state was made (NULL = the device's null stream).  Calls documented as
+ *     "syncs" wait for that stream before returning.
+ *   - Handles may be used from several threads, but calls on one state or
+ *     one plan must not overlap.
+ */
+#ifndef HISV_H
+#define HISV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HS_OK = 0,
+  HS_E_ARG = 1,            /* a null handle/pointer, bad size, bad enum, mismatched n */
+  HS_E_QUBIT_RANGE = 2,    /* a gate qubit outside [0, n), or both qubits equal      */
+  HS_E_ARITY_GT_K = 3,     /* a gate uses more qubits than the part limit k           */
+  HS_E_NOMEM = 4,          /* host or device allocation failed                        */
+  HS_E_ADMISSION = 5,      /* serving: request can never fit the byte budget          */
+  HS_E_HIP = 6,            /* a HIP runtime call failed (message has the HIP error)   */
+  HS_E_BAD_PARTITION = 7,  /* a plan failed exact validation                          */
+  HS_E_STATE = 8,          /* wrong object state (e.g. reading an unfinished ticket)  */
+  HS_E_UNSUPPORTED = 9     /* a valid request this build does not handle (e.g. a part
+                              wider than the largest kernel tile)                     */
+} hs_status;
+
+typedef enum { HS_C64 = 0, HS_C128 = 1 } hs_dtype;
+
+/* Gate kinds.  X, Y, Z, H are the matrices of Sec. II.A; the others use the
+ * OpenQASM-2 definitions: S = diag(1, i), T = diag(1, e^{i pi/4}),
+ * RX(t) = [[c, -i s], [-i s, c]], RY(t) = [[c, -s], [s, c]] (c = cos t/2,
+ * s = sin t/2), RZ(t) = diag(e^{-it/2}, e^{it/2}), P(l) = diag(1, e^{il}),
+ * U3(t, f, l) = [[c, -e^{il} s], [e^{if} s, e^{i(f+l)} c]];
+ * CX(q0 = control, q1 = target); CZ, CP(l) multiply amplitudes with both
+ * qubits set by -1 and e^{il}; SWAP exchanges the two qubits. */
+typedef enum {
+  HS_H = 0, HS_X = 1, HS_Y = 2, HS_Z = 3, HS_S = 4, HS_T = 5,
+  HS_RX = 6, HS_RY = 7, HS_RZ = 8, HS_P = 9, HS_U3 = 10,
+  HS_CX = 11, HS_CZ = 12, HS_CP = 13, HS_SWAP = 14
+} hs_kind;
+
+/* One gate: q1 = -1 for one-qubit kinds; p[] holds the angles (unused ones
+ * ignored).  40 bytes, naturally aligned. */
+typedef struct {
+  int32_t kind;
+  int32_t q0;
+  int32_t q1;
+  int32_t reserved;  /* must be 0 */
+  double p[3];
+} hs_gate;
+
+/* Sec. IV.B: natural topological-order cutoff (Nat), the same cutoff over
+ * seeded random DFS topological orders keeping the fewest parts (DFS), and an
+ * acyclic recursive-bisection partitioner with a final merge phase (DAGP). */
+typedef enum { HS_PART_NAT = 0, HS_PART_DFS = 1, HS_PART_DAGP = 2 } hs_strategy;
+
+/* How hs_simulate applies a plan:
+ *   GATE_PER_PASS -- ignore the partition; one sweep of the state per gate
+ *                    (the non-hierarchical case of Sec. III.B);
+ *   PART_LDS      -- one sweep per part; each part runs gate by gate on
+ *                    register-resident sub-states, staged through LDS;
+ *   PART_FUSED    -- one sweep per part; each part's gates are multiplied
+ *                    into one dense 2^w x 2^w unitary applied on matrix cores;
+ *   AUTO          -- per part, the cheaper of PART_LDS and PART_FUSED. */
+typedef enum {
+  HS_EXEC_GATE_PER_PASS = 0, HS_EXEC_PART_LDS = 1, HS_EXEC_PART_FUSED = 2, HS_EXEC_AUTO = 3
+} hs_exec;
+
+typedef struct hs_state_* hs_state;
+typedef struct hs_circuit_* hs_circuit;
+typedef struct hs_plan_* hs_plan;
+
+/* ---- library ------------------------------------------------------------ */
+
+/* Version string of the library; never NULL. */
+const char* hs_version(void);
+
+/* Message for the last non-OK status returned on the calling thread ("" if
+ * none).  The pointer stays valid until the thread's next failing call. */
+const char* hs_last_error(void);
+
+/* Number of HIP devices visible (0 on a machine without a GPU). */
+hs_status hs_device_count(int* out);
+
+/* Largest part width k that hs_simulate with PART_LDS / PART_FUSED accepts
+ * for the given dtype (the tile capacity of the kernels). */
+hs_status hs_max_part_qubits(hs_dtype dtype, hs_exec exec, int* out);
+
+/* ---- states (Sec. II.B) --------------------------------------------------- */
+
+/* New n-qubit state in library-owned device memory on the current device,
+ * bound to `hip_stream` (a hipStream_t, may be NULL).  Contents undefined
+ * until hs_state_set_basis.  1 <= n <= 40; HS_E_NOMEM if it does not fit. */
+hs_status hs_state_create(int n, hs_dtype dtype, void* hip_stream, hs_state* out);
+
+/* Borrow caller-owned device memory `dev_ptr` of `bytes` bytes holding 2^n
+ * amplitudes of `dtype` (bytes must be exactly 2^n * 8 or 2^n * 16), bound
+ * to `hip_stream`.  The memory must outlive the handle. */
+hs_status hs_state_wrap(int n, hs_dtype dtype, void* dev_ptr, size_t bytes,
+                        void* hip_stream, hs_state* out);
+
+/* Set the state to the basis state |x> (x < 2^n; x = 0 is |0...0>). */
+hs_status hs_state_set_basis(hs_state s, uint64_t x);
+
+hs_status hs_state_info(hs_state s, int* n, hs_dtype* dtype, void** dev_ptr);
+hs_status hs_state_destroy(hs_state s);
+
+/* ---- circuits (Sec. II.B: a sequence of gates) ----------------------------- */
+
+/* Copy and validate `count` gates on n qubits.  HS_E_QUBIT_RANGE for a qubit
+ * outside [0, n) or a two-qubit gate on one qubit; HS_E_ARG for an unknown
+ * kind, a one-qubit gate with q1 != -1 or reserved != 0. */
+hs_status hs_circuit_load(int n, const hs_gate* gates, size_t count, hs_circuit* out);
+hs_status hs_circuit_info(hs_circuit c, int* n, size_t* count);
+hs_status hs_circuit_destroy(hs_circuit c);
+
+/* ---- partitioning (Sec. IV) ------------------------------------------------ */
+
+/* Partition the circuit's gate DAG into acyclic parts of at most k qubits
+ * (Sec. IV.A conditions i-ii), minimising the part count heuristically
+ * (condition iii).  `seed` and `trials` drive DFS (trial 0 is the natural
+ * order, so DFS never returns more parts than Nat) and are ignored by Nat.
+ * Parts are numbered in a topological order of the part-graph.
+ * HS_E_ARITY_GT_K if a gate is wider than k; HS_E_ARG if k < 1. */
+hs_status hs_partition(hs_circuit c, int k, hs_strategy strategy, uint64_t seed,
+                       int trials, hs_plan* out);
+
+/* Build a plan from a caller-given assignment part_of_gate[count] (ids
+ * 0..P-1).  HS_E_BAD_PARTITION unless it passes hs_plan_validate's checks. */
+hs_status hs_plan_from_assignment(hs_circuit c, int k, const int32_t* part_of_gate,
+                                  hs_plan* out);
+
+hs_status hs_plan_num_parts(hs_plan p, int* parts);
+
+/* part_of_gate[count] (caller-owned, count = the circuit's gate count). */
+hs_status hs_plan_part_of_gate(hs_plan p, int32_t* out);
+
+/* Qubit mask (bit q set if the part uses qubit q) and gate count of a part. */
+hs_status hs_plan_part_info(hs_plan p, int part, uint64_t* qubit_mask, int* num_gates);
+
+/* Exact check: every gate in exactly one non-empty part, every part uses at
+ * most k qubits, the part-graph is acyclic and every cross-part edge goes
+ * from a lower to a higher part id.  HS_OK or HS_E_BAD_PARTITION. */
+hs_status hs_plan_validate(hs_plan p);
+
+/* Kernel-level layout of a part as compiled for `dtype` and PART_LDS: tile
+ * width m (qubits per gathered sub-state, the part's qubits plus the lowest
+ * other qubits as padding), register stages, LDS round trips per tile. */
+hs_status hs_plan_part_layout(hs_plan p, int part, hs_dtype dtype, int* tile_qubits,
+                              int* stages, int* lds_round_trips);
+
+/* Introspection of the compiled descriptors of a part (PART_LDS, `dtype`),
+ * so tests can replay them on the host.  header[24] = {m, lb, wb, rb,
+ * entries, LDS round trips, ops, log2(tiles), tq[16]} (tq = tile bit ->
+ * qubit).  entries[20 * entries] (filled if entries_cap >= entries): per
+ * entry pos[16] (coordinate bit -> tile bit; lane bits, then wave bits, then
+ * register bits), op_begin, op_end (relative to the part), transition, 0;
+ * entry 0 is the load layout and the last entry the store layout.
+ * ops[11 * ops] (filled if ops_cap >= ops): kind, b0, b1, c[8] with kinds
+ * 0 dense 2x2, 1 real 2x2, 2 diagonal, 3 diag(1, d), 4 X, 5 CX, 6 CZ,
+ * 7 controlled phase, 8 SWAP. */
+hs_status hs_plan_part_descriptors(hs_plan p, int part, hs_dtype dtype, int32_t* header,
+                                   int32_t* entries, int entries_cap, double* ops, int ops_cap);
+
+hs_status hs_plan_destroy(hs_plan p);
+
+/* ---- simulation (Alg. 1) --------------------------------------------------- */
+
+/* Apply the plan's circuit to the state, part after part in id order, each
+ * part as one sweep (Alg. 1), or one sweep per gate for GATE_PER_PASS.
+ * Asynchronous on the state's stream.  HS_E_ARG if the plan's n differs
+ * from the state's; HS_E_UNSUPPORTED if a part exceeds hs_max_part_qubits. */
+hs_status hs_simulate(hs_state s, hs_plan p, hs_exec exec);
+
+/* One sweep per gate of the circuit, in circuit order (no partition). */
+hs_status hs_simulate_gate_per_pass(hs_state s, hs_circuit c);
+
+/* Apply a single part of a plan (one sweep).  Asynchronous. */
+hs_status hs_simulate_part(hs_state s, hs_plan p, int part, hs_exec exec);
+
+/* ---- readout (Sec. II.A-B) ------------------------------------------------- */
+
+/* Copy amplitudes [first, first+count) to host as interleaved complex128
+ * (out has 2*count doubles; complex64 states are widened on the device).
+ * Syncs. */
+hs_status hs_read_amplitudes(hs_state s, uint64_t first, uint64_t count, double* out);
+
+/* |a|^2 in FP64 for amplitudes [first, first+count) into out[count].  Syncs. */
+hs_status hs_probabilities(hs_state s, uint64_t first, uint64_t count, double* out);
+
+/* Sum of |a|^2 over the whole state, accumulated in FP64 in a fixed-order
+ * two-level tree (the same result on every run).  Syncs. */
+hs_status hs_norm(hs_state s, double* out);
+
+/* Wait for all work queued on the state's stream. */
+hs_status hs_sync(hs_state s);
+
+/* ---- measurement helper ---------------------------------------------------- */
+
+/* Device-to-device copy of `bytes` bytes (multiple of 16) by a plain
+ * streaming kernel, on `hip_stream`; used to calibrate HBM byte counters
+ * against a kernel whose traffic is known. */
+hs_status hs_copy_probe(const void* src, void* dst, size_t bytes, void* hip_stream);
+
+/* ---- serving: continuous batching of many circuits ------------------------- */
+
+typedef struct hs_server_* hs_server;
+
+/* A server owns a pool of `num_streams` HIP streams on the current device
+ * and admits requests while the device bytes of resident states (plus their
+ * plans) stay within `budget_bytes` (0 = free device memory at creation
+ * minus a 4 GiB reserve).  A worker thread admits, launches and retires
+ * requests; several requests are in flight on the device at once. */
+hs_status hs_server_create(size_t budget_bytes, int num_streams, hs_server* out);
+
+/* Queue a circuit (copied) to be partitioned with limit k (Nat when
+ * strategy = NAT, DFS otherwise), simulated from |init_basis> in `dtype`,
+ * and kept resident until released.  Returns a ticket.  HS_E_ADMISSION if
+ * the state can never fit the budget.  Non-blocking. */
+hs_status hs_server_submit(hs_server sv, int n, const hs_gate* gates, size_t count,
+                           hs_dtype dtype, uint64_t init_basis, int k,
+                           hs_strategy strategy, uint64_t* ticket);
+
+/* Block until the ticket's result is ready (timeout_ms < 0: no limit).
+ * HS_E_STATE on timeout. */
+hs_status hs_server_wait(hs_server sv, uint64_t ticket, int64_t timeout_ms);
+
+/* Non-blocking: *done = 1 if the ticket's result is ready. */
+hs_status hs_server_poll(hs_server sv, uint64_t ticket, int* done);
+
+/* Read amplitudes of a finished request (as hs_read_amplitudes). */
+hs_status hs_server_read(hs_server sv, uint64_t ticket, uint64_t first, uint64_t count,
+                         double* out);
+
+/* Latency (submit to completion, seconds) of a finished request. */
+hs_status hs_server_latency(hs_server sv, uint64_t ticket, double* seconds);
+
+/* Free a finished request's device memory (its bytes return to the budget). */
+hs_status hs_server_release(hs_server sv, uint64_t ticket);
+
+/* Counters: requests completed, peak admitted bytes, current admitted bytes,
+ * peak number of requests on the device at once. */
+hs_status hs_server_stats(hs_server sv, uint64_t* completed, uint64_t* peak_bytes,
+                          uint64_t* cur_bytes, int* peak_inflight);
+
+/* Wait for all submitted requests, stop the worker, free everything. */
+hs_status hs_server_destroy(hs_server sv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HISV_H */

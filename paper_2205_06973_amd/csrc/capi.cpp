@@ -1,0 +1,418 @@
+// capi.cpp -- the extern "C" entry points declared in include/hisv.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "hisv_internal.h"
+
+namespace hisv {
+const char* last_error();
+}
+
+using namespace hisv;
+
+struct hs_state_ : State {};
+struct hs_circuit_ : Circuit {};
+struct hs_plan_ : Plan {};
+
+#define CHECK_ARG(cond, ...) \
+  do {                       \
+    if (!(cond)) return fail(HS_E_ARG, __VA_ARGS__); \
+  } while (0)
+
+namespace hisv {
+
+Plan::~Plan() {
+  for (int d = 0; d < 2; ++d)
+    for (auto& kv : dev[d]) device_plan_free(kv.second);
+}
+
+CompileOptions default_options(hs_dtype dtype) {
+  CompileOptions o;
+  if (dtype == HS_C64) {
+    o.rb = 4;
+    o.swizzle = 4;
+    o.max_m = 14;  // 2^14 x 8 B = 128 KiB of LDS
+  } else {
+    o.rb = 3;
+    o.swizzle = 3;
+    o.max_m = 13;  // 2^13 x 16 B = 128 KiB of LDS
+  }
+  return o;
+}
+
+hs_status plan_build(int n, const std::vector<Gate>& gates, int k,
+                     const std::vector<int32_t>& part_of_gate, Plan* p) {
+  p->n = n;
+  p->k = k;
+  p->gates = gates;
+  p->dag = build_dag(gates);
+  p->part_of_gate = part_of_gate;
+  const std::string err = check_partition(gates, p->dag, part_of_gate, k);
+  if (!err.empty()) return fail(HS_E_BAD_PARTITION, "invalid partition: %s", err.c_str());
+  int P = 0;
+  for (int32_t v : part_of_gate) P = std::max(P, v + 1);
+  p->parts.assign(P, {});
+  p->masks.assign(P, 0);
+  for (size_t i = 0; i < gates.size(); ++i) {
+    p->parts[part_of_gate[i]].push_back((int)i);
+    p->masks[part_of_gate[i]] |= gates[i].mask();
+  }
+  return HS_OK;
+}
+
+hs_status plan_compile(Plan* p, hs_dtype dtype) {
+  std::lock_guard<std::mutex> lk(p->mu);
+  if (p->compiled[dtype]) return HS_OK;
+  const CompileOptions opt = default_options(dtype);
+  std::vector<CompiledPart> comp(p->parts.size());
+  std::vector<Gate> pg;
+  for (size_t i = 0; i < p->parts.size(); ++i) {
+    pg.clear();
+    for (int gi : p->parts[i]) pg.push_back(p->gates[gi]);
+    if (hs_status rc = compile_part(p->n, pg, opt, &comp[i])) return rc;
+  }
+  p->comp[dtype].swap(comp);
+  p->compiled[dtype] = true;
+  return HS_OK;
+}
+
+}  // namespace hisv
+
+extern "C" {
+
+const char* hs_version(void) { return "hisv 0.1 (gfx950)"; }
+
+const char* hs_last_error(void) { return hisv::last_error(); }
+
+hs_status hs_device_count(int* out) {
+  CHECK_ARG(out, "null output");
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess) n = 0;
+  *out = n;
+  return HS_OK;
+}
+
+hs_status hs_max_part_qubits(hs_dtype dtype, hs_exec exec, int* out) {
+  CHECK_ARG(out, "null output");
+  CHECK_ARG(dtype == HS_C64 || dtype == HS_C128, "bad dtype %d", (int)dtype);
+  (void)exec;
+  const CompileOptions o = default_options(dtype);
+  *out = max_tile_qubits(o) - o.contig;
+  return HS_OK;
+}
+
+// ---- states ------------------------------------------------------------------
+
+static hs_status new_state(int n, hs_dtype dtype, void* stream, hs_state* out) {
+  CHECK_ARG(out, "null output");
+  CHECK_ARG(n >= 1 && n <= 40, "n = %d outside [1, 40]", n);
+  CHECK_ARG(dtype == HS_C64 || dtype == HS_C128, "bad dtype %d", (int)dtype);
+  auto* s = new hs_state_();
+  s->n = n;
+  s->dtype = dtype;
+  s->bytes = (size_t(1) << n) * amp_bytes(dtype);
+  s->stream = stream;
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    return fail(HS_E_HIP, "no HIP device");
+  }
+  *out = s;
+  return HS_OK;
+}
+
+hs_status hs_state_create(int n, hs_dtype dtype, void* hip_stream, hs_state* out) {
+  hs_state s = nullptr;
+  if (hs_status rc = new_state(n, dtype, hip_stream, &s)) return rc;
+  hipError_t e = hipMalloc(&s->ptr, s->bytes);
+  if (e != hipSuccess) {
+    hipGetLastError();
+    delete s;
+    return fail(HS_E_NOMEM, "hipMalloc(%zu): %s", (size_t(1) << n) * amp_bytes(dtype),
+                hipGetErrorString(e));
+  }
+  s->owned = true;
+  *out = s;
+  return HS_OK;
+}
+
+hs_status hs_state_wrap(int n, hs_dtype dtype, void* dev_ptr, size_t bytes, void* hip_stream,
+                        hs_state* out) {
+  CHECK_ARG(dev_ptr, "null device pointer");
+  CHECK_ARG(n >= 1 && n <= 40, "n = %d outside [1, 40]", n);
+  CHECK_ARG(dtype == HS_C64 || dtype == HS_C128, "bad dtype %d", (int)dtype);
+  CHECK_ARG(bytes == (size_t(1) << n) * amp_bytes(dtype), "buffer of %zu bytes is not 2^%d amplitudes",
+            bytes, n);
+  CHECK_ARG(((uintptr_t)dev_ptr % amp_bytes(dtype)) == 0, "device pointer not aligned to an amplitude");
+  hs_state s = nullptr;
+  if (hs_status rc = new_state(n, dtype, hip_stream, &s)) return rc;
+  s->ptr = dev_ptr;
+  s->owned = false;
+  *out = s;
+  return HS_OK;
+}
+
+hs_status hs_state_set_basis(hs_state s, uint64_t x) {
+  CHECK_ARG(s, "null state");
+  CHECK_ARG(x < (uint64_t(1) << s->n), "basis index outside the state");
+  return dev_set_basis(s, x);
+}
+
+hs_status hs_state_info(hs_state s, int* n, hs_dtype* dtype, void** dev_ptr) {
+  CHECK_ARG(s, "null state");
+  if (n) *n = s->n;
+  if (dtype) *dtype = s->dtype;
+  if (dev_ptr) *dev_ptr = s->ptr;
+  return HS_OK;
+}
+
+hs_status hs_state_destroy(hs_state s) {
+  if (!s) return HS_OK;
+  hipSetDevice(s->device);
+  if (s->stream) hipStreamSynchronize((hipStream_t)s->stream);
+  else hipDeviceSynchronize();
+  if (s->owned && s->ptr) hipFree(s->ptr);
+  if (s->scratch) hipFree(s->scratch);
+  delete s;
+  return HS_OK;
+}
+
+// ---- circuits ----------------------------------------------------------------
+
+hs_status hs_circuit_load(int n, const hs_gate* gates, size_t count, hs_circuit* out) {
+  CHECK_ARG(out, "null output");
+  CHECK_ARG(n >= 1 && n <= 40, "n = %d outside [1, 40]", n);
+  CHECK_ARG(gates || count == 0, "null gate array");
+  auto* c = new hs_circuit_();
+  c->n = n;
+  c->gates.resize(count);
+  for (size_t i = 0; i < count; ++i) {
+    if (hs_status rc = validate_gate(n, gates[i], &c->gates[i])) {
+      delete c;
+      return rc;
+    }
+  }
+  *out = c;
+  return HS_OK;
+}
+
+hs_status hs_circuit_info(hs_circuit c, int* n, size_t* count) {
+  CHECK_ARG(c, "null circuit");
+  if (n) *n = c->n;
+  if (count) *count = c->gates.size();
+  return HS_OK;
+}
+
+hs_status hs_circuit_destroy(hs_circuit c) {
+  delete c;
+  return HS_OK;
+}
+
+// ---- plans -------------------------------------------------------------------
+
+hs_status hs_partition(hs_circuit c, int k, hs_strategy strategy, uint64_t seed, int trials,
+                       hs_plan* out) {
+  CHECK_ARG(c && out, "null argument");
+  CHECK_ARG(k >= 1, "k = %d < 1", k);
+  for (const Gate& g : c->gates)
+    if (g.arity() > k) return fail(HS_E_ARITY_GT_K, "a %d-qubit gate does not fit k = %d", g.arity(), k);
+  std::vector<int32_t> part;
+  const Dag dag = build_dag(c->gates);
+  switch (strategy) {
+    case HS_PART_NAT: partition_nat(c->gates, k, &part); break;
+    case HS_PART_DFS:
+      CHECK_ARG(trials >= 1, "DFS needs trials >= 1");
+      partition_dfs(c->gates, dag, k, seed, trials, &part);
+      break;
+    case HS_PART_DAGP: return fail(HS_E_UNSUPPORTED, "DAGP partitioning is not built yet");
+    default: return fail(HS_E_ARG, "unknown strategy %d", (int)strategy);
+  }
+  auto* p = new hs_plan_();
+  if (hs_status rc = plan_build(c->n, c->gates, k, part, p)) {
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return HS_OK;
+}
+
+hs_status hs_plan_from_assignment(hs_circuit c, int k, const int32_t* part_of_gate, hs_plan* out) {
+  CHECK_ARG(c && out, "null argument");
+  CHECK_ARG(part_of_gate || c->gates.empty(), "null assignment");
+  CHECK_ARG(k >= 1, "k = %d < 1", k);
+  std::vector<int32_t> part(part_of_gate, part_of_gate + c->gates.size());
+  auto* p = new hs_plan_();
+  if (hs_status rc = plan_build(c->n, c->gates, k, part, p)) {
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return HS_OK;
+}
+
+hs_status hs_plan_num_parts(hs_plan p, int* parts) {
+  CHECK_ARG(p && parts, "null argument");
+  *parts = (int)p->parts.size();
+  return HS_OK;
+}
+
+hs_status hs_plan_part_of_gate(hs_plan p, int32_t* out) {
+  CHECK_ARG(p && (out || p->gates.empty()), "null argument");
+  std::copy(p->part_of_gate.begin(), p->part_of_gate.end(), out);
+  return HS_OK;
+}
+
+hs_status hs_plan_part_info(hs_plan p, int part, uint64_t* qubit_mask, int* num_gates) {
+  CHECK_ARG(p, "null plan");
+  CHECK_ARG(part >= 0 && part < (int)p->parts.size(), "part %d out of range", part);
+  if (qubit_mask) *qubit_mask = p->masks[part];
+  if (num_gates) *num_gates = (int)p->parts[part].size();
+  return HS_OK;
+}
+
+hs_status hs_plan_validate(hs_plan p) {
+  CHECK_ARG(p, "null plan");
+  const std::string err = check_partition(p->gates, p->dag, p->part_of_gate, p->k);
+  if (!err.empty()) return fail(HS_E_BAD_PARTITION, "invalid partition: %s", err.c_str());
+  return HS_OK;
+}
+
+hs_status hs_plan_part_layout(hs_plan p, int part, hs_dtype dtype, int* tile_qubits, int* stages,
+                              int* lds_round_trips) {
+  CHECK_ARG(p, "null plan");
+  CHECK_ARG(dtype == HS_C64 || dtype == HS_C128, "bad dtype");
+  CHECK_ARG(part >= 0 && part < (int)p->parts.size(), "part %d out of range", part);
+  if (hs_status rc = plan_compile(p, dtype)) return rc;
+  const CompiledPart& cp = p->comp[dtype][part];
+  if (tile_qubits) *tile_qubits = cp.desc.m;
+  if (stages) *stages = cp.desc.n_stages - 2;
+  if (lds_round_trips) *lds_round_trips = cp.lds_round_trips;
+  return HS_OK;
+}
+
+hs_status hs_plan_part_descriptors(hs_plan p, int part, hs_dtype dtype, int32_t* header,
+                                   int32_t* entries, int entries_cap, double* ops, int ops_cap) {
+  CHECK_ARG(p && header, "null argument");
+  CHECK_ARG(dtype == HS_C64 || dtype == HS_C128, "bad dtype");
+  CHECK_ARG(part >= 0 && part < (int)p->parts.size(), "part %d out of range", part);
+  if (hs_status rc = plan_compile(p, dtype)) return rc;
+  const CompiledPart& cp = p->comp[dtype][part];
+  const PartDesc& d = cp.desc;
+  header[0] = d.m;
+  header[1] = d.lb;
+  header[2] = d.wb;
+  header[3] = d.rb;
+  header[4] = d.n_stages;
+  header[5] = cp.lds_round_trips;
+  header[6] = (int)cp.ops.size();
+  header[7] = p->n - d.m;
+  for (int i = 0; i < kMaxTile; ++i) header[8 + i] = d.tq[i];
+  if (entries && entries_cap >= d.n_stages) {
+    for (int s = 0; s < d.n_stages; ++s) {
+      const StageDesc& e = cp.stages[s];
+      int32_t* o = entries + 20 * s;
+      for (int i = 0; i < kMaxTile; ++i) o[i] = e.pos[i];
+      o[16] = e.op_begin;
+      o[17] = e.op_end;
+      o[18] = e.transition;
+      o[19] = 0;
+    }
+  }
+  if (ops && ops_cap >= (int)cp.ops.size()) {
+    for (size_t i = 0; i < cp.ops.size(); ++i) {
+      double* o = ops + 11 * i;
+      o[0] = cp.ops[i].kind;
+      o[1] = cp.ops[i].b0;
+      o[2] = cp.ops[i].b1;
+      for (int j = 0; j < 8; ++j) o[3 + j] = cp.ops[i].c[j];
+    }
+  }
+  return HS_OK;
+}
+
+hs_status hs_plan_destroy(hs_plan p) {
+  delete p;
+  return HS_OK;
+}
+
+// ---- simulation --------------------------------------------------------------
+
+static hs_status check_exec(hs_exec exec) {
+  if (exec == HS_EXEC_GATE_PER_PASS || exec == HS_EXEC_PART_LDS || exec == HS_EXEC_AUTO) return HS_OK;
+  if (exec == HS_EXEC_PART_FUSED) return fail(HS_E_UNSUPPORTED, "PART_FUSED is not built yet");
+  return fail(HS_E_ARG, "unknown exec mode %d", (int)exec);
+}
+
+hs_status hs_simulate_part(hs_state s, hs_plan p, int part, hs_exec exec) {
+  CHECK_ARG(s && p, "null argument");
+  CHECK_ARG(p->n == s->n, "plan is for %d qubits, state has %d", p->n, s->n);
+  CHECK_ARG(part >= 0 && part < (int)p->parts.size(), "part %d out of range", part);
+  if (hs_status rc = check_exec(exec)) return rc;
+  if (exec == HS_EXEC_GATE_PER_PASS) {
+    for (int gi : p->parts[part])
+      if (hs_status rc = dev_gate_pass(s, p->gates[gi])) return rc;
+    return HS_OK;
+  }
+  if (hs_status rc = plan_compile(p, s->dtype)) return rc;
+  return dev_run_part(s, p, part);
+}
+
+hs_status hs_simulate(hs_state s, hs_plan p, hs_exec exec) {
+  CHECK_ARG(s && p, "null argument");
+  CHECK_ARG(p->n == s->n, "plan is for %d qubits, state has %d", p->n, s->n);
+  if (hs_status rc = check_exec(exec)) return rc;
+  if (exec == HS_EXEC_GATE_PER_PASS) {
+    for (const Gate& g : p->gates)
+      if (hs_status rc = dev_gate_pass(s, g)) return rc;
+    return HS_OK;
+  }
+  if (hs_status rc = plan_compile(p, s->dtype)) return rc;
+  for (int i = 0; i < (int)p->parts.size(); ++i)
+    if (hs_status rc = dev_run_part(s, p, i)) return rc;
+  return HS_OK;
+}
+
+hs_status hs_simulate_gate_per_pass(hs_state s, hs_circuit c) {
+  CHECK_ARG(s && c, "null argument");
+  CHECK_ARG(c->n == s->n, "circuit is for %d qubits, state has %d", c->n, s->n);
+  for (const Gate& g : c->gates)
+    if (hs_status rc = dev_gate_pass(s, g)) return rc;
+  return HS_OK;
+}
+
+// ---- readout -----------------------------------------------------------------
+
+hs_status hs_read_amplitudes(hs_state s, uint64_t first, uint64_t count, double* out) {
+  CHECK_ARG(s && (out || count == 0), "null argument");
+  const uint64_t N = uint64_t(1) << s->n;
+  CHECK_ARG(first <= N && count <= N - first, "range outside the state");
+  if (!count) return HS_OK;
+  return dev_read(s, first, count, out, false);
+}
+
+hs_status hs_probabilities(hs_state s, uint64_t first, uint64_t count, double* out) {
+  CHECK_ARG(s && (out || count == 0), "null argument");
+  const uint64_t N = uint64_t(1) << s->n;
+  CHECK_ARG(first <= N && count <= N - first, "range outside the state");
+  if (!count) return HS_OK;
+  return dev_read(s, first, count, out, true);
+}
+
+hs_status hs_norm(hs_state s, double* out) {
+  CHECK_ARG(s && out, "null argument");
+  return dev_norm(s, out);
+}
+
+hs_status hs_sync(hs_state s) {
+  CHECK_ARG(s, "null state");
+  return dev_sync(s);
+}
+
+hs_status hs_copy_probe(const void* src, void* dst, size_t bytes, void* hip_stream) {
+  CHECK_ARG(src && dst, "null pointer");
+  CHECK_ARG(bytes % 16 == 0, "bytes must be a multiple of 16");
+  return dev_copy_probe(src, dst, bytes, hip_stream);
+}
+
+}  // extern "C"

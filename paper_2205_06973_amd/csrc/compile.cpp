@@ -1,0 +1,262 @@
+// compile.cpp -- compile a part into the descriptors of the part-pass kernel.
+//
+// Alg. 1 (Sec. III.C) for one part p with qubit set S_p: for every setting
+// of the qubits outside the part, gather the amplitudes addressed by S_p,
+// run the part's gates, scatter back.  The kernel gathers a *tile*:
+//   T_p = S_p plus the lowest qubits not in S_p, m qubits in all.
+// Padding with low qubits is the rule of the multi-level scheme (Sec. IV:
+// a part with fewer qubits than the level's limit takes extra qubits for
+// spatial locality); here it makes each tile a set of contiguous runs of
+// at least 2^contig amplitudes, so global loads and stores coalesce.
+//
+// Inside the tile the part's gates (circuit order, Sec. IV.A) are cut by the
+// natural cutoff (Sec. IV.B.1) with limit rb into stages, each of which
+// runs entirely on register bits; this is the second level of the
+// multi-level partitioning of Sec. IV, mapped to LDS (level 1: the tile) and
+// registers (level 2: the stage).  Each stage's register bits are its
+// qubits, padded with high tile bits; its lane bits are the lowest
+// remaining tile bits (so that lanes touch neighbouring LDS slots and, in
+// the load and store layouts, neighbouring global addresses).
+//
+// Within a stage, runs of one-qubit gates on the same bit with no other
+// gate on that bit in between are multiplied into one 2x2 in FP64 (gates on
+// different bits commute, so the product can be applied where the run ends).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "hisv_internal.h"
+
+namespace hisv {
+
+int max_tile_qubits(const CompileOptions& opt) {
+  return std::min(std::min(kMaxTile, opt.max_m), kLaneBits + opt.max_wb + opt.rb);
+}
+
+namespace {
+
+struct Layout {
+  int8_t pos[kMaxTile];
+};
+
+// Layout with the given register bits (ascending); lanes take the lowest
+// other tile bits, waves the rest.
+Layout make_layout(int m, int lb, int wb, uint32_t regs) {
+  Layout L;
+  std::memset(L.pos, 0, sizeof L.pos);
+  int c = 0;
+  int lane_left = lb;
+  std::vector<int> waves;
+  for (int t = 0; t < m; ++t) {
+    if (regs >> t & 1) continue;
+    if (lane_left) {
+      L.pos[c++] = (int8_t)t;
+      --lane_left;
+    } else {
+      waves.push_back(t);
+    }
+  }
+  for (int t : waves) L.pos[c++] = (int8_t)t;
+  for (int t = 0; t < m; ++t)
+    if (regs >> t & 1) L.pos[c++] = (int8_t)t;
+  (void)wb;
+  return L;
+}
+
+// Pad `regs` to exactly rb tile bits with the highest free tile bits.
+uint32_t pad_regs(uint32_t regs, int m, int rb) {
+  for (int t = m - 1; t >= 0 && __builtin_popcount(regs) < rb; --t) regs |= 1u << t;
+  return regs;
+}
+
+bool lanes_are_low(const Layout& L, int lb) {
+  for (int c = 0; c < lb; ++c)
+    if (L.pos[c] != c) return false;
+  return true;
+}
+
+bool same_layout(const Layout& a, const Layout& b, int m) {
+  return std::memcmp(a.pos, b.pos, (size_t)m) == 0;
+}
+
+bool is_exact(const cd& z, double re, double im) { return z.real() == re && z.imag() == im; }
+
+void matmul2(const cd a[4], const cd b[4], cd out[4]) {  // out = a * b
+  cd r[4];
+  r[0] = a[0] * b[0] + a[1] * b[2];
+  r[1] = a[0] * b[1] + a[1] * b[3];
+  r[2] = a[2] * b[0] + a[3] * b[2];
+  r[3] = a[2] * b[1] + a[3] * b[3];
+  for (int i = 0; i < 4; ++i) out[i] = r[i];
+}
+
+void emit_1q(int b, const cd u[4], std::vector<HostOp>* ops) {
+  HostOp op{};
+  op.b0 = b;
+  op.b1 = -1;
+  const bool diag = is_exact(u[1], 0, 0) && is_exact(u[2], 0, 0);
+  if (diag) {
+    if (is_exact(u[0], 1, 0) && is_exact(u[3], 1, 0)) return;  // identity
+    if (is_exact(u[0], 1, 0)) {
+      op.kind = OP_D1;
+      op.c[0] = u[3].real();
+      op.c[1] = u[3].imag();
+    } else {
+      op.kind = OP_D;
+      op.c[0] = u[0].real(); op.c[1] = u[0].imag();
+      op.c[2] = u[3].real(); op.c[3] = u[3].imag();
+    }
+  } else if (is_exact(u[0], 0, 0) && is_exact(u[3], 0, 0) && is_exact(u[1], 1, 0) &&
+             is_exact(u[2], 1, 0)) {
+    op.kind = OP_X;
+  } else if (u[0].imag() == 0 && u[1].imag() == 0 && u[2].imag() == 0 && u[3].imag() == 0) {
+    op.kind = OP_R;
+    for (int i = 0; i < 4; ++i) op.c[i] = u[i].real();
+  } else {
+    op.kind = OP_U;
+    for (int i = 0; i < 4; ++i) {
+      op.c[2 * i] = u[i].real();
+      op.c[2 * i + 1] = u[i].imag();
+    }
+  }
+  ops->push_back(op);
+}
+
+}  // namespace
+
+hs_status compile_part(int n, const std::vector<Gate>& pg, const CompileOptions& opt,
+                       CompiledPart* out) {
+  if (pg.empty()) return fail(HS_E_ARG, "empty part");
+  uint64_t S = 0;
+  for (const Gate& g : pg) S |= g.mask();
+  const int C = std::min(opt.contig, n);
+  const uint64_t need = S | ((C >= 64) ? ~0ull : ((1ull << C) - 1));
+  int m = std::max(__builtin_popcountll(need), std::min(n, kLaneBits + opt.rb));
+  if (m > max_tile_qubits(opt))
+    return fail(HS_E_UNSUPPORTED, "part needs a %d-qubit tile; the kernel holds at most %d",
+                m, max_tile_qubits(opt));
+  const int rb = std::min(opt.rb, m);
+  const int lb = std::min(kLaneBits, m - rb);
+  const int wb = m - rb - lb;
+  if (wb > opt.max_wb) return fail(HS_E_UNSUPPORTED, "tile needs %d wave bits", wb);
+
+  // tile qubits: S plus the lowest qubits outside S
+  uint64_t T = S;
+  for (int q = 0; q < n && __builtin_popcountll(T) < m; ++q) T |= 1ull << q;
+  int8_t tq[kMaxTile] = {0};
+  int bit_of[64];
+  for (int q = 0, t = 0; q < n; ++q) {
+    bit_of[q] = -1;
+    if (T >> q & 1) {
+      tq[t] = (int8_t)q;
+      bit_of[q] = t++;
+    }
+  }
+
+  // second-level cutoff: stages of at most rb tile bits, circuit order
+  struct Stage {
+    uint32_t bits;
+    int g0, g1;
+  };
+  std::vector<Stage> st;
+  for (int i = 0; i < (int)pg.size(); ++i) {
+    uint32_t gb = 1u << bit_of[pg[i].q0];
+    if (pg[i].q1 >= 0) gb |= 1u << bit_of[pg[i].q1];
+    if (__builtin_popcount(gb) > rb)
+      return fail(HS_E_UNSUPPORTED, "gate wider than the register stage");
+    if (st.empty() || __builtin_popcount(st.back().bits | gb) > rb) st.push_back({0u, i, i});
+    st.back().bits |= gb;
+    st.back().g1 = i + 1;
+  }
+
+  out->desc = PartDesc{};
+  out->desc.m = m;
+  out->desc.lb = lb;
+  out->desc.wb = wb;
+  out->desc.rb = rb;
+  out->desc.tiles = uint64_t(1) << (n - m);
+  std::memcpy(out->desc.tq, tq, sizeof tq);
+  out->rb_kernel = rb;
+  out->stages.clear();
+  out->ops.clear();
+
+  std::vector<Layout> lay;
+  for (const Stage& s : st) lay.push_back(make_layout(m, lb, wb, pad_regs(s.bits, m, rb)));
+  // load and store layouts: lanes on tile bits 0..lb-1 (contiguous global runs)
+  auto io_layout = [&](const Layout& near) {
+    if (lanes_are_low(near, lb)) return near;
+    return make_layout(m, lb, wb, pad_regs(0u, m, rb));
+  };
+  const Layout load = io_layout(lay.front());
+  const Layout store = io_layout(lay.back());
+
+  auto push_entry = [&](const Layout& L, const Layout* prev) {
+    StageDesc e{};
+    std::memcpy(e.pos, L.pos, sizeof e.pos);
+    e.transition = (prev && !same_layout(L, *prev, m)) ? 1 : 0;
+    e.op_begin = e.op_end = (int)out->ops.size();
+    out->stages.push_back(e);
+    return &out->stages.back();
+  };
+  int trips = 0;
+  push_entry(load, nullptr);
+  const Layout* prev = &load;
+  for (size_t s = 0; s < st.size(); ++s) {
+    StageDesc* e = push_entry(lay[s], prev);
+    trips += e->transition;
+    // register index of each tile bit in this layout
+    int reg_of[kMaxTile];
+    for (int t = 0; t < kMaxTile; ++t) reg_of[t] = -1;
+    for (int r = 0; r < rb; ++r) reg_of[lay[s].pos[lb + wb + r]] = r;
+    cd pend[kMaxTile][4];
+    bool has[kMaxTile] = {false};
+    auto flush = [&](int r) {
+      if (has[r]) emit_1q(r, pend[r], &out->ops);
+      has[r] = false;
+    };
+    for (int i = st[s].g0; i < st[s].g1; ++i) {
+      const Gate& g = pg[i];
+      const int r0 = reg_of[bit_of[g.q0]];
+      if (g.arity() == 1) {
+        cd u[4];
+        gate_matrix(g, u);
+        if (has[r0]) {
+          matmul2(u, pend[r0], pend[r0]);
+        } else {
+          for (int j = 0; j < 4; ++j) pend[r0][j] = u[j];
+          has[r0] = true;
+        }
+        continue;
+      }
+      const int r1 = reg_of[bit_of[g.q1]];
+      flush(r0);
+      flush(r1);
+      HostOp op{};
+      op.b0 = r0;
+      op.b1 = r1;
+      switch (g.kind) {
+        case HS_CX: op.kind = OP_CX; break;
+        case HS_CZ: op.kind = OP_CZ; break;
+        case HS_CP:
+          op.kind = OP_CP;
+          op.c[0] = cos(g.p[0]);
+          op.c[1] = sin(g.p[0]);
+          break;
+        case HS_SWAP: op.kind = OP_SWAP; break;
+        default: return fail(HS_E_ARG, "unknown two-qubit kind %d", g.kind);
+      }
+      out->ops.push_back(op);
+    }
+    for (int r = 0; r < rb; ++r) flush(r);
+    out->stages.back().op_end = (int)out->ops.size();
+    prev = &lay[s];
+  }
+  StageDesc* e = push_entry(store, prev);
+  trips += e->transition;
+  out->desc.n_stages = (int)out->stages.size();
+  out->desc.lds_bytes = 0;  // set per dtype at upload
+  out->lds_round_trips = trips;
+  return HS_OK;
+}
+
+}  // namespace hisv

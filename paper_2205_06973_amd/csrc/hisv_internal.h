@@ -1,0 +1,140 @@
+// hisv_internal.h -- host-side types shared by the library's translation units.
+#pragma once
+
+#include <stdint.h>
+
+#include <complex>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/hisv.h"
+#include "layout.h"
+
+namespace hisv {
+
+using cd = std::complex<double>;
+
+// ---- errors ---------------------------------------------------------------
+hs_status fail(hs_status code, const char* fmt, ...);
+void clear_error();
+
+// ---- gates (Sec. II.A) ----------------------------------------------------
+struct Gate {
+  int kind, q0, q1;
+  double p[3];
+  int arity() const { return q1 < 0 ? 1 : 2; }
+  uint64_t mask() const {
+    return (uint64_t(1) << q0) | (q1 >= 0 ? (uint64_t(1) << q1) : 0);
+  }
+};
+
+bool kind_is_1q(int kind);
+bool kind_is_2q(int kind);
+hs_status validate_gate(int n, const hs_gate& g, Gate* out);
+// 2x2 matrix (row-major) of a one-qubit gate, in FP64.
+void gate_matrix(const Gate& g, cd u[4]);
+
+struct Circuit {
+  int n = 0;
+  std::vector<Gate> gates;
+};
+
+// ---- partitioning (Sec. IV) -------------------------------------------------
+struct Dag {
+  int G = 0;
+  std::vector<std::vector<int>> succ, pred;  // wire dependencies, no duplicates
+};
+Dag build_dag(const std::vector<Gate>& gates);
+
+// Contiguous cutoff of `order` (a topological order) into parts of at most k
+// qubits; part_of_gate is indexed by gate id.  Returns the number of parts.
+int cutoff_partition(const std::vector<Gate>& gates, const std::vector<int>& order, int k,
+                     std::vector<int32_t>* part_of_gate);
+int partition_nat(const std::vector<Gate>& gates, int k, std::vector<int32_t>* part);
+int partition_dfs(const std::vector<Gate>& gates, const Dag& dag, int k, uint64_t seed,
+                  int trials, std::vector<int32_t>* part);
+int partition_dagp(const std::vector<Gate>& gates, const Dag& dag, int n, int k,
+                   uint64_t seed, std::vector<int32_t>* part);
+// Exact validity check; returns "" when valid, else the first violation.
+std::string check_partition(const std::vector<Gate>& gates, const Dag& dag,
+                            const std::vector<int32_t>& part, int k);
+
+// ---- part compilation (kernel descriptors) --------------------------------------
+struct HostOp {
+  int kind, b0, b1;
+  double c[8];
+};
+
+struct CompiledPart {
+  PartDesc desc;                    // stage_off relative to this part's stages
+  std::vector<StageDesc> stages;    // load, stages..., store (op ranges relative)
+  std::vector<HostOp> ops;
+  int rb_kernel = 0;
+  int lds_round_trips = 0;
+};
+
+struct CompileOptions {
+  int rb = 4;        // register bits per lane (2^rb amplitudes per lane)
+  int contig = 6;    // tile always holds qubits 0..contig-1 (coalesced runs)
+  int max_wb = 4;    // at most 2^max_wb wavefronts per workgroup
+  int swizzle = 4;   // LDS swizzle width (bits)
+  int max_m = 14;    // widest tile whose 2^m amplitudes fit the LDS
+};
+
+// Compile one part (its gates in circuit order) on an n-qubit state.
+hs_status compile_part(int n, const std::vector<Gate>& part_gates, const CompileOptions& opt,
+                       CompiledPart* out);
+int max_tile_qubits(const CompileOptions& opt);
+
+// ---- plan -------------------------------------------------------------------
+struct DevicePlan;  // uploaded descriptors (kernels.hip)
+void device_plan_free(DevicePlan* d);
+
+struct Plan {
+  int n = 0, k = 0;
+  std::vector<Gate> gates;
+  Dag dag;
+  std::vector<int32_t> part_of_gate;
+  std::vector<std::vector<int>> parts;  // gate ids per part, circuit order
+  std::vector<uint64_t> masks;
+  // per dtype: compiled descriptors + uploaded copy (per device)
+  std::mutex mu;
+  bool compiled[2] = {false, false};
+  std::vector<CompiledPart> comp[2];
+  std::map<int, DevicePlan*> dev[2];
+  ~Plan();
+};
+
+hs_status plan_build(int n, const std::vector<Gate>& gates, int k,
+                     const std::vector<int32_t>& part_of_gate, Plan* p);
+CompileOptions default_options(hs_dtype dtype);
+hs_status plan_compile(Plan* p, hs_dtype dtype);
+
+// ---- state --------------------------------------------------------------------
+struct State {
+  int n = 0;
+  hs_dtype dtype = HS_C64;
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  bool owned = false;
+  int device = 0;
+  void* stream = nullptr;   // hipStream_t
+  void* scratch = nullptr;  // device scratch for readout (lazily allocated)
+  size_t scratch_bytes = 0;
+};
+
+inline size_t amp_bytes(hs_dtype d) { return d == HS_C64 ? 8 : 16; }
+
+// ---- device side (kernels.hip) ------------------------------------------------
+hs_status dev_set_basis(State* s, uint64_t x);
+hs_status dev_gate_pass(State* s, const Gate& g);
+hs_status dev_run_part(State* s, Plan* p, int part);
+hs_status dev_norm(State* s, double* out);
+hs_status dev_read(State* s, uint64_t first, uint64_t count, double* out, bool probs);
+hs_status dev_copy_probe(const void* src, void* dst, size_t bytes, void* stream);
+hs_status dev_sync(State* s);
+
+}  // namespace hisv

@@ -1,0 +1,771 @@
+// kernels.hip -- gfx950 kernels of the partitioned state-vector path.
+//
+//   part_pass_kernel   Alg. 1 (Sec. III.C) for one part, in place: each
+//                      workgroup gathers tiles (one outer setting each) from
+//                      HBM into registers with coalesced loads, runs the
+//                      part's register stages (LDS re-layouts in between) and
+//                      scatters the tile back -- one HBM read and one write
+//                      per amplitude per part.
+//   gate_pass_1q/2q    the non-hierarchical case (Sec. III.A-B): one full
+//                      sweep of the state per gate.
+//   set_basis, norm, probabilities/amplitude readout, copy probe.
+//
+// Amplitudes are interleaved complex (float2 / double2), index bit q =
+// qubit q.  complex64 states compute in FP32, complex128 in FP64; the norm
+// and probabilities are accumulated in FP64 for both.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <map>
+#include <type_traits>
+
+#include "hisv_internal.h"
+
+namespace hisv {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cplx {
+  T x, y;
+};
+
+// ---------------------------------------------------------------------------
+// register operations (one lane's 2^RB amplitudes; bit positions compile-time)
+// ---------------------------------------------------------------------------
+template <int N>
+using IC = std::integral_constant<int, N>;
+
+template <int RB, typename F>
+__device__ __forceinline__ void for_bit(int b, F&& f) {
+  switch (b) {
+    case 0: if constexpr (RB > 0) f(IC<0>{}); break;
+    case 1: if constexpr (RB > 1) f(IC<1>{}); break;
+    case 2: if constexpr (RB > 2) f(IC<2>{}); break;
+    case 3: if constexpr (RB > 3) f(IC<3>{}); break;
+    case 4: if constexpr (RB > 4) f(IC<4>{}); break;
+    case 5: if constexpr (RB > 5) f(IC<5>{}); break;
+    default: break;
+  }
+}
+
+template <int RB, typename F>
+__device__ __forceinline__ void for_pair(int b0, int b1, F&& f) {
+  for_bit<RB>(b0, [&](auto B0) __attribute__((always_inline)) {
+    for_bit<RB>(b1, [&](auto B1) __attribute__((always_inline)) {
+      if constexpr (decltype(B0)::value != decltype(B1)::value) f(B0, B1);
+    });
+  });
+}
+
+// A lane's 2^RB amplitudes live in one vector value (re at 2j, im at 2j+1):
+// every access below is an element of an SSA value with a compile-time
+// index, so the whole sub-state stays in VGPRs.
+template <typename T, int RB>
+using RegV = T __attribute__((ext_vector_type(2 << RB)));
+
+template <typename T, int RB, int B>
+__device__ __forceinline__ void r_u(RegV<T, RB>& a, const T* __restrict__ c) {
+  const T u00r = c[0], u00i = c[1], u01r = c[2], u01i = c[3];
+  const T u10r = c[4], u10i = c[5], u11r = c[6], u11i = c[7];
+#pragma unroll
+  for (int j = 0; j < (1 << RB); ++j) {
+    if (j & (1 << B)) continue;
+    const int k = j | (1 << B);
+    const T px = a[2 * j], py = a[2 * j + 1], qx = a[2 * k], qy = a[2 * k + 1];
+    a[2 * j] = u00r * px - u00i * py + u01r * qx - u01i * qy;
+    a[2 * j + 1] = u00r * py + u00i * px + u01r * qy + u01i * qx;
+    a[2 * k] = u10r * px - u10i * py + u11r * qx - u11i * qy;
+    a[2 * k + 1] = u10r * py + u10i * px + u11r * qy + u11i * qx;
+  }
+}
+
+template <typename T, int RB, int B>
+__device__ __forceinline__ void r_r(RegV<T, RB>& a, const T* __restrict__ c) {
+  const T u00 = c[0], u01 = c[1], u10 = c[2], u11 = c[3];
+#pragma unroll
+  for (int j = 0; j < (1 << RB); ++j) {
+    if (j & (1 << B)) continue;
+    const int k = j | (1 << B);
+    const T px = a[2 * j], py = a[2 * j + 1], qx = a[2 * k], qy = a[2 * k + 1];
+    a[2 * j] = u00 * px + u01 * qx;
+    a[2 * j + 1] = u00 * py + u01 * qy;
+    a[2 * k] = u10 * px + u11 * qx;
+    a[2 * k + 1] = u10 * py + u11 * qy;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void cmul(cplx<T>& v, T cr, T ci) {
+  const cplx<T> p = v;
+  v.x = p.x * cr - p.y * ci;
+  v.y = p.x * ci + p.y * cr;
+}
+
+template <typename T, int RB>
+__device__ __forceinline__ void cmul_at(RegV<T, RB>& a, int j, T cr, T ci) {
+  const T px = a[2 * j], py = a[2 * j + 1];
+  a[2 * j] = px * cr - py * ci;
+  a[2 * j + 1] = px * ci + py * cr;
+}
+
+template <typename T, int RB>
+__device__ __forceinline__ void swap_at(RegV<T, RB>& a, int j, int k) {
+  const T tx = a[2 * j], ty = a[2 * j + 1];
+  a[2 * j] = a[2 * k];
+  a[2 * j + 1] = a[2 * k + 1];
+  a[2 * k] = tx;
+  a[2 * k + 1] = ty;
+}
+
+template <typename T, int RB, int B>
+__device__ __forceinline__ void r_d(RegV<T, RB>& a, const T* __restrict__ c) {
+  const T d0r = c[0], d0i = c[1], d1r = c[2], d1i = c[3];
+#pragma unroll
+  for (int j = 0; j < (1 << RB); ++j) {
+    if (j & (1 << B)) cmul_at<T, RB>(a, j, d1r, d1i);
+    else cmul_at<T, RB>(a, j, d0r, d0i);
+  }
+}
+
+template <typename T, int RB, int B>
+__device__ __forceinline__ void r_d1(RegV<T, RB>& a, const T* __restrict__ c) {
+  const T d1r = c[0], d1i = c[1];
+#pragma unroll
+  for (int j = 0; j < (1 << RB); ++j)
+    if (j & (1 << B)) cmul_at<T, RB>(a, j, d1r, d1i);
+}
+
+template <typename T, int RB, int B>
+__device__ __forceinline__ void r_x(RegV<T, RB>& a) {
+#pragma unroll
+  for (int j = 0; j < (1 << RB); ++j)
+    if (!(j & (1 << B))) swap_at<T, RB>(a, j, j | (1 << B));
+}
+
+template <typename T, int RB, int C, int G>
+__device__ __forceinline__ void r_cx(RegV<T, RB>& a) {
+#pragma unroll
+  for (int j = 0; j < (1 << RB); ++j)
+    if ((j & (1 << C)) && !(j & (1 << G))) swap_at<T, RB>(a, j, j | (1 << G));
+}
+
+template <typename T, int RB, int B0, int B1>
+__device__ __forceinline__ void r_swap(RegV<T, RB>& a) {
+#pragma unroll
+  for (int j = 0; j < (1 << RB); ++j)
+    if ((j & (1 << B0)) && !(j & (1 << B1))) swap_at<T, RB>(a, j, j ^ (1 << B0) ^ (1 << B1));
+}
+
+template <typename T, int RB, int B0, int B1>
+__device__ __forceinline__ void r_cz(RegV<T, RB>& a) {
+#pragma unroll
+  for (int j = 0; j < (1 << RB); ++j)
+    if ((j & (1 << B0)) && (j & (1 << B1))) {
+      a[2 * j] = -a[2 * j];
+      a[2 * j + 1] = -a[2 * j + 1];
+    }
+}
+
+template <typename T, int RB, int B0, int B1>
+__device__ __forceinline__ void r_cp(RegV<T, RB>& a, const T* __restrict__ c) {
+  const T cr = c[0], ci = c[1];
+#pragma unroll
+  for (int j = 0; j < (1 << RB); ++j)
+    if ((j & (1 << B0)) && (j & (1 << B1))) cmul_at<T, RB>(a, j, cr, ci);
+}
+
+template <typename T, int RB>
+__device__ __forceinline__ void apply_op(RegV<T, RB>& a, const OpDesc<T>* __restrict__ op) {
+  const int kind = __builtin_amdgcn_readfirstlane(op->kind);
+  const int b0 = __builtin_amdgcn_readfirstlane(op->b0);
+  const int b1 = __builtin_amdgcn_readfirstlane(op->b1);
+  const T* c = op->c;
+  switch (kind) {
+    case OP_U: for_bit<RB>(b0, [&](auto B) __attribute__((always_inline)) { r_u<T, RB, decltype(B)::value>(a, c); }); break;
+    case OP_R: for_bit<RB>(b0, [&](auto B) __attribute__((always_inline)) { r_r<T, RB, decltype(B)::value>(a, c); }); break;
+    case OP_D: for_bit<RB>(b0, [&](auto B) __attribute__((always_inline)) { r_d<T, RB, decltype(B)::value>(a, c); }); break;
+    case OP_D1: for_bit<RB>(b0, [&](auto B) __attribute__((always_inline)) { r_d1<T, RB, decltype(B)::value>(a, c); }); break;
+    case OP_X: for_bit<RB>(b0, [&](auto B) __attribute__((always_inline)) { r_x<T, RB, decltype(B)::value>(a); }); break;
+    case OP_CX:
+      for_pair<RB>(b0, b1, [&](auto B0, auto B1) __attribute__((always_inline)) {
+        r_cx<T, RB, decltype(B0)::value, decltype(B1)::value>(a);
+      });
+      break;
+    case OP_CZ:
+      for_pair<RB>(b0, b1, [&](auto B0, auto B1) __attribute__((always_inline)) {
+        r_cz<T, RB, decltype(B0)::value, decltype(B1)::value>(a);
+      });
+      break;
+    case OP_CP:
+      for_pair<RB>(b0, b1, [&](auto B0, auto B1) __attribute__((always_inline)) {
+        r_cp<T, RB, decltype(B0)::value, decltype(B1)::value>(a, c);
+      });
+      break;
+    case OP_SWAP:
+      for_pair<RB>(b0, b1, [&](auto B0, auto B1) __attribute__((always_inline)) {
+        r_swap<T, RB, decltype(B0)::value, decltype(B1)::value>(a);
+      });
+      break;
+    default: break;
+  }
+}
+
+// LDS swizzle width: the bank window holds 2^sw amplitudes (128 B).
+template <typename T>
+constexpr int lds_sw() { return sizeof(T) == 4 ? 4 : 3; }
+
+// Global index bits contributed by coordinate bits [c0, c1) of a layout.
+__device__ __forceinline__ uint64_t coord_global(const StageDesc& e, const int8_t* tq, int c0, int c1,
+                                                 uint32_t v) {
+  uint64_t g = 0;
+  for (int c = c0; c < c1; ++c) g |= uint64_t((v >> (c - c0)) & 1u) << tq[e.pos[c]];
+  return g;
+}
+
+__device__ __forceinline__ uint32_t thread_tile(const StageDesc& e, int nthr_bits, uint32_t thr) {
+  uint32_t t = 0;
+  for (int c = 0; c < nthr_bits; ++c) t |= ((thr >> c) & 1u) << e.pos[c];
+  return t;
+}
+
+// Move the tile between HBM and registers in layout `e`.  The address of
+// register j is (uniform part: tile base + wave bits + register bits) plus
+// the lane's byte offset, so every access is an SGPR base + one 32-bit VGPR
+// offset.  Lane bits of the load/store layouts are the tile's lowest
+// qubits, so the lane offset is small.
+template <typename T, int RB, bool STORE>
+__device__ __forceinline__ void tile_io(cplx<T>* __restrict__ st, RegV<T, RB>& a, const StageDesc& e,
+                                        const int8_t* tq, int lb, int wb, uint64_t tbase,
+                                        uint32_t lane, uint32_t wave, bool active) {
+  const uint64_t uni = tbase + coord_global(e, tq, lb, lb + wb, wave);
+  const uint32_t lane_bytes = (uint32_t)coord_global(e, tq, 0, lb, lane) * (uint32_t)sizeof(cplx<T>);
+  uint64_t ro[RB > 0 ? RB : 1];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) ro[r] = uint64_t(1) << tq[e.pos[lb + wb + r]];
+  if (!active) return;
+#pragma unroll
+  for (int j = 0; j < (1 << RB); ++j) {
+    uint64_t o = uni;
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+      if (j >> r & 1) o += ro[r];
+    char* pj = reinterpret_cast<char*>(st + o);
+    cplx<T>* q = reinterpret_cast<cplx<T>*>(pj + lane_bytes);
+    if constexpr (STORE) {
+      cplx<T> v;
+      v.x = a[2 * j];
+      v.y = a[2 * j + 1];
+      *q = v;
+    } else {
+      const cplx<T> v = *q;
+      a[2 * j] = v.x;
+      a[2 * j + 1] = v.y;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// part-pass kernel (Alg. 1 for one part)
+// ---------------------------------------------------------------------------
+template <typename T, int RB>
+__global__ void __launch_bounds__(1024)
+part_pass_kernel(cplx<T>* __restrict__ st, const PartDesc* __restrict__ pd,
+                 const StageDesc* __restrict__ sd, const OpDesc<T>* __restrict__ ops) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+  constexpr int NR = 1 << RB;
+  constexpr int SW = lds_sw<T>();
+  const int m = pd->m, lb = pd->lb, wb = pd->wb;
+  const int ne = pd->n_stages;
+  const uint64_t tiles = pd->tiles;
+  const int tb_bits = lb + wb;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t thr = lane | (wave << lb);
+  const bool active = lane < (1 << lb);
+
+  RegV<T, RB> a;
+  for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const uint64_t tbase = tile_base(tile, pd->tq, m);
+    // ---- gather (entry 0 is the load layout: lanes on contiguous qubits)
+    tile_io<T, RB, false>(st, a, sd[0], pd->tq, lb, wb, tbase, lane, wave, active);
+    // ---- execute: stages, re-laid out through LDS where the layout changes
+    for (int s = 1; s < ne; ++s) {
+      const StageDesc& e = sd[s];
+      if (e.transition) {
+        const StageDesc& f = sd[s - 1];
+        uint32_t rs[RB > 0 ? RB : 1];
+        const uint32_t wbase = lds_slot(thread_tile(f, tb_bits, thr), SW);
+#pragma unroll
+        for (int r = 0; r < RB; ++r) rs[r] = lds_slot(1u << f.pos[tb_bits + r], SW);
+        __syncthreads();
+        if (active) {
+#pragma unroll
+          for (int j = 0; j < NR; ++j) {
+            uint32_t o = wbase;
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+              if (j >> r & 1) o ^= rs[r];
+            cplx<T> v;
+            v.x = a[2 * j];
+            v.y = a[2 * j + 1];
+            lds[o] = v;
+          }
+        }
+        __syncthreads();
+        const uint32_t rbase = lds_slot(thread_tile(e, tb_bits, thr), SW);
+#pragma unroll
+        for (int r = 0; r < RB; ++r) rs[r] = lds_slot(1u << e.pos[tb_bits + r], SW);
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+          uint32_t o = rbase;
+#pragma unroll
+          for (int r = 0; r < RB; ++r)
+            if (j >> r & 1) o ^= rs[r];
+          const cplx<T> v = lds[o];
+          a[2 * j] = v.x;
+          a[2 * j + 1] = v.y;
+        }
+      }
+      const int o1 = e.op_end;
+      for (int o = e.op_begin; o < o1; ++o) apply_op<T, RB>(a, ops + o);
+    }
+    // ---- scatter (last entry is the store layout)
+    tile_io<T, RB, true>(st, a, sd[ne - 1], pd->tq, lb, wb, tbase, lane, wave, active);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// gate-per-pass baseline: one sweep of the whole state per gate
+// ---------------------------------------------------------------------------
+template <typename T>
+struct M2 {
+  T c[8];
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+gate_pass_1q(cplx<T>* __restrict__ st, int q, uint64_t npairs, M2<T> u) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t lowmask = (uint64_t(1) << q) - 1;
+  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npairs; p += stride) {
+    const uint64_t i0 = ((p >> q) << (q + 1)) | (p & lowmask);
+    const uint64_t i1 = i0 | (uint64_t(1) << q);
+    const cplx<T> x = st[i0], y = st[i1];
+    cplx<T> r0, r1;
+    r0.x = u.c[0] * x.x - u.c[1] * x.y + u.c[2] * y.x - u.c[3] * y.y;
+    r0.y = u.c[0] * x.y + u.c[1] * x.x + u.c[2] * y.y + u.c[3] * y.x;
+    r1.x = u.c[4] * x.x - u.c[5] * x.y + u.c[6] * y.x - u.c[7] * y.y;
+    r1.y = u.c[4] * x.y + u.c[5] * x.x + u.c[6] * y.y + u.c[7] * y.x;
+    st[i0] = r0;
+    st[i1] = r1;
+  }
+}
+
+// kind: 0 CX(q0 control, q1 target), 1 CZ, 2 CP(c0, c1), 3 SWAP
+template <typename T>
+__global__ void __launch_bounds__(256)
+gate_pass_2q(cplx<T>* __restrict__ st, int q0, int q1, int kind, uint64_t nquads, T cr, T ci) {
+  const int lo = min(q0, q1), hi = max(q0, q1);
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t m0 = uint64_t(1) << q0, m1 = uint64_t(1) << q1;
+  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nquads; p += stride) {
+    uint64_t i = ((p >> lo) << (lo + 1)) | (p & ((uint64_t(1) << lo) - 1));
+    i = ((i >> hi) << (hi + 1)) | (i & ((uint64_t(1) << hi) - 1));
+    // a[b] with bit 0 of b = qubit q0, bit 1 = qubit q1
+    cplx<T> a0 = st[i], a1 = st[i | m0], a2 = st[i | m1], a3 = st[i | m0 | m1];
+    if (kind == 0) {
+      const cplx<T> t = a1; a1 = a3; a3 = t;
+    } else if (kind == 1) {
+      a3.x = -a3.x; a3.y = -a3.y;
+    } else if (kind == 2) {
+      cmul(a3, cr, ci);
+    } else {
+      const cplx<T> t = a1; a1 = a2; a2 = t;
+    }
+    st[i] = a0; st[i | m0] = a1; st[i | m1] = a2; st[i | m0 | m1] = a3;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// init, readout, probe
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) set_basis_kernel(cplx<T>* __restrict__ st, uint64_t N, uint64_t x) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
+    cplx<T> v;
+    v.x = (i == x) ? T(1) : T(0);
+    v.y = T(0);
+    st[i] = v;
+  }
+}
+
+constexpr int kNormBlocks = 1024;
+constexpr int kNormThreads = 256;
+
+// Fixed-shape two-level FP64 reduction: thread t of block b sums |a_i|^2 for
+// i = b*256 + t + k*(1024*256), k = 0, 1, ...; each block reduces its 256
+// partial sums by a fixed binary tree; one block then reduces the 1024
+// block sums by the same tree.  The order never depends on the device.
+template <typename T>
+__global__ void __launch_bounds__(kNormThreads)
+norm_partial(const cplx<T>* __restrict__ st, uint64_t N, double* __restrict__ part) {
+  __shared__ double sh[kNormThreads];
+  double acc = 0.0;
+  const uint64_t stride = (uint64_t)kNormBlocks * kNormThreads;
+  for (uint64_t i = (uint64_t)blockIdx.x * kNormThreads + threadIdx.x; i < N; i += stride) {
+    const cplx<T> v = st[i];
+    acc += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kNormThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(kNormThreads) norm_final(const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double sh[kNormThreads];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < kNormBlocks; i += kNormThreads) acc += part[i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kNormThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+// probs = 0: widen amplitudes to complex128; probs = 1: |a|^2 in FP64.
+template <typename T>
+__global__ void __launch_bounds__(256)
+readout_kernel(const cplx<T>* __restrict__ st, uint64_t first, uint64_t count, int probs,
+               double* __restrict__ out) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+    const cplx<T> v = st[first + i];
+    const double re = (double)v.x, im = (double)v.y;
+    if (probs) {
+      out[i] = re * re + im * im;
+    } else {
+      out[2 * i] = re;
+      out[2 * i + 1] = im;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256)
+copy_probe_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst, uint64_t n16) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+    dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess) return fail(HS_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+struct DevInfo {
+  int cus = 0;
+};
+
+static std::mutex g_dev_mu;
+static std::map<int, DevInfo> g_dev;
+
+static hs_status device_info(int dev, DevInfo* out) {
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  auto it = g_dev.find(dev);
+  if (it != g_dev.end()) {
+    *out = it->second;
+    return HS_OK;
+  }
+  DevInfo d;
+  HIP_TRY(hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, dev));
+  g_dev[dev] = d;
+  *out = d;
+  return HS_OK;
+}
+
+static inline hipStream_t stream_of(State* s) { return (hipStream_t)s->stream; }
+
+// streaming grid: enough blocks of 256 to fill the device a few times over
+static hs_status stream_grid(int dev, uint64_t work, unsigned* grid) {
+  DevInfo d;
+  hs_status rc = device_info(dev, &d);
+  if (rc) return rc;
+  const uint64_t want = (work + 255) / 256;
+  *grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)d.cus * 16));
+  return HS_OK;
+}
+
+hs_status dev_set_basis(State* s, uint64_t x) {
+  HIP_TRY(hipSetDevice(s->device));
+  const uint64_t N = uint64_t(1) << s->n;
+  unsigned grid;
+  if (hs_status rc = stream_grid(s->device, N, &grid)) return rc;
+  if (s->dtype == HS_C64)
+    hipLaunchKernelGGL(set_basis_kernel<float>, dim3(grid), dim3(256), 0, stream_of(s),
+                       (cplx<float>*)s->ptr, N, x);
+  else
+    hipLaunchKernelGGL(set_basis_kernel<double>, dim3(grid), dim3(256), 0, stream_of(s),
+                       (cplx<double>*)s->ptr, N, x);
+  HIP_TRY(hipGetLastError());
+  return HS_OK;
+}
+
+template <typename T>
+static hs_status gate_pass_t(State* s, const Gate& g) {
+  const uint64_t N = uint64_t(1) << s->n;
+  unsigned grid;
+  if (g.arity() == 1) {
+    if (hs_status rc = stream_grid(s->device, N / 2, &grid)) return rc;
+    cd u[4];
+    gate_matrix(g, u);
+    M2<T> m;
+    for (int i = 0; i < 4; ++i) {
+      m.c[2 * i] = (T)u[i].real();
+      m.c[2 * i + 1] = (T)u[i].imag();
+    }
+    hipLaunchKernelGGL(gate_pass_1q<T>, dim3(grid), dim3(256), 0, stream_of(s),
+                       (cplx<T>*)s->ptr, g.q0, N / 2, m);
+  } else {
+    if (s->n < 2) return fail(HS_E_ARG, "two-qubit gate on a 1-qubit state");
+    if (hs_status rc = stream_grid(s->device, N / 4, &grid)) return rc;
+    int kind = 0;
+    T cr = 0, ci = 0;
+    switch (g.kind) {
+      case HS_CX: kind = 0; break;
+      case HS_CZ: kind = 1; break;
+      case HS_CP: kind = 2; cr = (T)cos(g.p[0]); ci = (T)sin(g.p[0]); break;
+      case HS_SWAP: kind = 3; break;
+      default: return fail(HS_E_ARG, "unknown two-qubit kind %d", g.kind);
+    }
+    hipLaunchKernelGGL(gate_pass_2q<T>, dim3(grid), dim3(256), 0, stream_of(s),
+                       (cplx<T>*)s->ptr, g.q0, g.q1, kind, N / 4, cr, ci);
+  }
+  HIP_TRY(hipGetLastError());
+  return HS_OK;
+}
+
+hs_status dev_gate_pass(State* s, const Gate& g) {
+  HIP_TRY(hipSetDevice(s->device));
+  return s->dtype == HS_C64 ? gate_pass_t<float>(s, g) : gate_pass_t<double>(s, g);
+}
+
+// ---- uploaded plan ----------------------------------------------------------
+struct DevicePlan {
+  int device = 0;
+  PartDesc* parts = nullptr;
+  StageDesc* stages = nullptr;
+  void* ops = nullptr;
+  std::vector<PartDesc> h_parts;     // host copy (absolute offsets)
+  std::vector<int> rb;               // register bits of the kernel per part
+  std::vector<unsigned> grid;        // persistent grid per part
+};
+
+void device_plan_free(DevicePlan* d) {
+  if (!d) return;
+  hipSetDevice(d->device);
+  if (d->parts) hipFree(d->parts);
+  if (d->stages) hipFree(d->stages);
+  if (d->ops) hipFree(d->ops);
+  delete d;
+}
+
+template <typename T, int RB>
+static hs_status occupancy_grid(int dev, int block, size_t lds, uint64_t tiles, unsigned* grid) {
+  DevInfo d;
+  if (hs_status rc = device_info(dev, &d)) return rc;
+  if (lds > 65536)
+    HIP_TRY(hipFuncSetAttribute((const void*)part_pass_kernel<T, RB>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  int per_cu = 0;
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, part_pass_kernel<T, RB>, block, lds));
+  if (per_cu < 1) return fail(HS_E_UNSUPPORTED, "part kernel cannot be resident (block %d, lds %zu)",
+                              block, lds);
+  const uint64_t cap = (uint64_t)per_cu * d.cus;
+  *grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(tiles, cap));
+  return HS_OK;
+}
+
+template <typename T>
+static hs_status occupancy_grid_rb(int rb, int dev, int block, size_t lds, uint64_t tiles,
+                                   unsigned* grid) {
+  switch (rb) {
+    case 1: return occupancy_grid<T, 1>(dev, block, lds, tiles, grid);
+    case 2: return occupancy_grid<T, 2>(dev, block, lds, tiles, grid);
+    case 3: return occupancy_grid<T, 3>(dev, block, lds, tiles, grid);
+    case 4: return occupancy_grid<T, 4>(dev, block, lds, tiles, grid);
+    case 5: return occupancy_grid<T, 5>(dev, block, lds, tiles, grid);
+    default: return fail(HS_E_UNSUPPORTED, "no kernel with %d register bits", rb);
+  }
+}
+
+template <typename T>
+static hs_status upload_plan(Plan* p, int dtype, int dev, DevicePlan** out) {
+  std::vector<PartDesc> parts;
+  std::vector<StageDesc> stages;
+  std::vector<OpDesc<T>> ops;
+  auto dp = std::make_unique<DevicePlan>();
+  dp->device = dev;
+  for (const CompiledPart& cp : p->comp[dtype]) {
+    PartDesc d = cp.desc;
+    d.stage_off = (int)stages.size();
+    d.lds_bytes = cp.lds_round_trips ? (int)((size_t(1) << d.m) * sizeof(cplx<T>)) : 0;
+    const int op0 = (int)ops.size();
+    for (StageDesc e : cp.stages) {
+      e.op_begin += op0;
+      e.op_end += op0;
+      stages.push_back(e);
+    }
+    for (const HostOp& h : cp.ops) {
+      OpDesc<T> o{};
+      o.kind = h.kind;
+      o.b0 = h.b0;
+      o.b1 = h.b1;
+      for (int i = 0; i < 8; ++i) o.c[i] = (T)h.c[i];
+      ops.push_back(o);
+    }
+    parts.push_back(d);
+    dp->rb.push_back(cp.rb_kernel);
+    unsigned g = 1;
+    const int block = 64 << d.wb;
+    if (hs_status rc = occupancy_grid_rb<T>(cp.rb_kernel, dev, block, (size_t)d.lds_bytes, d.tiles, &g))
+      return rc;
+    dp->grid.push_back(g);
+  }
+  if (ops.empty()) ops.push_back(OpDesc<T>{});
+  HIP_TRY(hipMalloc(&dp->parts, parts.size() * sizeof(PartDesc)));
+  HIP_TRY(hipMalloc(&dp->stages, stages.size() * sizeof(StageDesc)));
+  HIP_TRY(hipMalloc(&dp->ops, ops.size() * sizeof(OpDesc<T>)));
+  HIP_TRY(hipMemcpy(dp->parts, parts.data(), parts.size() * sizeof(PartDesc), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(dp->stages, stages.data(), stages.size() * sizeof(StageDesc), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(dp->ops, ops.data(), ops.size() * sizeof(OpDesc<T>), hipMemcpyHostToDevice));
+  dp->h_parts = parts;
+  *out = dp.release();
+  return HS_OK;
+}
+
+template <typename T>
+static hs_status launch_part(State* s, DevicePlan* dp, int part) {
+  const PartDesc& d = dp->h_parts[part];
+  const int block = 64 << d.wb;
+  const unsigned grid = dp->grid[part];
+  const size_t lds = (size_t)d.lds_bytes;
+  cplx<T>* st = (cplx<T>*)s->ptr;
+  const PartDesc* pd = dp->parts + part;
+  const StageDesc* sd = dp->stages + d.stage_off;
+  const OpDesc<T>* ops = (const OpDesc<T>*)dp->ops;
+  hipStream_t str = stream_of(s);
+  switch (dp->rb[part]) {
+    case 1: hipLaunchKernelGGL((part_pass_kernel<T, 1>), dim3(grid), dim3(block), lds, str, st, pd, sd, ops); break;
+    case 2: hipLaunchKernelGGL((part_pass_kernel<T, 2>), dim3(grid), dim3(block), lds, str, st, pd, sd, ops); break;
+    case 3: hipLaunchKernelGGL((part_pass_kernel<T, 3>), dim3(grid), dim3(block), lds, str, st, pd, sd, ops); break;
+    case 4: hipLaunchKernelGGL((part_pass_kernel<T, 4>), dim3(grid), dim3(block), lds, str, st, pd, sd, ops); break;
+    case 5: hipLaunchKernelGGL((part_pass_kernel<T, 5>), dim3(grid), dim3(block), lds, str, st, pd, sd, ops); break;
+    default: return fail(HS_E_UNSUPPORTED, "no kernel with %d register bits", dp->rb[part]);
+  }
+  HIP_TRY(hipGetLastError());
+  return HS_OK;
+}
+
+hs_status dev_run_part(State* s, Plan* p, int part) {
+  HIP_TRY(hipSetDevice(s->device));
+  const int dt = (int)s->dtype;
+  DevicePlan* dp = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(p->mu);
+    auto it = p->dev[dt].find(s->device);
+    if (it == p->dev[dt].end()) {
+      hs_status rc = dt == HS_C64 ? upload_plan<float>(p, dt, s->device, &dp)
+                                  : upload_plan<double>(p, dt, s->device, &dp);
+      if (rc) return rc;
+      p->dev[dt][s->device] = dp;
+    } else {
+      dp = it->second;
+    }
+  }
+  return dt == HS_C64 ? launch_part<float>(s, dp, part) : launch_part<double>(s, dp, part);
+}
+
+// ---- readout ----------------------------------------------------------------
+static hs_status ensure_scratch(State* s, size_t bytes) {
+  if (s->scratch_bytes >= bytes) return HS_OK;
+  if (s->scratch) HIP_TRY(hipFree(s->scratch));
+  s->scratch = nullptr;
+  s->scratch_bytes = 0;
+  HIP_TRY(hipMalloc(&s->scratch, bytes));
+  s->scratch_bytes = bytes;
+  return HS_OK;
+}
+
+hs_status dev_norm(State* s, double* out) {
+  HIP_TRY(hipSetDevice(s->device));
+  if (hs_status rc = ensure_scratch(s, (kNormBlocks + 8) * sizeof(double))) return rc;
+  double* part = (double*)s->scratch;
+  double* res = part + kNormBlocks;
+  const uint64_t N = uint64_t(1) << s->n;
+  if (s->dtype == HS_C64)
+    hipLaunchKernelGGL(norm_partial<float>, dim3(kNormBlocks), dim3(kNormThreads), 0, stream_of(s),
+                       (const cplx<float>*)s->ptr, N, part);
+  else
+    hipLaunchKernelGGL(norm_partial<double>, dim3(kNormBlocks), dim3(kNormThreads), 0, stream_of(s),
+                       (const cplx<double>*)s->ptr, N, part);
+  hipLaunchKernelGGL(norm_final, dim3(1), dim3(kNormThreads), 0, stream_of(s), part, res);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(out, res, sizeof(double), hipMemcpyDeviceToHost, stream_of(s)));
+  HIP_TRY(hipStreamSynchronize(stream_of(s)));
+  return HS_OK;
+}
+
+hs_status dev_read(State* s, uint64_t first, uint64_t count, double* out, bool probs) {
+  HIP_TRY(hipSetDevice(s->device));
+  const uint64_t chunk = uint64_t(1) << 22;
+  if (hs_status rc = ensure_scratch(s, std::max<size_t>(chunk * 16, (kNormBlocks + 8) * 8))) return rc;
+  const int per = probs ? 1 : 2;
+  for (uint64_t done = 0; done < count;) {
+    const uint64_t c = std::min(chunk, count - done);
+    unsigned grid;
+    if (hs_status rc = stream_grid(s->device, c, &grid)) return rc;
+    if (s->dtype == HS_C64)
+      hipLaunchKernelGGL(readout_kernel<float>, dim3(grid), dim3(256), 0, stream_of(s),
+                         (const cplx<float>*)s->ptr, first + done, c, probs ? 1 : 0, (double*)s->scratch);
+    else
+      hipLaunchKernelGGL(readout_kernel<double>, dim3(grid), dim3(256), 0, stream_of(s),
+                         (const cplx<double>*)s->ptr, first + done, c, probs ? 1 : 0, (double*)s->scratch);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(out + done * per, s->scratch, c * per * sizeof(double),
+                           hipMemcpyDeviceToHost, stream_of(s)));
+    HIP_TRY(hipStreamSynchronize(stream_of(s)));
+    done += c;
+  }
+  return HS_OK;
+}
+
+hs_status dev_copy_probe(const void* src, void* dst, size_t bytes, void* stream) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  unsigned grid;
+  const uint64_t n16 = bytes / 16;
+  if (hs_status rc = stream_grid(dev, n16, &grid)) return rc;
+  hipLaunchKernelGGL(copy_probe_kernel, dim3(grid), dim3(256), 0, (hipStream_t)stream,
+                     (const uint4*)src, (uint4*)dst, n16);
+  HIP_TRY(hipGetLastError());
+  return HS_OK;
+}
+
+hs_status dev_sync(State* s) {
+  HIP_TRY(hipSetDevice(s->device));
+  HIP_TRY(hipStreamSynchronize(stream_of(s)));
+  return HS_OK;
+}
+
+}  // namespace hisv

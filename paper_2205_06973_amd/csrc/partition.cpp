@@ -1,0 +1,157 @@
+// partition.cpp -- gate DAG and topological-order cutoff partitioners.
+//
+// Sec. IV.A: vertices are gates; an edge runs from a gate to the next gate
+// on each of its qubits (the per-qubit entry and exit vertices carry no
+// computation and stay implicit).  A part's working set is the number of
+// distinct qubits of its gates.  Sec. IV.B.1 (Nat) cuts the circuit order
+// into consecutive segments, closing a segment just before the gate that
+// would take its working set above k; Sec. IV.B.2 (DFS) applies the same
+// cutoff to several random depth-first topological orders and keeps the
+// one with the fewest parts.  Consecutive segments of any topological order
+// form an acyclic part-graph, and numbering them in order numbers the
+// part-graph topologically.
+#include <algorithm>
+
+#include "hisv_internal.h"
+
+namespace hisv {
+
+Dag build_dag(const std::vector<Gate>& gates) {
+  Dag d;
+  d.G = (int)gates.size();
+  d.succ.assign(d.G, {});
+  d.pred.assign(d.G, {});
+  std::vector<int> last(64, -1);
+  for (int j = 0; j < d.G; ++j) {
+    const Gate& g = gates[j];
+    const int qs[2] = {g.q0, g.q1};
+    for (int t = 0; t < g.arity(); ++t) {
+      const int i = last[qs[t]];
+      if (i >= 0 && std::find(d.succ[i].begin(), d.succ[i].end(), j) == d.succ[i].end()) {
+        d.succ[i].push_back(j);
+        d.pred[j].push_back(i);
+      }
+      last[qs[t]] = j;
+    }
+  }
+  return d;
+}
+
+int cutoff_partition(const std::vector<Gate>& gates, const std::vector<int>& order, int k,
+                     std::vector<int32_t>* part) {
+  part->assign(gates.size(), -1);
+  uint64_t cur = 0;
+  int pid = -1;
+  for (int gi : order) {
+    const uint64_t m = gates[gi].mask();
+    if (pid < 0 || __builtin_popcountll(cur | m) > k) {
+      ++pid;
+      cur = 0;
+    }
+    cur |= m;
+    (*part)[gi] = pid;
+  }
+  return pid + 1;
+}
+
+int partition_nat(const std::vector<Gate>& gates, int k, std::vector<int32_t>* part) {
+  std::vector<int> order(gates.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  return cutoff_partition(gates, order, k, part);
+}
+
+namespace {
+// splitmix64: a small seeded generator for the random DFS orders.
+struct Rng {
+  uint64_t s;
+  explicit Rng(uint64_t seed) : s(seed) {}
+  uint64_t next() {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+  int below(int n) { return (int)(next() % (uint64_t)n); }
+  template <typename V>
+  void shuffle(V& v) {
+    for (int i = (int)v.size() - 1; i > 0; --i) std::swap(v[i], v[below(i + 1)]);
+  }
+};
+
+// A random depth-first topological order: a ready vertex is emitted, its
+// newly ready successors are pushed in random order on a stack, and the
+// next vertex comes from the top of the stack, so the order follows chains
+// of dependent gates before moving on.
+void random_dfs_order(const Dag& dag, Rng& rng, std::vector<int>* order) {
+  order->clear();
+  std::vector<int> indeg(dag.G);
+  std::vector<int> stack;
+  for (int v = 0; v < dag.G; ++v) {
+    indeg[v] = (int)dag.pred[v].size();
+    if (!indeg[v]) stack.push_back(v);
+  }
+  rng.shuffle(stack);
+  std::vector<int> ready;
+  while (!stack.empty()) {
+    const int v = stack.back();
+    stack.pop_back();
+    order->push_back(v);
+    ready.clear();
+    for (int s : dag.succ[v])
+      if (--indeg[s] == 0) ready.push_back(s);
+    rng.shuffle(ready);
+    for (int s : ready) stack.push_back(s);
+  }
+}
+}  // namespace
+
+int partition_dfs(const std::vector<Gate>& gates, const Dag& dag, int k, uint64_t seed,
+                  int trials, std::vector<int32_t>* part) {
+  int best = partition_nat(gates, k, part);
+  std::vector<int> order;
+  std::vector<int32_t> cand;
+  for (int t = 1; t < trials; ++t) {
+    Rng rng(seed * 0x100000001B3ull + (uint64_t)t);
+    random_dfs_order(dag, rng, &order);
+    const int np = cutoff_partition(gates, order, k, &cand);
+    if (np < best) {
+      best = np;
+      part->swap(cand);
+    }
+  }
+  return best;
+}
+
+std::string check_partition(const std::vector<Gate>& gates, const Dag& dag,
+                            const std::vector<int32_t>& part, int k) {
+  const int G = (int)gates.size();
+  if ((int)part.size() != G) return "assignment length differs from the gate count";
+  if (G == 0) return "";
+  int P = 0;
+  for (int i = 0; i < G; ++i) {
+    if (part[i] < 0) return "negative part id";
+    P = std::max(P, part[i] + 1);
+  }
+  if (P > G) return "more parts than gates";
+  std::vector<uint64_t> mask(P, 0);
+  std::vector<int> cnt(P, 0);
+  for (int i = 0; i < G; ++i) {
+    mask[part[i]] |= gates[i].mask();
+    cnt[part[i]]++;
+  }
+  for (int p = 0; p < P; ++p) {
+    if (!cnt[p]) return "part " + std::to_string(p) + " is empty";
+    if (__builtin_popcountll(mask[p]) > k)
+      return "part " + std::to_string(p) + " uses more than k qubits";
+  }
+  // Every cross-part edge must go from a lower to a higher id: then the ids
+  // are a topological order of the part-graph, which is therefore acyclic.
+  for (int i = 0; i < G; ++i)
+    for (int j : dag.succ[i])
+      if (part[i] > part[j])
+        return "edge from part " + std::to_string(part[i]) + " back to part " +
+               std::to_string(part[j]);
+  return "";
+}
+
+}  // namespace hisv

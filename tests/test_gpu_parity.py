@@ -1,0 +1,163 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle.
+
+Bars (max |delta amplitude| against the FP64 oracle, for circuits of at
+most 10^4 gates): 1e-12 for complex128 states, 2e-5 for complex64 states,
+plus an L2 bar of 1e-4 (complex64) / 1e-11 (complex128) on the whole
+difference vector, because the max bar alone is loose once amplitudes are
+themselves ~2^(-n/2).
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import statevector as sv
+from paper_2205_06973_amd import hisv
+from paper_2205_06973_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"c64": (2e-5, 1e-4), "c128": (1e-12, 1e-11)}
+TDT = {"c64": torch.complex64, "c128": torch.complex128}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible GPU")
+    torch.cuda.init()
+    yield
+    torch.cuda.synchronize()
+
+
+def new_state(n, dtype, init=0):
+    t = torch.empty(1 << n, dtype=TDT[dtype], device="cuda")
+    st = hisv.State.wrap_tensor(t, torch.cuda.current_stream())
+    st.set_basis(init)
+    return st
+
+
+def run_hip(n, gates, dtype, k, strategy="dfs", mode="part_lds", init=0, seed=0, trials=16):
+    print(f"[case] n={n} G={len(gates)} {dtype} k={k} {strategy} {mode}", flush=True)
+    c = hisv.Circuit(n, gates)
+    plan = hisv.Plan.partition(c, k, strategy, seed=seed, trials=trials)
+    st = new_state(n, dtype, init)
+    if mode == "gate_per_pass":
+        st.simulate_gate_per_pass(c)
+    else:
+        st.simulate(plan, mode)
+    out = st.amplitudes()
+    st.close()
+    return out, plan
+
+
+def check(got, want, dtype):
+    d = np.abs(got - want)
+    mx, l2 = float(d.max()), float(np.linalg.norm(got - want))
+    bar_max, bar_l2 = TOL[dtype]
+    assert mx <= bar_max, f"max|d| = {mx:.3e} > {bar_max:.0e}"
+    assert l2 <= bar_l2, f"||d||_2 = {l2:.3e} > {bar_l2:.0e}"
+    return mx, l2
+
+
+ALL = sv.ONE_QUBIT + sv.TWO_QUBIT
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("mode", ["part_lds", "gate_per_pass"])
+def test_random12_k4(dtype, mode):
+    """The small workload: 12 qubits, 200 gates of {H, X, RZ, CX}, k = 4."""
+    n, gates = wl.random12(0)
+    got, plan = run_hip(n, gates, dtype, 4, "dfs", mode)
+    check(got, sv.simulate(n, gates), dtype)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n,k,strategy", [
+    (1, 1, "nat"), (2, 2, "nat"), (3, 3, "dfs"), (5, 2, "dfs"), (6, 6, "nat"), (7, 3, "dfs"),
+    (9, 5, "dfs"), (10, 7, "dfs"), (12, 12, "nat"), (13, 6, "dfs"), (14, 8, "dfs"),
+    (16, 4, "nat"), (17, 7, "dfs"),
+])
+def test_random_all_kinds(n, k, strategy, dtype):
+    kinds = ALL if n >= 2 else sv.ONE_QUBIT
+    gates = wl.random_circuit(n, 150, kinds, seed=100 + n + k)
+    if k > hisv.hs_max_part_qubits(dtype) and k < n:
+        pytest.skip("part wider than the kernel tile for this dtype")
+    got, _ = run_hip(n, gates, dtype, k, strategy, "part_lds", init=(n * 7919) % (1 << n))
+    check(got, sv.simulate(n, gates, (n * 7919) % (1 << n)), dtype)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_layered_20_k6(dtype):
+    n, gates = wl.layered28(3, n=20, layers=8)
+    got, _ = run_hip(n, gates, dtype, 6, "dfs")
+    check(got, sv.simulate(n, gates), dtype)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_qft_closed_form_18(dtype):
+    n = 18
+    x = wl.random_basis_index(n, 5)
+    got, _ = run_hip(n, wl.qft_circuit(n), dtype, 7, "dfs", init=x)
+    y = np.arange(1 << n)
+    want = np.exp(2j * np.pi * ((x * y) % (1 << n)) / (1 << n)) / math.sqrt(1 << n)
+    check(got, want, dtype)
+
+
+def test_empty_circuit_leaves_state():
+    st = new_state(10, "c64", init=37)
+    c = hisv.Circuit(10, [])
+    plan = hisv.Plan.partition(c, 4, "dfs")
+    assert plan.num_parts == 0
+    st.simulate(plan, "part_lds")
+    want = sv.basis_state(10, 37)
+    np.testing.assert_array_equal(st.amplitudes(), want)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_readout_norm_probabilities(dtype):
+    n, gates = wl.random34(4, n=15, num_gates=200)
+    c = hisv.Circuit(n, gates)
+    plan = hisv.Plan.partition(c, 6, "dfs")
+    st = new_state(n, dtype)
+    st.simulate(plan, "part_lds")
+    want = sv.simulate(n, gates)
+    amp = st.amplitudes()
+    check(amp, want, dtype)
+    # slices, probabilities and the FP64 norm
+    np.testing.assert_array_equal(st.amplitudes(1000, 77), amp[1000:1077])
+    p = st.probabilities(5, 300)
+    np.testing.assert_allclose(p, np.abs(amp[5:305]) ** 2, rtol=1e-12, atol=1e-300)
+    nrm = st.norm()
+    assert abs(nrm - 1.0) < (1e-12 if dtype == "c128" else 1e-5)
+    assert st.norm() == nrm  # fixed-order reduction: identical on every call
+
+
+def test_part_by_part_equals_prefix():
+    """The state after the first j parts equals the oracle after those parts' gates."""
+    n, gates = wl.random34(9, n=14, num_gates=160)
+    c = hisv.Circuit(n, gates)
+    plan = hisv.Plan.partition(c, 5, "dfs", seed=2, trials=8)
+    parts = plan.part_of_gate()
+    st = new_state(n, "c128")
+    for j in range(plan.num_parts):
+        st.simulate_part(plan, j, "part_lds")
+        if j in (0, plan.num_parts // 2, plan.num_parts - 1):
+            prefix = [g for g, p in zip(gates, parts) if p <= j]
+            check(st.amplitudes(), sv.simulate(n, prefix), "c128")
+
+
+def test_errors_through_the_abi():
+    c = hisv.Circuit(8, [("h", 0, -1, ())])
+    plan = hisv.Plan.partition(c, 2, "nat")
+    st = new_state(9, "c64")
+    with pytest.raises(hisv.HisvError) as e:
+        st.simulate(plan, "part_lds")
+    assert e.value.code == "HS_E_ARG"
+    with pytest.raises(hisv.HisvError):
+        st.amplitudes(500, 100)
+    with pytest.raises(hisv.HisvError):
+        st.set_basis(1 << 9)

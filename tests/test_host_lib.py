@@ -1,0 +1,221 @@
+"""CPU tests of libhisv.so: exports, validation, partitioner, part compiler.
+
+No compute call here touches a GPU: partitioning and part compilation are
+host code, and the compiled descriptors are replayed on the host
+(tests/replay.py) against the oracle.
+"""
+
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import partition as op
+from oracle import statevector as sv
+from paper_2205_06973_amd import hisv
+from paper_2205_06973_amd import workloads as wl
+from tests.replay import replay_plan
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    with open(os.path.join(ROOT, "include", "hisv.h")) as f:
+        text = f.read()
+    declared = set(re.findall(r"^\s*(?:hs_status|const char\*)\s+(hs_\w+)\s*\(", text, re.M))
+    assert len(declared) >= 30
+    L = hisv.lib()
+    missing = [s for s in sorted(declared) if not hasattr(L, s)]
+    assert missing == []
+    # the binding covers every declared entry point
+    assert declared <= set(hisv.declared_symbols())
+    assert "gfx950" in hisv.hs_version()
+
+
+def test_device_count_works_without_gpu():
+    assert hisv.hs_device_count() >= 0
+
+
+def test_gate_struct_layout():
+    import ctypes
+    assert ctypes.sizeof(hisv.hs_gate) == 40
+
+
+@pytest.mark.parametrize("gate,code", [
+    (("h", 5, -1, ()), "HS_E_QUBIT_RANGE"),
+    (("cx", 1, 1, ()), "HS_E_QUBIT_RANGE"),
+    (("cx", 0, 9, ()), "HS_E_QUBIT_RANGE"),
+    (("h", -1, -1, ()), "HS_E_QUBIT_RANGE"),
+])
+def test_circuit_validation(gate, code):
+    with pytest.raises(hisv.HisvError) as e:
+        hisv.Circuit(5, [gate])
+    assert e.value.code == code
+
+
+def test_circuit_validation_bad_q1_for_1q():
+    arr = hisv.gates_to_array([("h", 0, -1, ())])
+    arr[0].q1 = 2
+    import ctypes
+    h = ctypes.c_void_p()
+    rc = hisv.lib().hs_circuit_load(4, arr, 1, ctypes.byref(h))
+    assert hisv.STATUS[rc] == "HS_E_ARG"
+    arr[0].q1 = -1
+    arr[0].kind = 99
+    rc = hisv.lib().hs_circuit_load(4, arr, 1, ctypes.byref(h))
+    assert hisv.STATUS[rc] == "HS_E_ARG"
+
+
+def test_arity_greater_than_k():
+    c = hisv.Circuit(4, [("cx", 0, 1, ())])
+    with pytest.raises(hisv.HisvError) as e:
+        hisv.Plan.partition(c, 1, "nat")
+    assert e.value.code == "HS_E_ARITY_GT_K"
+    with pytest.raises(hisv.HisvError) as e:
+        hisv.Plan.partition(c, 0, "nat")
+    assert e.value.code == "HS_E_ARG"
+
+
+CIRCUITS = [
+    ("random12", lambda: wl.random12(0)),
+    ("random12s3", lambda: wl.random12(3)),
+    ("layered14", lambda: wl.layered28(1, n=14, layers=6)),
+    ("qft10", lambda: (10, wl.qft_circuit(10))),
+    ("random20", lambda: wl.random34(2, n=20, num_gates=300)),
+]
+
+
+@pytest.mark.parametrize("name,make", CIRCUITS)
+@pytest.mark.parametrize("k", [2, 4, 6])
+def test_nat_matches_oracle_exactly(name, make, k):
+    n, gates = make()
+    c = hisv.Circuit(n, gates)
+    plan = hisv.Plan.partition(c, k, "nat")
+    got = plan.part_of_gate().tolist()
+    assert got == op.nat_partition(gates, k)
+    plan.validate()
+
+
+@pytest.mark.parametrize("name,make", CIRCUITS)
+@pytest.mark.parametrize("k", [2, 4, 6])
+def test_dfs_valid_and_not_worse_than_nat(name, make, k):
+    n, gates = make()
+    c = hisv.Circuit(n, gates)
+    nat = hisv.Plan.partition(c, k, "nat")
+    dfs = hisv.Plan.partition(c, k, "dfs", seed=7, trials=32)
+    parts = dfs.part_of_gate().tolist()
+    assert op.check_partition(n, gates, parts, k) == []
+    assert dfs.num_parts <= nat.num_parts
+    # deterministic for a seed
+    again = hisv.Plan.partition(c, k, "dfs", seed=7, trials=32)
+    assert again.part_of_gate().tolist() == parts
+    # part info agrees with the assignment
+    for p in range(dfs.num_parts):
+        mask, ng = dfs.part_info(p)
+        members = [i for i, x in enumerate(parts) if x == p]
+        assert ng == len(members)
+        assert mask == sum(1 << q for q in op.working_set(gates, members))
+
+
+def test_dfs_finds_fewer_parts_on_interleaved_circuit():
+    # Nat is poor when the order alternates between disjoint qubit groups
+    gates = []
+    for _ in range(6):
+        gates += [("cx", 0, 1, ()), ("cx", 2, 3, ())]
+    c = hisv.Circuit(4, gates)
+    nat = hisv.Plan.partition(c, 2, "nat")
+    dfs = hisv.Plan.partition(c, 2, "dfs", seed=1, trials=16)
+    assert nat.num_parts == 12
+    assert dfs.num_parts == op.brute_min_parts(4, gates[:8], 2) == 2 or dfs.num_parts == 2
+
+
+def test_plan_from_assignment_checks():
+    gates = [("cx", 0, 1, ()), ("cx", 1, 2, ()), ("cx", 0, 1, ())]
+    c = hisv.Circuit(3, gates)
+    ok = hisv.Plan.from_assignment(c, 3, [0, 0, 1])
+    assert ok.num_parts == 2
+    for bad, k in (([0, 1, 0], 3), ([0, 0, 1], 2), ([1, 0, 0], 3), ([0, 2, 2], 3)):
+        with pytest.raises(hisv.HisvError) as e:
+            hisv.Plan.from_assignment(c, k, bad)
+        assert e.value.code == "HS_E_BAD_PARTITION"
+
+
+# ---- part compiler: replay of the descriptors against the oracle --------------
+
+def _random_state(n, seed):
+    rng = np.random.default_rng(seed)
+    v = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    return v / np.linalg.norm(v)
+
+
+REPLAY_CASES = [
+    (1, 1, "nat"), (2, 2, "nat"), (3, 2, "dfs"), (5, 3, "dfs"), (6, 4, "nat"),
+    (8, 3, "dfs"), (9, 5, "dfs"), (11, 4, "dfs"), (12, 4, "nat"), (12, 6, "dfs"),
+    (12, 8, "dfs"), (13, 7, "dfs"), (14, 5, "dfs"), (12, 12, "nat"),
+]
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("n,k,strategy", REPLAY_CASES)
+def test_replay_of_compiled_parts_matches_oracle(n, k, strategy, dtype):
+    kinds = sv.ONE_QUBIT + sv.TWO_QUBIT if n >= 2 else sv.ONE_QUBIT
+    gates = wl.random_circuit(n, 120, kinds, seed=n * 31 + k)
+    c = hisv.Circuit(n, gates)
+    try:
+        plan = hisv.Plan.partition(c, k, strategy, seed=3, trials=8)
+        psi0 = _random_state(n, n + k)
+        got, facts = replay_plan(plan, n, psi0, dtype)
+    except hisv.HisvError as e:
+        assert e.code == "HS_E_UNSUPPORTED" and k > hisv.hs_max_part_qubits(dtype)
+        return
+    want = sv.simulate(n, gates, psi0)
+    np.testing.assert_allclose(got, want, atol=1e-12, rtol=0)
+    parts = plan.part_of_gate()
+    for p, f in enumerate(facts):
+        mask, _ = plan.part_info(p)
+        S = [q for q in range(n) if mask >> q & 1]
+        assert set(S) <= set(f["tq"]), "tile must hold the part's qubits"
+        assert f["tq"] == sorted(f["tq"])
+        pad = sorted(set(f["tq"]) - set(S))
+        others = [q for q in range(n) if q not in S]
+        assert pad == others[:len(pad)], "padding takes the lowest other qubits"
+        assert f["load_lane_qubits"] == list(range(f["lb"]))
+        assert f["store_lane_qubits"] == list(range(f["lb"]))
+        assert f["m"] == f["lb"] + f["wb"] + f["rb"] <= n
+        assert len(parts) == len(gates)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_replay_structured_circuits(dtype):
+    for n, gates in [(10, wl.qft_circuit(10)), (12, wl.layered28(2, n=12, layers=5)[1]),
+                     (9, wl.ghz_circuit(9))]:
+        c = hisv.Circuit(n, gates)
+        plan = hisv.Plan.partition(c, min(n, 6), "dfs", seed=1, trials=8)
+        psi0 = _random_state(n, 5)
+        got, _ = replay_plan(plan, n, psi0, dtype)
+        np.testing.assert_allclose(got, sv.simulate(n, gates, psi0), atol=1e-12, rtol=0)
+
+
+def test_fusion_merges_runs_of_one_qubit_gates():
+    # 40 one-qubit gates on one qubit fuse into a single register op
+    gates = [("rx", 3, -1, (0.1 * i,)) if i % 2 else ("rz", 3, -1, (0.2 * i,)) for i in range(40)]
+    c = hisv.Circuit(8, gates)
+    plan = hisv.Plan.partition(c, 2, "nat")
+    assert plan.num_parts == 1
+    hdr, ent, ops = plan.part_descriptors(0, "c128")
+    assert len(ops) == 1
+    got, _ = replay_plan(plan, 8, sv.basis_state(8, 0))
+    np.testing.assert_allclose(got, sv.simulate(8, gates), atol=1e-12)
+
+
+def test_layout_report():
+    n, gates = wl.random12(0)
+    c = hisv.Circuit(n, gates)
+    plan = hisv.Plan.partition(c, 4, "dfs", seed=0, trials=16)
+    for p in range(plan.num_parts):
+        m, stages, trips = plan.part_layout(p, "c64")
+        assert m <= n and stages >= 1 and trips >= 0
+    assert hisv.hs_max_part_qubits("c64") >= 7
+    assert hisv.hs_max_part_qubits("c128") >= 6
