@@ -1,0 +1,249 @@
+#!/usr/bin/env python3
+"""Benchmark of the partitioned state-vector hot path on one MI355X.
+
+A step applies one whole circuit -- every part of its acyclic partition, one
+in-place Gather-Execute-Scatter sweep of the state per part (Alg. 1) -- to
+a state already resident in HBM.  Default workload: a 34-qubit random
+circuit of 1,000 gates drawn uniformly from {H, RZ, RX, CX, CZ}, complex64
+state (128 GiB), DFS partition (Sec. IV.B.2) with at most k qubits per part.
+
+Prints ONE JSON line on stdout:
+  value      gates/s over the timed steps (wall clock, synchronized)
+  roofline   the part-pass kernel: algorithmic bytes per launch (read + write
+             every amplitude once: 2 * 2^n * bytes/amplitude) / the average
+             launch duration from HIP events on the kernel's stream, against
+             the 8 TB/s HBM peak; `traffic` from committed rocprofv3 counters
+  gate_per_pass  the same GPU, one sweep per gate, on the circuit's first gates
+  serving    p50/p99 latency and circuits/s of a short Poisson request stream
+  cpu_baseline  the oracle (numpy complex128) on a bounded sample
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "gates/s + HBM GB/s per part-pass at n=30..34; p50/p99 latency in serving loop"
+HBM_PEAK_GBS = 8000.0
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+
+
+def part_pass_bytes(n: int, dtype: str) -> int:
+    """Algorithmic HBM bytes of one part-pass: every amplitude read and written once."""
+    return 2 * (1 << n) * (8 if dtype == "c64" else 16)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "layout.h", "compile.cpp"):
+        with open(os.path.join(ROOT, "paper_2205_06973_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(n: int, dtype: str, k: int):
+    """Per-launch HBM bytes from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source and this workload; else None."""
+    path = os.path.join(PROFILE_DIR, "part_pass_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    key = f"n{n}_{dtype}_k{k}"
+    if d.get("kernel_source_hash") != kernel_source_hash() or key not in d.get("workloads", {}):
+        return None
+    return d["workloads"][key]["bytes_per_launch"]
+
+
+def cpu_baseline(n_target: int, seed: int, budget_s: float = 12.0, n_cpu: int = 24) -> dict:
+    """The oracle as it stands, one host thread, on the first gates of the same
+    circuit distribution at n_cpu qubits; per-gate time scaled by 2^(n_target-n_cpu)."""
+    from oracle import statevector as sv  # test infrastructure: this leg only
+    from paper_2205_06973_amd import workloads as wl
+    _, gates = wl.random34(seed, n=n_cpu)
+    psi = sv.basis_state(n_cpu, 0)
+    t0 = time.perf_counter()
+    done = 0
+    while done < len(gates):
+        sv.apply_gate(psi, gates[done])
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    per_gate = dt / done
+    scale = 2.0 ** (n_target - n_cpu)
+    return {
+        "value": 1.0 / (per_gate * scale), "unit": "gates/s", "cores": 1, "kind": "oracle",
+        "sample": (f"numpy complex128 oracle, 1 thread, first {done} gates of the same "
+                   f"distribution at n={n_cpu} ({dt:.1f} s); per-gate time x2^{n_target - n_cpu} "
+                   f"to n={n_target}"),
+        "host_cpus": len(os.sched_getaffinity(0)),
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=34)
+    ap.add_argument("--gates", type=int, default=1000)
+    ap.add_argument("--k", type=int, default=7)
+    ap.add_argument("--dtype", default="c64", choices=["c64", "c128"])
+    ap.add_argument("--strategy", default="dfs", choices=["nat", "dfs"])
+    ap.add_argument("--trials", type=int, default=32)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--mode", default="part_lds", choices=["part_lds", "auto"])
+    ap.add_argument("--gpp-gates", type=int, default=48,
+                    help="gates timed on the gate-per-pass baseline (0 = skip)")
+    ap.add_argument("--serving", type=int, default=120, help="serving requests (0 = skip)")
+    ap.add_argument("--serving-rate", type=float, default=40.0, help="arrivals per second")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--copy-probe-gib", type=float, default=0.0,
+                    help="also run the plain copy kernel on this many GiB (counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus}, WORLD_SIZE {world}).", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2205_06973_amd import hisv
+    from paper_2205_06973_amd import workloads as wl
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+
+    n, G = args.n, args.gates
+    _, gates = wl.random34(args.seed, n=n, num_gates=G)
+    circ = hisv.Circuit(n, gates)
+    t = time.perf_counter()
+    plan = hisv.Plan.partition(circ, args.k, args.strategy, seed=args.seed, trials=args.trials)
+    part_ms = (time.perf_counter() - t) * 1e3
+    P = plan.num_parts
+    log(f"[bench] n={n} G={G} k={args.k} {args.strategy}: {P} parts ({part_ms:.1f} ms)")
+
+    stream = torch.cuda.Stream()
+    tdt = torch.complex64 if args.dtype == "c64" else torch.complex128
+    with torch.cuda.stream(stream):
+        buf = torch.empty(1 << n, dtype=tdt, device="cuda")
+    st = hisv.State.wrap_tensor(buf, stream)
+    st.set_basis(0)
+    for _ in range(args.warmup):
+        st.simulate(plan, args.mode)
+    torch.cuda.synchronize()
+    log(f"[bench] warmup done ({args.warmup} steps)")
+
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for i in range(args.steps):
+        st.simulate(plan, args.mode)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = e0.elapsed_time(e1)
+    log(f"[bench] timed {args.steps} steps: wall {wall:.3f} s, events {gpu_ms:.1f} ms")
+    norm = st.norm()
+
+    launches = args.steps * P
+    avg_launch_s = gpu_ms / 1e3 / launches
+    bpl = part_pass_bytes(n, args.dtype)
+    achieved = bpl / avg_launch_s / 1e9
+    traffic = committed_traffic(n, args.dtype, args.k)
+    out = {
+        "metric": METRIC,
+        "value": G * args.steps / wall,
+        "unit": "gates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.dtype == "c64" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"random{n}: {n}-qubit random circuit, {G} gates uniform over "
+                         f"{{H,RZ,RX,CX,CZ}}, {'complex64' if args.dtype == 'c64' else 'complex128'} "
+                         f"state ({bpl // 2 / 2**30:.0f} GiB), {args.strategy.upper()} partition k={args.k}"),
+            "n": n, "gates": G, "k": args.k, "parts": P, "strategy": args.strategy,
+            "state": "complex64" if args.dtype == "c64" else "complex128", "mode": args.mode,
+            "passes_saved": G / P,
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": "part_pass_kernel", "bytes_per_launch": bpl,
+            "avg_launch_us": avg_launch_s * 1e6, "launches": launches,
+        },
+        "norm_after": norm,
+    }
+
+    if args.gpp_gates > 0:
+        sub = hisv.Circuit(n, gates[:args.gpp_gates])
+        st.simulate_gate_per_pass(sub)  # warm
+        torch.cuda.synchronize()
+        e0.record(stream)
+        st.simulate_gate_per_pass(sub)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        gpp_s = e0.elapsed_time(e1) / 1e3
+        gpp_rate = args.gpp_gates / gpp_s
+        out["gate_per_pass"] = {
+            "gates_timed": args.gpp_gates, "gates_per_s": gpp_rate,
+            "pass_GBps": bpl / (gpp_s / args.gpp_gates) / 1e9,
+            "speedup_partitioned": out["value"] / gpp_rate,
+            "passes_saved": G / P,
+        }
+        log(f"[bench] gate-per-pass: {gpp_rate:.1f} gates/s")
+
+    st.close()
+    del buf
+    torch.cuda.empty_cache()
+
+    if args.copy_probe_gib > 0:
+        nbytes = int(args.copy_probe_gib * 2**30) // 16 * 16
+        a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        hisv.hs_copy_probe(a.data_ptr(), b.data_ptr(), nbytes, stream)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = nbytes
+        del a, b
+        torch.cuda.empty_cache()
+
+    if args.serving > 0:
+        from paper_2205_06973_amd import serving
+        reqs = wl.serving_stream(args.serving, args.serving_rate, seed=args.seed)
+        lat, swall, stats, _ = serving.run_stream(reqs)
+        out["serving"] = serving.summarize(lat, swall, len(reqs))
+        out["serving"].update({"arrival_rate_per_s": args.serving_rate,
+                               "peak_inflight": stats["peak_inflight"],
+                               "peak_admitted_GiB": stats["peak_bytes"] / 2**30})
+        log(f"[bench] serving: {out['serving']}")
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(n, args.seed)
+        log(f"[bench] cpu baseline: {out['cpu_baseline']['value']:.3g} gates/s")
+
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -225,7 +225,7 @@ hs_status hs_partition(hs_circuit c, int k, hs_strategy strategy, uint64_t seed,
       CHECK_ARG(trials >= 1, "DFS needs trials >= 1");
       partition_dfs(c->gates, dag, k, seed, trials, &part);
       break;
-    case HS_PART_DAGP: return fail(HS_E_UNSUPPORTED, "DAGP partitioning is not built yet");
+    case HS_PART_DAGP: partition_dagp(c->gates, dag, c->n, k, seed, &part); break;
     default: return fail(HS_E_ARG, "unknown strategy %d", (int)strategy);
   }
   auto* p = new hs_plan_();

@@ -37,13 +37,13 @@ using IC = std::integral_constant<int, N>;
 template <int RB, typename F>
 __device__ __forceinline__ void for_bit(int b, F&& f) {
   switch (b) {
-    case 0: if constexpr (RB > 0) f(IC<0>{}); break;
-    case 1: if constexpr (RB > 1) f(IC<1>{}); break;
-    case 2: if constexpr (RB > 2) f(IC<2>{}); break;
-    case 3: if constexpr (RB > 3) f(IC<3>{}); break;
-    case 4: if constexpr (RB > 4) f(IC<4>{}); break;
-    case 5: if constexpr (RB > 5) f(IC<5>{}); break;
-    default: break;
+    case 0: if constexpr (RB > 0) { f(IC<0>{}); break; } else __builtin_unreachable();
+    case 1: if constexpr (RB > 1) { f(IC<1>{}); break; } else __builtin_unreachable();
+    case 2: if constexpr (RB > 2) { f(IC<2>{}); break; } else __builtin_unreachable();
+    case 3: if constexpr (RB > 3) { f(IC<3>{}); break; } else __builtin_unreachable();
+    case 4: if constexpr (RB > 4) { f(IC<4>{}); break; } else __builtin_unreachable();
+    case 5: if constexpr (RB > 5) { f(IC<5>{}); break; } else __builtin_unreachable();
+    default: __builtin_unreachable();
   }
 }
 
@@ -52,6 +52,7 @@ __device__ __forceinline__ void for_pair(int b0, int b1, F&& f) {
   for_bit<RB>(b0, [&](auto B0) __attribute__((always_inline)) {
     for_bit<RB>(b1, [&](auto B1) __attribute__((always_inline)) {
       if constexpr (decltype(B0)::value != decltype(B1)::value) f(B0, B1);
+      else __builtin_unreachable();
     });
   });
 }
@@ -205,7 +206,7 @@ __device__ __forceinline__ void apply_op(RegV<T, RB>& a, const OpDesc<T>* __rest
         r_swap<T, RB, decltype(B0)::value, decltype(B1)::value>(a);
       });
       break;
-    default: break;
+    default: __builtin_unreachable();
   }
 }
 

@@ -219,3 +219,53 @@ def test_layout_report():
         assert m <= n and stages >= 1 and trips >= 0
     assert hisv.hs_max_part_qubits("c64") >= 7
     assert hisv.hs_max_part_qubits("c128") >= 6
+
+
+# ---- dagP-style partitioner ----------------------------------------------------
+
+@pytest.mark.parametrize("name,make", CIRCUITS)
+@pytest.mark.parametrize("k", [2, 3, 5, 7])
+def test_dagp_valid_and_deterministic(name, make, k):
+    n, gates = make()
+    c = hisv.Circuit(n, gates)
+    p = hisv.Plan.partition(c, k, "dagp", seed=11)
+    parts = p.part_of_gate().tolist()
+    assert op.check_partition(n, gates, parts, k) == []
+    assert hisv.Plan.partition(c, k, "dagp", seed=11).part_of_gate().tolist() == parts
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_dagp_not_below_brute_force(seed):
+    n = 5
+    gates = wl.random_circuit(n, 8, ("h", "rz", "cx", "cz"), seed)
+    for k in (2, 3):
+        p = hisv.Plan.partition(hisv.Circuit(n, gates), k, "dagp", seed=seed)
+        assert p.num_parts >= op.brute_min_parts(n, gates, k)
+        assert op.check_partition(n, gates, p.part_of_gate().tolist(), k) == []
+
+
+def test_dagp_merges_interleaved_groups():
+    gates = []
+    for _ in range(6):
+        gates += [("cx", 0, 1, ()), ("cx", 2, 3, ())]
+    p = hisv.Plan.partition(hisv.Circuit(4, gates), 2, "dagp", seed=0)
+    assert p.num_parts == 2
+
+
+def test_dagp_beats_cutoffs_on_qft():
+    n = 24
+    gates = wl.qft_circuit(n)
+    c = hisv.Circuit(n, gates)
+    d = hisv.Plan.partition(c, 7, "dagp", seed=0).num_parts
+    f = hisv.Plan.partition(c, 7, "dfs", seed=0, trials=32).num_parts
+    assert d < f
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_replay_dagp_plan(dtype):
+    n, gates = wl.random34(5, n=13, num_gates=200)
+    c = hisv.Circuit(n, gates)
+    plan = hisv.Plan.partition(c, 6, "dagp", seed=2)
+    psi0 = _random_state(n, 3)
+    got, _ = replay_plan(plan, n, psi0, dtype)
+    np.testing.assert_allclose(got, sv.simulate(n, gates, psi0), atol=1e-12, rtol=0)
