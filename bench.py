@@ -98,10 +98,10 @@ def main() -> int:
     ap.add_argument("--gates", type=int, default=1000)
     ap.add_argument("--k", type=int, default=7)
     ap.add_argument("--dtype", default="c64", choices=["c64", "c128"])
-    ap.add_argument("--strategy", default="dfs", choices=["nat", "dfs"])
+    ap.add_argument("--strategy", default="dfs", choices=["nat", "dfs", "dagp"])
     ap.add_argument("--trials", type=int, default=32)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--mode", default="part_lds", choices=["part_lds", "auto"])
+    ap.add_argument("--mode", default="part_spec", choices=["part_lds", "part_spec", "auto"])
     ap.add_argument("--gpp-gates", type=int, default=48,
                     help="gates timed on the gate-per-pass baseline (0 = skip)")
     ap.add_argument("--serving", type=int, default=120, help="serving requests (0 = skip)")
@@ -134,6 +134,13 @@ def main() -> int:
     part_ms = (time.perf_counter() - t) * 1e3
     P = plan.num_parts
     log(f"[bench] n={n} G={G} k={args.k} {args.strategy}: {P} parts ({part_ms:.1f} ms)")
+
+    spec_s = 0.0
+    if args.mode == "part_spec":
+        t = time.perf_counter()
+        plan.specialize(args.dtype)
+        spec_s = time.perf_counter() - t
+        log(f"[bench] specialized {P} part kernels in {spec_s:.1f} s")
 
     stream = torch.cuda.Stream()
     tdt = torch.complex64 if args.dtype == "c64" else torch.complex128
@@ -184,7 +191,7 @@ def main() -> int:
                          f"state ({bpl // 2 / 2**30:.0f} GiB), {args.strategy.upper()} partition k={args.k}"),
             "n": n, "gates": G, "k": args.k, "parts": P, "strategy": args.strategy,
             "state": "complex64" if args.dtype == "c64" else "complex128", "mode": args.mode,
-            "passes_saved": G / P,
+            "passes_saved": G / P, "specialize_s": spec_s,
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

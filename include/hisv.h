@@ -93,9 +93,16 @@ typedef enum { HS_PART_NAT = 0, HS_PART_DFS = 1, HS_PART_DAGP = 2 } hs_strategy;
  *                    register-resident sub-states, staged through LDS;
  *   PART_FUSED    -- one sweep per part; each part's gates are multiplied
  *                    into one dense 2^w x 2^w unitary applied on matrix cores;
- *   AUTO          -- per part, the cheaper of PART_LDS and PART_FUSED. */
+ *   AUTO          -- per part, the cheaper of PART_LDS and PART_FUSED;
+ *   PART_SPEC     -- one sweep per part, as PART_LDS, with each part's kernel
+ *                    specialized at plan time: the part's layouts, register
+ *                    operations and coefficients become compile-time
+ *                    constants of a kernel built with hipRTC for gfx950
+ *                    (hs_plan_specialize builds them ahead; otherwise the
+ *                    first hs_simulate does). */
 typedef enum {
-  HS_EXEC_GATE_PER_PASS = 0, HS_EXEC_PART_LDS = 1, HS_EXEC_PART_FUSED = 2, HS_EXEC_AUTO = 3
+  HS_EXEC_GATE_PER_PASS = 0, HS_EXEC_PART_LDS = 1, HS_EXEC_PART_FUSED = 2, HS_EXEC_AUTO = 3,
+  HS_EXEC_PART_SPEC = 4
 } hs_exec;
 
 typedef struct hs_state_* hs_state;
@@ -113,6 +120,15 @@ const char* hs_last_error(void);
 
 /* Number of HIP devices visible (0 on a machine without a GPU). */
 hs_status hs_device_count(int* out);
+
+/* Layout knobs read when a plan is next compiled (plans already compiled
+ * keep theirs): "rb_c64" / "rb_c128" = register bits per lane (1..5, 2^rb
+ * amplitudes each); "contig" = the tile always holds qubits 0..contig-1
+ * (0..6); "min_run_c64" / "min_run_c128" = gather and scatter straight in a
+ * stage's layout when its lanes still cover qubits 0..min_run-1, instead of
+ * re-laying out through LDS (0..6; 6 = only fully contiguous 64-amplitude
+ * runs).  HS_E_ARG for an unknown key or value. */
+hs_status hs_tune(const char* key, int value);
 
 /* Largest part width k that hs_simulate with PART_LDS / PART_FUSED accepts
  * for the given dtype (the tile capacity of the kernels). */
@@ -194,6 +210,27 @@ hs_status hs_plan_part_layout(hs_plan p, int part, hs_dtype dtype, int* tile_qub
 hs_status hs_plan_part_descriptors(hs_plan p, int part, hs_dtype dtype, int32_t* header,
                                    int32_t* entries, int entries_cap, double* ops, int ops_cap);
 
+/* The HIP source of a part's specialized kernel (PART_SPEC) for `dtype`,
+ * NUL-terminated, into buf[cap]; *len receives the length without the NUL
+ * (query with buf = NULL).  HS_E_ARG if cap is too small. */
+hs_status hs_plan_part_source(hs_plan p, int part, hs_dtype dtype, char* buf, size_t cap,
+                              size_t* len);
+
+/* Build (hipRTC, in parallel) and load the PART_SPEC kernels of every part
+ * for `dtype` on the current device.  Kernels are cached per device by their
+ * source, so plans sharing parts share kernels.  HS_E_HIP with the compiler
+ * log on failure. */
+hs_status hs_plan_specialize(hs_plan p, hs_dtype dtype);
+
+/* The dense unitary U_p of a part as the fused path applies it: *w = the
+ * number of qubits it acts on (4 or 5; parts of fewer qubits are widened
+ * with the lowest other qubits, on which U acts as the identity).  If out is
+ * not NULL it receives w doubles (the qubits, ascending; bit b of a row or
+ * column index is the b-th of them) followed by the 2^w x 2^w matrix,
+ * row-major, interleaved complex128.  Built in FP64 from the part's gates
+ * in circuit order.  HS_E_UNSUPPORTED for parts wider than 5 qubits. */
+hs_status hs_plan_part_unitary(hs_plan p, int part, int* w, double* out);
+
 hs_status hs_plan_destroy(hs_plan p);
 
 /* ---- simulation (Alg. 1) --------------------------------------------------- */
@@ -216,6 +253,10 @@ hs_status hs_simulate_part(hs_state s, hs_plan p, int part, hs_exec exec);
  * (out has 2*count doubles; complex64 states are widened on the device).
  * Syncs. */
 hs_status hs_read_amplitudes(hs_state s, uint64_t first, uint64_t count, double* out);
+
+/* Amplitudes at the caller's indices idx[count] (each < 2^n; host array,
+ * copied) as interleaved complex128 into out[2*count].  Syncs. */
+hs_status hs_read_amplitudes_at(hs_state s, const uint64_t* idx, uint64_t count, double* out);
 
 /* |a|^2 in FP64 for amplitudes [first, first+count) into out[count].  Syncs. */
 hs_status hs_probabilities(hs_state s, uint64_t first, uint64_t count, double* out);

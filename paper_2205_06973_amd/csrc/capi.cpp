@@ -28,14 +28,22 @@ Plan::~Plan() {
     for (auto& kv : dev[d]) device_plan_free(kv.second);
 }
 
+// Tunable knobs (hs_tune), read when a plan is compiled.
+static std::mutex g_tune_mu;
+static int g_rb[2] = {4, 3};
+static int g_contig = 6;
+static int g_min_run[2] = {6, 6};
+
 CompileOptions default_options(hs_dtype dtype) {
   CompileOptions o;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  o.rb = g_rb[dtype];
+  o.contig = g_contig;
+  o.min_run = g_min_run[dtype];
   if (dtype == HS_C64) {
-    o.rb = 4;
     o.swizzle = 4;
     o.max_m = 14;  // 2^14 x 8 B = 128 KiB of LDS
   } else {
-    o.rb = 3;
     o.swizzle = 3;
     o.max_m = 13;  // 2^13 x 16 B = 128 KiB of LDS
   }
@@ -59,6 +67,23 @@ hs_status plan_build(int n, const std::vector<Gate>& gates, int k,
     p->parts[part_of_gate[i]].push_back((int)i);
     p->masks[part_of_gate[i]] |= gates[i].mask();
   }
+  return HS_OK;
+}
+
+// Fused forms of every part (w = 0 where a part is wider than the kernel).
+hs_status plan_compile_fused(Plan* p) {
+  std::lock_guard<std::mutex> lk(p->mu);
+  if (p->fused_built) return HS_OK;
+  std::vector<FusedPart> fused(p->parts.size());
+  std::vector<Gate> pg;
+  for (size_t i = 0; i < p->parts.size(); ++i) {
+    pg.clear();
+    for (int gi : p->parts[i]) pg.push_back(p->gates[gi]);
+    if (compile_fused(p->n, pg, &fused[i]) != HS_OK) fused[i] = FusedPart{};
+  }
+  clear_error();
+  p->fused.swap(fused);
+  p->fused_built = true;
   return HS_OK;
 }
 
@@ -91,6 +116,25 @@ hs_status hs_device_count(int* out) {
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess) n = 0;
   *out = n;
+  return HS_OK;
+}
+
+hs_status hs_tune(const char* key, int value) {
+  CHECK_ARG(key, "null key");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  const std::string k(key);
+  if (k == "rb_c64" || k == "rb_c128") {
+    CHECK_ARG(value >= 1 && value <= 5, "register bits must be 1..5");
+    g_rb[k == "rb_c64" ? 0 : 1] = value;
+  } else if (k == "contig") {
+    CHECK_ARG(value >= 0 && value <= 6, "contig must be 0..6");
+    g_contig = value;
+  } else if (k == "min_run_c64" || k == "min_run_c128") {
+    CHECK_ARG(value >= 0 && value <= 6, "min_run must be 0..6");
+    g_min_run[k == "min_run_c64" ? 0 : 1] = value;
+  } else {
+    return fail(HS_E_ARG, "unknown tuning key '%s'", key);
+  }
   return HS_OK;
 }
 
@@ -331,6 +375,52 @@ hs_status hs_plan_part_descriptors(hs_plan p, int part, hs_dtype dtype, int32_t*
   return HS_OK;
 }
 
+static hs_status ensure_spec(Plan* p, hs_dtype dtype, int device,
+                             std::vector<std::shared_ptr<SpecKernel>>** out) {
+  if (hs_status rc = plan_compile(p, dtype)) return rc;
+  std::lock_guard<std::mutex> lk(p->mu);
+  auto it = p->spec[dtype].find(device);
+  if (it == p->spec[dtype].end()) {
+    std::vector<std::shared_ptr<SpecKernel>> ks;
+    if (hs_status rc = specialize_plan(p->comp[dtype], dtype, device, &ks)) return rc;
+    it = p->spec[dtype].emplace(device, std::move(ks)).first;
+  }
+  *out = &it->second;
+  return HS_OK;
+}
+
+hs_status hs_plan_part_source(hs_plan p, int part, hs_dtype dtype, char* buf, size_t cap, size_t* len) {
+  CHECK_ARG(p, "null plan");
+  CHECK_ARG(dtype == HS_C64 || dtype == HS_C128, "bad dtype");
+  CHECK_ARG(part >= 0 && part < (int)p->parts.size(), "part %d out of range", part);
+  if (hs_status rc = plan_compile(p, dtype)) return rc;
+  const std::string src = specialize_part_source(p->comp[dtype][part], dtype, "part_pass_spec");
+  if (len) *len = src.size();
+  if (!buf) return HS_OK;
+  CHECK_ARG(cap > src.size(), "buffer of %zu bytes is too small", cap);
+  std::memcpy(buf, src.c_str(), src.size() + 1);
+  return HS_OK;
+}
+
+hs_status hs_plan_specialize(hs_plan p, hs_dtype dtype) {
+  CHECK_ARG(p, "null plan");
+  CHECK_ARG(dtype == HS_C64 || dtype == HS_C128, "bad dtype");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(HS_E_HIP, "no HIP device");
+  std::vector<std::shared_ptr<SpecKernel>>* ks = nullptr;
+  return ensure_spec(p, dtype, dev, &ks);
+}
+
+static hs_status run_spec_parts(hs_state s, Plan* p, int first, int last) {
+  std::vector<std::shared_ptr<SpecKernel>>* ks = nullptr;
+  if (hipSetDevice(s->device) != hipSuccess) return fail(HS_E_HIP, "hipSetDevice failed");
+  if (hs_status rc = ensure_spec(p, s->dtype, s->device, &ks)) return rc;
+  for (int i = first; i < last; ++i)
+    if (hs_status rc = launch_specialized(*(*ks)[i], s->ptr, p->comp[s->dtype][i].desc.tiles, s->stream))
+      return rc;
+  return HS_OK;
+}
+
 hs_status hs_plan_destroy(hs_plan p) {
   delete p;
   return HS_OK;
@@ -339,9 +429,31 @@ hs_status hs_plan_destroy(hs_plan p) {
 // ---- simulation --------------------------------------------------------------
 
 static hs_status check_exec(hs_exec exec) {
-  if (exec == HS_EXEC_GATE_PER_PASS || exec == HS_EXEC_PART_LDS || exec == HS_EXEC_AUTO) return HS_OK;
-  if (exec == HS_EXEC_PART_FUSED) return fail(HS_E_UNSUPPORTED, "PART_FUSED is not built yet");
+  if (exec == HS_EXEC_GATE_PER_PASS || exec == HS_EXEC_PART_LDS || exec == HS_EXEC_AUTO ||
+      exec == HS_EXEC_PART_SPEC || exec == HS_EXEC_PART_FUSED)
+    return HS_OK;
   return fail(HS_E_ARG, "unknown exec mode %d", (int)exec);
+}
+
+// Parts [first, last) on the interpreter LDS kernel, the fused kernel, or
+// (AUTO) whichever the cost model prefers per part.
+static hs_status run_parts(hs_state s, Plan* p, int first, int last, hs_exec exec) {
+  if (hs_status rc = plan_compile(p, s->dtype)) return rc;
+  if (exec != HS_EXEC_PART_LDS)
+    if (hs_status rc = plan_compile_fused(p)) return rc;
+  for (int i = first; i < last; ++i) {
+    bool fused = false;
+    if (exec == HS_EXEC_PART_FUSED) {
+      if (!p->fused[i].w)
+        return fail(HS_E_UNSUPPORTED, "part %d uses more than 5 qubits: no fused form", i);
+      fused = true;
+    } else if (exec == HS_EXEC_AUTO) {
+      fused = p->fused[i].w &&
+              fused_part_cost(p->fused[i], s->dtype) < lds_part_cost(p->comp[s->dtype][i]);
+    }
+    if (hs_status rc = fused ? dev_run_fused(s, p, i) : dev_run_part(s, p, i)) return rc;
+  }
+  return HS_OK;
 }
 
 hs_status hs_simulate_part(hs_state s, hs_plan p, int part, hs_exec exec) {
@@ -354,8 +466,8 @@ hs_status hs_simulate_part(hs_state s, hs_plan p, int part, hs_exec exec) {
       if (hs_status rc = dev_gate_pass(s, p->gates[gi])) return rc;
     return HS_OK;
   }
-  if (hs_status rc = plan_compile(p, s->dtype)) return rc;
-  return dev_run_part(s, p, part);
+  if (exec == HS_EXEC_PART_SPEC) return run_spec_parts(s, p, part, part + 1);
+  return run_parts(s, p, part, part + 1, exec);
 }
 
 hs_status hs_simulate(hs_state s, hs_plan p, hs_exec exec) {
@@ -367,9 +479,25 @@ hs_status hs_simulate(hs_state s, hs_plan p, hs_exec exec) {
       if (hs_status rc = dev_gate_pass(s, g)) return rc;
     return HS_OK;
   }
-  if (hs_status rc = plan_compile(p, s->dtype)) return rc;
-  for (int i = 0; i < (int)p->parts.size(); ++i)
-    if (hs_status rc = dev_run_part(s, p, i)) return rc;
+  if (exec == HS_EXEC_PART_SPEC) return run_spec_parts(s, p, 0, (int)p->parts.size());
+  return run_parts(s, p, 0, (int)p->parts.size(), exec);
+}
+
+hs_status hs_plan_part_unitary(hs_plan p, int part, int* w, double* out) {
+  CHECK_ARG(p && w, "null argument");
+  CHECK_ARG(part >= 0 && part < (int)p->parts.size(), "part %d out of range", part);
+  if (hs_status rc = plan_compile_fused(p)) return rc;
+  const FusedPart& f = p->fused[part];
+  *w = f.w;
+  if (!f.w) return fail(HS_E_UNSUPPORTED, "part %d has no fused form", part);
+  if (out) {
+    for (int b = 0; b < f.w; ++b) out[b] = f.sq[b];
+    double* u = out + f.w;
+    for (size_t i = 0; i < f.u.size(); ++i) {
+      u[2 * i] = f.u[i].real();
+      u[2 * i + 1] = f.u[i].imag();
+    }
+  }
   return HS_OK;
 }
 
@@ -389,6 +517,15 @@ hs_status hs_read_amplitudes(hs_state s, uint64_t first, uint64_t count, double*
   CHECK_ARG(first <= N && count <= N - first, "range outside the state");
   if (!count) return HS_OK;
   return dev_read(s, first, count, out, false);
+}
+
+hs_status hs_read_amplitudes_at(hs_state s, const uint64_t* idx, uint64_t count, double* out) {
+  CHECK_ARG(s && ((idx && out) || count == 0), "null argument");
+  const uint64_t N = uint64_t(1) << s->n;
+  for (uint64_t i = 0; i < count; ++i)
+    CHECK_ARG(idx[i] < N, "index %llu outside the state", (unsigned long long)idx[i]);
+  if (!count) return HS_OK;
+  return dev_read_at(s, idx, count, out);
 }
 
 hs_status hs_probabilities(hs_state s, uint64_t first, uint64_t count, double* out) {

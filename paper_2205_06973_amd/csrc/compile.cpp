@@ -75,6 +75,14 @@ bool lanes_are_low(const Layout& L, int lb) {
   return true;
 }
 
+// Number of leading lane bits that are tile bits 0, 1, 2, ... (the length,
+// in bits, of the contiguous global run each group of lanes touches).
+int low_run(const Layout& L, int lb) {
+  int c = 0;
+  while (c < lb && L.pos[c] == c) ++c;
+  return c;
+}
+
 bool same_layout(const Layout& a, const Layout& b, int m) {
   return std::memcmp(a.pos, b.pos, (size_t)m) == 0;
 }
@@ -184,7 +192,7 @@ hs_status compile_part(int n, const std::vector<Gate>& pg, const CompileOptions&
   for (const Stage& s : st) lay.push_back(make_layout(m, lb, wb, pad_regs(s.bits, m, rb)));
   // load and store layouts: lanes on tile bits 0..lb-1 (contiguous global runs)
   auto io_layout = [&](const Layout& near) {
-    if (lanes_are_low(near, lb)) return near;
+    if (lanes_are_low(near, lb) || low_run(near, lb) >= std::min(opt.min_run, lb)) return near;
     return make_layout(m, lb, wb, pad_regs(0u, m, rb));
   };
   const Layout load = io_layout(lay.front());
@@ -257,6 +265,114 @@ hs_status compile_part(int n, const std::vector<Gate>& pg, const CompileOptions&
   out->desc.lds_bytes = 0;  // set per dtype at upload
   out->lds_round_trips = trips;
   return HS_OK;
+}
+
+}  // namespace hisv
+
+namespace hisv {
+
+// ---- fused path: one dense unitary per part -----------------------------------
+//
+// U_p = product of the part's gates (circuit order), built in FP64 by
+// applying each gate to every column of the identity as a state of the
+// part's qubits (inner slot b = the b-th smallest part qubit, the slot order
+// of Alg. 1's worked example).  Parts narrower than 4 qubits take the lowest
+// other qubits as extra slots (U acts as the identity on them).
+hs_status compile_fused(int n, const std::vector<Gate>& pg, FusedPart* out) {
+  uint64_t S = 0;
+  for (const Gate& g : pg) S |= g.mask();
+  for (int q = 0; q < n && __builtin_popcountll(S) < 4; ++q) S |= 1ull << q;
+  const int w = __builtin_popcountll(S);
+  if (w > 5) return fail(HS_E_UNSUPPORTED, "fused path takes parts of at most 5 qubits (got %d)", w);
+  if (n < w + 4) return fail(HS_E_UNSUPPORTED, "fused path needs n >= %d", w + 4);
+  FusedPart f;
+  f.w = w;
+  f.m = w + 4;
+  f.tiles = uint64_t(1) << (n - f.m);
+  int slot[64];
+  for (int q = 0, b = 0; q < n; ++q) {
+    slot[q] = -1;
+    if (S >> q & 1) {
+      f.sq[b] = (int8_t)q;
+      slot[q] = b++;
+    }
+  }
+  uint64_t T = S;
+  for (int q = 0, c = 0; q < n && c < 4; ++q)
+    if (!(S >> q & 1)) {
+      f.pq[c++] = (int8_t)q;
+      T |= 1ull << q;
+    }
+  for (int q = 0, t = 0; q < n; ++q)
+    if (T >> q & 1) f.tq[t++] = (int8_t)q;
+  const int R = 1 << w;
+  f.u.assign((size_t)R * R, cd(0.0, 0.0));
+  for (int i = 0; i < R; ++i) f.u[(size_t)i * R + i] = 1.0;
+  // apply a gate to every column: column c is a 2^w state vector
+  for (const Gate& g : pg) {
+    const int a = slot[g.q0];
+    if (g.arity() == 1) {
+      cd m[4];
+      gate_matrix(g, m);
+      for (int c = 0; c < R; ++c)
+        for (int r0 = 0; r0 < R; ++r0) {
+          if (r0 >> a & 1) continue;
+          const int r1 = r0 | (1 << a);
+          const cd x = f.u[(size_t)r0 * R + c], y = f.u[(size_t)r1 * R + c];
+          f.u[(size_t)r0 * R + c] = m[0] * x + m[1] * y;
+          f.u[(size_t)r1 * R + c] = m[2] * x + m[3] * y;
+        }
+      continue;
+    }
+    const int b = slot[g.q1];
+    const cd ph = g.kind == HS_CP ? std::polar(1.0, g.p[0]) : cd(-1.0, 0.0);
+    for (int c = 0; c < R; ++c)
+      for (int r = 0; r < R; ++r) {
+        const bool ba = r >> a & 1, bb = r >> b & 1;
+        cd& v = f.u[(size_t)r * R + c];
+        switch (g.kind) {
+          case HS_CX:  // control a, target b: swap the pair with a = 1
+            if (ba && !bb) std::swap(v, f.u[(size_t)(r | (1 << b)) * R + c]);
+            break;
+          case HS_CZ:
+          case HS_CP:
+            if (ba && bb) v *= ph;
+            break;
+          case HS_SWAP:
+            if (ba && !bb) std::swap(v, f.u[(size_t)(r ^ (1 << a) ^ (1 << b)) * R + c]);
+            break;
+          default: return fail(HS_E_ARG, "unknown two-qubit kind %d", g.kind);
+        }
+      }
+  }
+  *out = std::move(f);
+  return HS_OK;
+}
+
+}  // namespace hisv
+
+namespace hisv {
+
+// Relative cost of a part (one HBM sweep of the state = 1), from timings of
+// the part-pass kernel on MI355X with a 30-qubit complex64 state: each LDS
+// re-layout of the tile costs about 0.14 sweep, each register operation on
+// a 16-amplitude lane as listed (dense complex 2x2 ~0.066 sweep, real or
+// diagonal ~0.035, controlled/permutation ~0.007).  Used by AUTO only.
+double lds_part_cost(const CompiledPart& cp) {
+  static const double op_cost[OP_NUM] = {0.066, 0.035, 0.038, 0.025, 0.01,
+                                         0.007, 0.007, 0.012, 0.01};
+  double c = 1.0 + 0.14 * cp.lds_round_trips;
+  for (const HostOp& op : cp.ops) c += op_cost[op.kind];
+  return c;
+}
+
+// The fused kernel's matrix-core time is about 0.4 (w = 4) and 0.8 (w = 5)
+// of an HBM sweep for both precisions, mostly overlapped with the sweep.
+double fused_part_cost(const FusedPart& f, hs_dtype dt) {
+  (void)dt;
+  if (f.w == 4) return 1.05;
+  if (f.w == 5) return 1.2;
+  return 1e30;
 }
 
 }  // namespace hisv

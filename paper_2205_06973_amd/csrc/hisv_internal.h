@@ -76,12 +76,28 @@ struct CompiledPart {
   int lds_round_trips = 0;
 };
 
+// A part applied as one dense unitary on matrix cores (the fused path):
+// U acts on the qubits sq[0..w) (bit b of a row/column index = qubit sq[b]),
+// columns of the batched product are the settings of the 4 column qubits.
+struct FusedPart {
+  int w = 0;                  // 4 or 5
+  int m = 0;                  // tile = w + 4 qubits
+  uint64_t tiles = 0;         // 2^(n - m)
+  int8_t sq[8] = {0};
+  int8_t pq[4] = {0};
+  int8_t tq[12] = {0};        // sq and pq together, ascending
+  std::vector<cd> u;          // 2^w x 2^w, row-major
+};
+hs_status compile_fused(int n, const std::vector<Gate>& part_gates, FusedPart* out);
+
 struct CompileOptions {
   int rb = 4;        // register bits per lane (2^rb amplitudes per lane)
   int contig = 6;    // tile always holds qubits 0..contig-1 (coalesced runs)
   int max_wb = 4;    // at most 2^max_wb wavefronts per workgroup
   int swizzle = 4;   // LDS swizzle width (bits)
   int max_m = 14;    // widest tile whose 2^m amplitudes fit the LDS
+  int min_run = 6;   // load/store straight in a stage layout whose lanes cover
+                     // at least qubits 0..min_run-1 (runs of 2^min_run amplitudes)
 };
 
 // Compile one part (its gates in circuit order) on an n-qubit state.
@@ -92,6 +108,7 @@ int max_tile_qubits(const CompileOptions& opt);
 // ---- plan -------------------------------------------------------------------
 struct DevicePlan;  // uploaded descriptors (kernels.hip)
 void device_plan_free(DevicePlan* d);
+struct SpecKernel;  // a part's specialized kernel (specialize.cpp)
 
 struct Plan {
   int n = 0, k = 0;
@@ -105,6 +122,9 @@ struct Plan {
   bool compiled[2] = {false, false};
   std::vector<CompiledPart> comp[2];
   std::map<int, DevicePlan*> dev[2];
+  std::map<int, std::vector<std::shared_ptr<SpecKernel>>> spec[2];  // per device
+  bool fused_built = false;
+  std::vector<FusedPart> fused;  // w = 0 where a part has no fused form
   ~Plan();
 };
 
@@ -132,9 +152,21 @@ inline size_t amp_bytes(hs_dtype d) { return d == HS_C64 ? 8 : 16; }
 hs_status dev_set_basis(State* s, uint64_t x);
 hs_status dev_gate_pass(State* s, const Gate& g);
 hs_status dev_run_part(State* s, Plan* p, int part);
+hs_status dev_run_fused(State* s, Plan* p, int part);
+hs_status plan_compile_fused(Plan* p);
+// relative cost (one HBM sweep = 1) of a part on each path, for AUTO
+double lds_part_cost(const CompiledPart& cp);
+double fused_part_cost(const FusedPart& f, hs_dtype dt);
 hs_status dev_norm(State* s, double* out);
 hs_status dev_read(State* s, uint64_t first, uint64_t count, double* out, bool probs);
+hs_status dev_read_at(State* s, const uint64_t* idx, uint64_t count, double* out);
 hs_status dev_copy_probe(const void* src, void* dst, size_t bytes, void* stream);
 hs_status dev_sync(State* s);
+
+// ---- specialized part kernels (specialize.cpp) ------------------------------------
+std::string specialize_part_source(const CompiledPart& cp, hs_dtype dt, const std::string& name);
+hs_status specialize_plan(const std::vector<CompiledPart>& parts, hs_dtype dt, int device,
+                          std::vector<std::shared_ptr<SpecKernel>>* out);
+hs_status launch_specialized(const SpecKernel& k, void* state, uint64_t tiles, void* stream);
 
 }  // namespace hisv

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 #include <map>
 #include <type_traits>
 
@@ -284,11 +285,19 @@ part_pass_kernel(cplx<T>* __restrict__ st, const PartDesc* __restrict__ pd,
   const uint32_t thr = lane | (wave << lb);
   const bool active = lane < (1 << lb);
 
-  RegV<T, RB> a;
-  for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+  // Software pipeline: the loads of a workgroup's next tile are issued
+  // before the current tile is processed, so HBM traffic overlaps the
+  // register and LDS work of the stages.
+  RegV<T, RB> a, nxt;
+  uint64_t tile = blockIdx.x;
+  if (tile < tiles)
+    tile_io<T, RB, false>(st, a, sd[0], pd->tq, lb, wb, tile_base(tile, pd->tq, m), lane, wave, active);
+  for (; tile < tiles; tile += gridDim.x) {
     const uint64_t tbase = tile_base(tile, pd->tq, m);
-    // ---- gather (entry 0 is the load layout: lanes on contiguous qubits)
-    tile_io<T, RB, false>(st, a, sd[0], pd->tq, lb, wb, tbase, lane, wave, active);
+    const uint64_t next = tile + gridDim.x;
+    if (next < tiles)
+      tile_io<T, RB, false>(st, nxt, sd[0], pd->tq, lb, wb, tile_base(next, pd->tq, m), lane, wave,
+                            active);
     // ---- execute: stages, re-laid out through LDS where the layout changes
     for (int s = 1; s < ne; ++s) {
       const StageDesc& e = sd[s];
@@ -332,6 +341,116 @@ part_pass_kernel(cplx<T>* __restrict__ st, const PartDesc* __restrict__ pd,
     }
     // ---- scatter (last entry is the store layout)
     tile_io<T, RB, true>(st, a, sd[ne - 1], pd->tq, lb, wb, tbase, lane, wave, active);
+    a = nxt;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// fused part-pass kernel: one dense unitary per part on matrix cores
+// ---------------------------------------------------------------------------
+// For a part on w qubits (w = 4 or 5) every outer setting is a column of X
+// (2^w rows, one per setting of the part's qubits); Y = U X for all columns.
+// A wavefront takes 16 columns at a time -- the settings of the 4 lowest
+// other qubits, so column runs are contiguous -- and computes the complex
+// product as four real products on 16x16x4 MFMA tiles:
+//   Yr = Ur Xr - Ui Xi,  Yi = Ur Xi + Ui Xr.
+// Operand layouts of the 16x16x4 MFMA (64 lanes, l = lane):
+//   A[i][k]: i = l % 16, k = l / 16;   B[k][j]: j = l % 16, k = l / 16;
+//   D[i][j] (4 registers v): j = l % 16 and
+//     i = 4 * (l / 16) + v  for the FP32 instruction,
+//     i = l / 16 + 4 * v    for the FP64 instruction
+// (checked on gfx950 with a probe that feeds lane numbers through A and B).
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+// deposit the low bits of v onto the listed qubits
+__device__ __forceinline__ uint64_t deposit(uint32_t v, const int8_t* q, int count) {
+  uint64_t g = 0;
+  for (int b = 0; b < count; ++b) g |= uint64_t((v >> b) & 1u) << q[b];
+  return g;
+}
+
+template <typename T, int W>
+__global__ void __launch_bounds__(256)
+fused_pass_kernel(cplx<T>* __restrict__ st, const FusedDesc* __restrict__ fd, const T* __restrict__ umat) {
+  using v4 = typename Mfma<T>::v4;
+  constexpr int R = 1 << W;   // rows of U
+  constexpr int RBK = R / 16; // 16-row blocks
+  constexpr int KS = R / 4;   // K steps of 4
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t i16 = lane & 15, g4 = lane >> 4;
+  const int m = fd->m;
+  const uint64_t tiles = fd->tiles;
+  const T* Ur = umat + fd->u_off;
+  const T* Ui = Ur + R * R;
+  T ur[RBK][KS], ui[RBK][KS], nui[RBK][KS];
+#pragma unroll
+  for (int rb = 0; rb < RBK; ++rb)
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int idx = (rb * 16 + i16) * R + ks * 4 + g4;
+      ur[rb][ks] = Ur[idx];
+      ui[rb][ks] = Ui[idx];
+      nui[rb][ks] = -ui[rb][ks];
+    }
+  // lane parts of the addresses: B rows k = 4*ks + g4 (slots 0-1 from the
+  // lane); D rows i = 16*rb + 4*g4 + v (FP32: slots 2-3 from the lane) or
+  // 16*rb + 4*v + g4 (FP64: slots 0-1 from the lane); columns j = i16 on
+  // the column qubits
+  constexpr bool f64 = sizeof(T) == 8;
+  const uint64_t col = deposit(i16, fd->pq, 4);
+  const uint64_t lane_ld = col + deposit(g4, fd->sq, 2);
+  const uint64_t lane_st = f64 ? lane_ld : col + deposit(g4 << 2, fd->sq, W);
+  uint64_t row_ld[KS], row_st[RBK][4];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) row_ld[ks] = deposit(4 * ks, fd->sq, W);
+#pragma unroll
+  for (int rb = 0; rb < RBK; ++rb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) row_st[rb][v] = deposit(16 * rb + (f64 ? 4 * v : v), fd->sq, W);
+  const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+  for (uint64_t tile = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); tile < tiles;
+       tile += waves) {
+    const uint64_t base = tile_base(tile, fd->tq, m);
+    T xr[KS], xi[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const cplx<T> v = st[base + row_ld[ks] + lane_ld];
+      xr[ks] = v.x;
+      xi[ks] = v.y;
+    }
+#pragma unroll
+    for (int rb = 0; rb < RBK; ++rb) {
+      v4 yr = {0, 0, 0, 0}, yi = {0, 0, 0, 0};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        yr = Mfma<T>::mma(ur[rb][ks], xr[ks], yr);
+        yr = Mfma<T>::mma(nui[rb][ks], xi[ks], yr);
+        yi = Mfma<T>::mma(ur[rb][ks], xi[ks], yi);
+        yi = Mfma<T>::mma(ui[rb][ks], xr[ks], yi);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        cplx<T> o;
+        o.x = yr[v];
+        o.y = yi[v];
+        st[base + row_st[rb][v] + lane_st] = o;
+      }
+    }
   }
 }
 
@@ -458,6 +577,18 @@ readout_kernel(const cplx<T>* __restrict__ st, uint64_t first, uint64_t count, i
   }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256)
+gather_kernel(const cplx<T>* __restrict__ st, const uint64_t* __restrict__ idx, uint64_t count,
+              double* __restrict__ out) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+    const cplx<T> v = st[idx[i]];
+    out[2 * i] = (double)v.x;
+    out[2 * i + 1] = (double)v.y;
+  }
+}
+
 __global__ void __launch_bounds__(256)
 copy_probe_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst, uint64_t n16) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -570,6 +701,12 @@ struct DevicePlan {
   std::vector<PartDesc> h_parts;     // host copy (absolute offsets)
   std::vector<int> rb;               // register bits of the kernel per part
   std::vector<unsigned> grid;        // persistent grid per part
+  // fused path (uploaded on first use)
+  bool fused_ready = false;
+  FusedDesc* fparts = nullptr;
+  void* fmat = nullptr;
+  std::vector<FusedDesc> h_fparts;
+  std::vector<unsigned> fgrid;
 };
 
 void device_plan_free(DevicePlan* d) {
@@ -578,6 +715,8 @@ void device_plan_free(DevicePlan* d) {
   if (d->parts) hipFree(d->parts);
   if (d->stages) hipFree(d->stages);
   if (d->ops) hipFree(d->ops);
+  if (d->fparts) hipFree(d->fparts);
+  if (d->fmat) hipFree(d->fmat);
   delete d;
 }
 
@@ -678,23 +817,95 @@ static hs_status launch_part(State* s, DevicePlan* dp, int part) {
   return HS_OK;
 }
 
+static hs_status device_plan(State* s, Plan* p, DevicePlan** out) {
+  const int dt = (int)s->dtype;
+  auto it = p->dev[dt].find(s->device);
+  if (it != p->dev[dt].end()) {
+    *out = it->second;
+    return HS_OK;
+  }
+  DevicePlan* dp = nullptr;
+  hs_status rc = dt == HS_C64 ? upload_plan<float>(p, dt, s->device, &dp)
+                              : upload_plan<double>(p, dt, s->device, &dp);
+  if (rc) return rc;
+  p->dev[dt][s->device] = dp;
+  *out = dp;
+  return HS_OK;
+}
+
 hs_status dev_run_part(State* s, Plan* p, int part) {
   HIP_TRY(hipSetDevice(s->device));
-  const int dt = (int)s->dtype;
   DevicePlan* dp = nullptr;
   {
     std::lock_guard<std::mutex> lk(p->mu);
-    auto it = p->dev[dt].find(s->device);
-    if (it == p->dev[dt].end()) {
-      hs_status rc = dt == HS_C64 ? upload_plan<float>(p, dt, s->device, &dp)
-                                  : upload_plan<double>(p, dt, s->device, &dp);
+    if (hs_status rc = device_plan(s, p, &dp)) return rc;
+  }
+  return s->dtype == HS_C64 ? launch_part<float>(s, dp, part) : launch_part<double>(s, dp, part);
+}
+
+template <typename T>
+static hs_status upload_fused(Plan* p, DevicePlan* dp) {
+  std::vector<FusedDesc> fds;
+  std::vector<T> mats;
+  DevInfo di;
+  if (hs_status rc = device_info(dp->device, &di)) return rc;
+  for (const FusedPart& f : p->fused) {
+    FusedDesc d{};
+    d.w = f.w;
+    d.m = f.m;
+    d.tiles = f.tiles;
+    d.u_off = (int32_t)mats.size();
+    std::memcpy(d.sq, f.sq, sizeof d.sq);
+    std::memcpy(d.pq, f.pq, sizeof d.pq);
+    std::memcpy(d.tq, f.tq, sizeof d.tq);
+    for (const cd& z : f.u) mats.push_back((T)z.real());
+    for (const cd& z : f.u) mats.push_back((T)z.imag());
+    fds.push_back(d);
+    // four wavefronts per block, enough blocks to cover every CU a few times
+    const uint64_t waves = f.tiles;
+    dp->fgrid.push_back((unsigned)std::max<uint64_t>(
+        1, std::min<uint64_t>((waves + 3) / 4, (uint64_t)di.cus * 8)));
+  }
+  if (mats.empty()) mats.push_back(T(0));
+  if (fds.empty()) fds.push_back(FusedDesc{});
+  HIP_TRY(hipMalloc(&dp->fparts, fds.size() * sizeof(FusedDesc)));
+  HIP_TRY(hipMalloc(&dp->fmat, mats.size() * sizeof(T)));
+  HIP_TRY(hipMemcpy(dp->fparts, fds.data(), fds.size() * sizeof(FusedDesc), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(dp->fmat, mats.data(), mats.size() * sizeof(T), hipMemcpyHostToDevice));
+  dp->h_fparts = fds;
+  dp->fused_ready = true;
+  return HS_OK;
+}
+
+template <typename T>
+static hs_status launch_fused(State* s, DevicePlan* dp, int part) {
+  const FusedDesc& d = dp->h_fparts[part];
+  cplx<T>* st = (cplx<T>*)s->ptr;
+  const FusedDesc* fd = dp->fparts + part;
+  const T* um = (const T*)dp->fmat;
+  hipStream_t str = stream_of(s);
+  if (d.w == 4)
+    hipLaunchKernelGGL((fused_pass_kernel<T, 4>), dim3(dp->fgrid[part]), dim3(256), 0, str, st, fd, um);
+  else if (d.w == 5)
+    hipLaunchKernelGGL((fused_pass_kernel<T, 5>), dim3(dp->fgrid[part]), dim3(256), 0, str, st, fd, um);
+  else
+    return fail(HS_E_UNSUPPORTED, "part %d has no fused form", part);
+  HIP_TRY(hipGetLastError());
+  return HS_OK;
+}
+
+hs_status dev_run_fused(State* s, Plan* p, int part) {
+  HIP_TRY(hipSetDevice(s->device));
+  DevicePlan* dp = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (hs_status rc = device_plan(s, p, &dp)) return rc;
+    if (!dp->fused_ready) {
+      hs_status rc = s->dtype == HS_C64 ? upload_fused<float>(p, dp) : upload_fused<double>(p, dp);
       if (rc) return rc;
-      p->dev[dt][s->device] = dp;
-    } else {
-      dp = it->second;
     }
   }
-  return dt == HS_C64 ? launch_part<float>(s, dp, part) : launch_part<double>(s, dp, part);
+  return s->dtype == HS_C64 ? launch_fused<float>(s, dp, part) : launch_fused<double>(s, dp, part);
 }
 
 // ---- readout ----------------------------------------------------------------
@@ -745,6 +956,34 @@ hs_status dev_read(State* s, uint64_t first, uint64_t count, double* out, bool p
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(out + done * per, s->scratch, c * per * sizeof(double),
                            hipMemcpyDeviceToHost, stream_of(s)));
+    HIP_TRY(hipStreamSynchronize(stream_of(s)));
+    done += c;
+  }
+  return HS_OK;
+}
+
+// Amplitudes at host-given indices (validated < 2^n by the caller), widened
+// to complex128, in chunks through the state's scratch buffer.
+hs_status dev_read_at(State* s, const uint64_t* idx, uint64_t count, double* out) {
+  HIP_TRY(hipSetDevice(s->device));
+  const uint64_t chunk = uint64_t(1) << 21;  // 16 MiB of indices + 32 MiB of output
+  if (hs_status rc = ensure_scratch(s, chunk * 24)) return rc;
+  uint64_t* didx = (uint64_t*)s->scratch;
+  double* dout = (double*)((char*)s->scratch + chunk * 8);
+  for (uint64_t done = 0; done < count;) {
+    const uint64_t c = std::min(chunk, count - done);
+    unsigned grid;
+    if (hs_status rc = stream_grid(s->device, c, &grid)) return rc;
+    HIP_TRY(hipMemcpyAsync(didx, idx + done, c * sizeof(uint64_t), hipMemcpyHostToDevice, stream_of(s)));
+    if (s->dtype == HS_C64)
+      hipLaunchKernelGGL(gather_kernel<float>, dim3(grid), dim3(256), 0, stream_of(s),
+                         (const cplx<float>*)s->ptr, didx, c, dout);
+    else
+      hipLaunchKernelGGL(gather_kernel<double>, dim3(grid), dim3(256), 0, stream_of(s),
+                         (const cplx<double>*)s->ptr, didx, c, dout);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(out + 2 * done, dout, c * 2 * sizeof(double), hipMemcpyDeviceToHost,
+                           stream_of(s)));
     HIP_TRY(hipStreamSynchronize(stream_of(s)));
     done += c;
   }

@@ -64,6 +64,18 @@ struct alignas(16) OpDesc {
   T c[8];
 };
 
+// A fused part on the device: U (2^w x 2^w, real block then imaginary
+// block, row-major, in the state's precision) starts at element u_off of the
+// plan's matrix buffer.
+struct alignas(16) FusedDesc {
+  int32_t w, m;
+  uint64_t tiles;
+  int32_t u_off, pad;
+  int8_t sq[8];
+  int8_t pq[4];
+  int8_t tq[12];
+};
+
 // Tile index of coordinate bits `coord` under layout `pos` (bits < m).
 __host__ __device__ inline uint32_t tile_index(const int8_t* pos, int m, uint32_t coord) {
   uint32_t t = 0;

@@ -1,0 +1,395 @@
+// specialize.cpp -- per-part specialized part-pass kernels, built at plan time.
+//
+// The part-pass kernel in kernels.hip interprets a part's descriptors: every
+// register operation is dispatched at run time on its kind and bit
+// positions.  For long-running plans this file instead turns each compiled
+// part (tile qubits, load / stage / store layouts, register operations and
+// their coefficients) into straight-line HIP source -- register indices, LDS
+// offsets and coefficients become compile-time constants -- compiles it with
+// hipRTC for gfx950 and caches the resulting kernel.  The computation is the
+// same Alg. 1 sweep (gather the tile, run the stages, scatter it back); the
+// generated kernel also keeps the loads of the next tile in flight while the
+// current tile is processed.
+#include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
+
+#include <cinttypes>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <future>
+#include <sstream>
+#include <thread>
+
+#include "hisv_internal.h"
+
+namespace hisv {
+
+namespace {
+
+std::string lit(double v, bool f32) {
+  char buf[64];
+  if (f32) {
+    const float x = (float)v;
+    if (x == 0.0f) return std::signbit(x) ? "(-0.0f)" : "0.0f";
+    snprintf(buf, sizeof buf, "(%af)", x);
+  } else {
+    if (v == 0.0) return std::signbit(v) ? "(-0.0)" : "0.0";
+    snprintf(buf, sizeof buf, "(%a)", v);
+  }
+  return buf;
+}
+
+// value of coordinate bits -> tile index, for the register bits of a layout
+uint32_t reg_tile_offset(const StageDesc& e, int lb, int wb, int rb, int j) {
+  uint32_t t = 0;
+  for (int r = 0; r < rb; ++r)
+    if (j >> r & 1) t |= 1u << e.pos[lb + wb + r];
+  return t;
+}
+
+uint32_t slot(uint32_t t, int sw) {
+  const uint32_t mask = (1u << sw) - 1u;
+  uint32_t f = 0;
+  for (uint32_t h = t >> sw; h; h >>= sw) f ^= h & mask;
+  return t ^ f;
+}
+
+struct Emit {
+  std::ostringstream o;
+  bool f32;
+  int rb;
+  std::string T() const { return f32 ? "float" : "double"; }
+};
+
+// a[j] register names: ar<j>, ai<j>
+void emit_op(Emit& E, const HostOp& op) {
+  const int N = 1 << E.rb;
+  auto& o = E.o;
+  const bool f = E.f32;
+  auto L = [&](double v) { return lit(v, f); };
+  switch (op.kind) {
+    case OP_U: {
+      const double* c = op.c;
+      for (int j = 0; j < N; ++j) {
+        if (j >> op.b0 & 1) continue;
+        const int k = j | (1 << op.b0);
+        o << "  { const " << E.T() << " px = ar" << j << ", py = ai" << j << ", qx = ar" << k
+          << ", qy = ai" << k << ";\n"
+          << "    ar" << j << " = " << L(c[0]) << "*px - " << L(c[1]) << "*py + " << L(c[2]) << "*qx - "
+          << L(c[3]) << "*qy;\n"
+          << "    ai" << j << " = " << L(c[0]) << "*py + " << L(c[1]) << "*px + " << L(c[2]) << "*qy + "
+          << L(c[3]) << "*qx;\n"
+          << "    ar" << k << " = " << L(c[4]) << "*px - " << L(c[5]) << "*py + " << L(c[6]) << "*qx - "
+          << L(c[7]) << "*qy;\n"
+          << "    ai" << k << " = " << L(c[4]) << "*py + " << L(c[5]) << "*px + " << L(c[6]) << "*qy + "
+          << L(c[7]) << "*qx; }\n";
+      }
+      break;
+    }
+    case OP_R: {
+      const double* c = op.c;
+      for (int j = 0; j < N; ++j) {
+        if (j >> op.b0 & 1) continue;
+        const int k = j | (1 << op.b0);
+        o << "  { const " << E.T() << " px = ar" << j << ", py = ai" << j << ", qx = ar" << k
+          << ", qy = ai" << k << ";\n"
+          << "    ar" << j << " = " << L(c[0]) << "*px + " << L(c[1]) << "*qx; ai" << j << " = "
+          << L(c[0]) << "*py + " << L(c[1]) << "*qy;\n"
+          << "    ar" << k << " = " << L(c[2]) << "*px + " << L(c[3]) << "*qx; ai" << k << " = "
+          << L(c[2]) << "*py + " << L(c[3]) << "*qy; }\n";
+      }
+      break;
+    }
+    case OP_D:
+    case OP_D1:
+    case OP_CP:
+    case OP_CZ: {
+      for (int j = 0; j < N; ++j) {
+        double cr, ci;
+        if (op.kind == OP_D) {
+          const bool one = j >> op.b0 & 1;
+          cr = one ? op.c[2] : op.c[0];
+          ci = one ? op.c[3] : op.c[1];
+        } else if (op.kind == OP_D1) {
+          if (!(j >> op.b0 & 1)) continue;
+          cr = op.c[0];
+          ci = op.c[1];
+        } else {
+          if (!((j >> op.b0 & 1) && (j >> op.b1 & 1))) continue;
+          if (op.kind == OP_CZ) {
+            o << "  ar" << j << " = -ar" << j << "; ai" << j << " = -ai" << j << ";\n";
+            continue;
+          }
+          cr = op.c[0];
+          ci = op.c[1];
+        }
+        o << "  { const " << E.T() << " px = ar" << j << ", py = ai" << j << ";\n"
+          << "    ar" << j << " = px*" << L(cr) << " - py*" << L(ci) << "; ai" << j << " = px*" << L(ci)
+          << " + py*" << L(cr) << "; }\n";
+      }
+      break;
+    }
+    case OP_X:
+    case OP_CX:
+    case OP_SWAP: {
+      for (int j = 0; j < N; ++j) {
+        int k;
+        if (op.kind == OP_X) {
+          if (j >> op.b0 & 1) continue;
+          k = j | (1 << op.b0);
+        } else if (op.kind == OP_CX) {
+          if (!(j >> op.b0 & 1) || (j >> op.b1 & 1)) continue;
+          k = j | (1 << op.b1);
+        } else {
+          if (!(j >> op.b0 & 1) || (j >> op.b1 & 1)) continue;
+          k = j ^ (1 << op.b0) ^ (1 << op.b1);
+        }
+        o << "  { const " << E.T() << " tx = ar" << j << ", ty = ai" << j << "; ar" << j << " = ar" << k
+          << "; ai" << j << " = ai" << k << "; ar" << k << " = tx; ai" << k << " = ty; }\n";
+      }
+      break;
+    }
+    default: break;
+  }
+}
+
+// Global index contributed by the lane and wave bits of layout e.
+void emit_thread_offsets(Emit& E, const StageDesc& e, const PartDesc& d, const char* lane_var,
+                         const char* wave_var, const char* out_lane, const char* out_wave) {
+  auto& o = E.o;
+  o << "    const unsigned " << out_lane << " = 0u";
+  for (int c = 0; c < d.lb; ++c)
+    o << " | (((" << lane_var << " >> " << c << ") & 1u) << " << (int)d.tq[e.pos[c]] << ")";
+  o << ";\n    const unsigned long long " << out_wave << " = 0ull";
+  for (int c = 0; c < d.wb; ++c)
+    o << " | ((unsigned long long)((" << wave_var << " >> " << c << ") & 1u) << "
+      << (int)d.tq[e.pos[d.lb + c]] << ")";
+  o << ";\n";
+}
+
+void emit_io(Emit& E, const StageDesc& e, const PartDesc& d, bool store, const char* prefix,
+             const char* base) {
+  auto& o = E.o;
+  const int N = 1 << E.rb;
+  for (int j = 0; j < N; ++j) {
+    uint64_t g = 0;
+    const uint32_t t = reg_tile_offset(e, d.lb, d.wb, E.rb, j);
+    for (int i = 0; i < d.m; ++i)
+      if (t >> i & 1) g |= uint64_t(1) << d.tq[i];
+    if (store)
+      o << "      " << base << "[" << g << "ull] = make_v(ar" << j << ", ai" << j << ");\n";
+    else
+      o << "      { const V v = " << base << "[" << g << "ull]; " << prefix << "r" << j << " = v.x; "
+        << prefix << "i" << j << " = v.y; }\n";
+  }
+}
+
+void emit_transition(Emit& E, const StageDesc& from, const StageDesc& to, const PartDesc& d, int sw) {
+  auto& o = E.o;
+  const int N = 1 << E.rb;
+  auto thread_slot = [&](const StageDesc& e, const char* name) {
+    o << "    const unsigned " << name << " = sl(0u";
+    for (int c = 0; c < d.lb + d.wb; ++c)
+      o << " | (((thr >> " << c << ") & 1u) << " << (int)e.pos[c] << ")";
+    o << ");\n";
+  };
+  o << "    {\n";
+  thread_slot(from, "wb_");
+  o << "    __syncthreads();\n";
+  if (d.lb < 6) o << "    if (active) {\n";
+  for (int j = 0; j < N; ++j)
+    o << "      lds[wb_ ^ " << slot(reg_tile_offset(from, d.lb, d.wb, E.rb, j), sw) << "u] = make_v(ar" << j
+      << ", ai" << j << ");\n";
+  if (d.lb < 6) o << "    }\n";
+  o << "    __syncthreads();\n";
+  thread_slot(to, "rb_");
+  for (int j = 0; j < N; ++j)
+    o << "      { const V v = lds[rb_ ^ " << slot(reg_tile_offset(to, d.lb, d.wb, E.rb, j), sw)
+      << "u]; ar" << j << " = v.x; ai" << j << " = v.y; }\n";
+  o << "    }\n";
+}
+
+}  // namespace
+
+std::string specialize_part_source(const CompiledPart& cp, hs_dtype dt, const std::string& name) {
+  Emit E;
+  E.f32 = dt == HS_C64;
+  E.rb = cp.rb_kernel;
+  const PartDesc& d = cp.desc;
+  const int N = 1 << E.rb;
+  const int sw = E.f32 ? 4 : 3;
+  const int ne = (int)cp.stages.size();
+  auto& o = E.o;
+  const std::string T = E.T();
+  // hipRTC predefines the HIP language keywords; an offline hipcc build of
+  // the same source (used to inspect it) takes them from the runtime header
+  o << "#ifndef __HIPCC_RTC__\n#include <hip/hip_runtime.h>\n#endif\n";
+  o << "typedef " << T << " T;\n"
+    << "typedef struct __attribute__((aligned(" << 2 * (E.f32 ? 4 : 8) << "))) { T x, y; } V;\n"
+    << "static __device__ inline __attribute__((always_inline)) V make_v(T x, T y) { V v; v.x = x; v.y = y; return v; }\n"
+    << "static __device__ inline __attribute__((always_inline)) unsigned sl(unsigned t) { unsigned f = 0u, h = t >> " << sw
+    << "; while (h) { f ^= h & " << ((1 << sw) - 1) << "u; h >>= " << sw << "; } return t ^ f; }\n";
+  o << "extern \"C\" __global__ void __launch_bounds__(" << (64 << d.wb) << ") " << name
+    << "(V* __restrict__ st, unsigned long long tiles) {\n";
+  if (cp.lds_round_trips) o << "  __shared__ V lds[" << (1u << d.m) << "];\n";
+  o << "  const unsigned lane = threadIdx.x & 63u;\n"
+    << "  const unsigned wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);\n"
+    << "  const unsigned thr = lane | (wave << " << d.lb << ");\n"
+    << "  const bool active = lane < " << (1u << d.lb) << "u;\n"
+    << "  (void)thr; (void)active;\n";
+  o << "  " << T << " ";
+  for (int j = 0; j < N; ++j) o << "ar" << j << ", ai" << j << (j + 1 < N ? ", " : ";\n");
+  o << "  " << T << " ";
+  for (int j = 0; j < N; ++j) o << "nr" << j << ", ni" << j << (j + 1 < N ? ", " : ";\n");
+  // tile base: insert a zero bit at every tile qubit (ascending)
+  o << "  auto base_of = [&](unsigned long long t) -> unsigned long long {\n    unsigned long long b = t;\n";
+  for (int i = 0; i < d.m; ++i) {
+    const int q = d.tq[i];
+    o << "    b = ((b >> " << q << ") << " << (q + 1) << ") | (b & " << ((uint64_t(1) << q) - 1) << "ull);\n";
+  }
+  o << "    return b;\n  };\n";
+  // load layout offsets
+  o << "  {\n";
+  emit_thread_offsets(E, cp.stages[0], d, "lane", "wave", "lo_ld", "wo_ld");
+  emit_thread_offsets(E, cp.stages[ne - 1], d, "lane", "wave", "lo_st", "wo_st");
+  o << "  unsigned long long tile = blockIdx.x;\n"
+    << "  if (tile < tiles && active) {\n"
+    << "    const V* p = st + base_of(tile) + wo_ld + lo_ld;\n";
+  emit_io(E, cp.stages[0], d, false, "a", "p");
+  o << "  }\n"
+    << "  for (; tile < tiles; tile += gridDim.x) {\n"
+    << "    const unsigned long long tb = base_of(tile);\n"
+    << "    const unsigned long long nt = tile + gridDim.x;\n"
+    << "    if (nt < tiles && active) {\n"
+    << "      const V* p = st + base_of(nt) + wo_ld + lo_ld;\n";
+  emit_io(E, cp.stages[0], d, false, "n", "p");
+  o << "    }\n";
+  for (int s = 1; s < ne; ++s) {
+    const StageDesc& e = cp.stages[s];
+    if (e.transition) emit_transition(E, cp.stages[s - 1], e, d, sw);
+    for (int i = e.op_begin; i < e.op_end; ++i) emit_op(E, cp.ops[i]);
+  }
+  o << "    if (active) {\n"
+    << "      V* p = st + tb + wo_st + lo_st;\n";
+  emit_io(E, cp.stages[ne - 1], d, true, "a", "p");
+  o << "    }\n";
+  for (int j = 0; j < N; ++j) o << "    ar" << j << " = nr" << j << "; ai" << j << " = ni" << j << ";\n";
+  o << "  }\n  }\n}\n";
+  return o.str();
+}
+
+// ---- compile / cache / launch ----------------------------------------------------
+
+struct SpecKernel {
+  hipModule_t mod = nullptr;
+  hipFunction_t fn = nullptr;
+  int block = 64;
+  unsigned grid = 1;
+};
+
+namespace {
+std::mutex g_spec_mu;
+std::map<std::pair<int, size_t>, std::shared_ptr<SpecKernel>> g_spec;  // (device, source hash)
+
+hs_status rtc_compile(const std::string& src, const std::string& name, std::vector<char>* code) {
+  hiprtcProgram prog;
+  if (hiprtcCreateProgram(&prog, src.c_str(), (name + ".hip").c_str(), 0, nullptr, nullptr) !=
+      HIPRTC_SUCCESS)
+    return fail(HS_E_HIP, "hiprtcCreateProgram failed");
+  const char* opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature",
+                        "-Xclang", "-packed-fp32-ops"};
+  hiprtcResult r = hiprtcCompileProgram(prog, 7, opts);
+  if (r != HIPRTC_SUCCESS) {
+    size_t n = 0;
+    hiprtcGetProgramLogSize(prog, &n);
+    std::string log(n, '\0');
+    if (n) hiprtcGetProgramLog(prog, &log[0]);
+    hiprtcDestroyProgram(&prog);
+    return fail(HS_E_HIP, "hipRTC failed for %s: %s", name.c_str(), log.substr(0, 400).c_str());
+  }
+  size_t n = 0;
+  hiprtcGetCodeSize(prog, &n);
+  code->resize(n);
+  hiprtcGetCode(prog, code->data());
+  hiprtcDestroyProgram(&prog);
+  return HS_OK;
+}
+}  // namespace
+
+// Compile (in parallel) and load the specialized kernels of every part of a
+// plan for `dtype` on `device`; returns one kernel per part.
+hs_status specialize_plan(const std::vector<CompiledPart>& parts, hs_dtype dt, int device,
+                          std::vector<std::shared_ptr<SpecKernel>>* out) {
+  const int P = (int)parts.size();
+  std::vector<std::string> src(P);
+  std::vector<size_t> hash(P);
+  out->assign(P, nullptr);
+  std::vector<int> todo;
+  {
+    std::lock_guard<std::mutex> lk(g_spec_mu);
+    for (int i = 0; i < P; ++i) {
+      src[i] = specialize_part_source(parts[i], dt, "part_pass_spec");
+      hash[i] = std::hash<std::string>()(src[i]);
+      auto it = g_spec.find({device, hash[i]});
+      if (it != g_spec.end()) (*out)[i] = it->second;
+      else todo.push_back(i);
+    }
+  }
+  // dedupe identical sources among the parts still to build
+  std::map<size_t, int> first;
+  std::vector<int> build;
+  for (int i : todo)
+    if (!first.count(hash[i])) {
+      first[hash[i]] = i;
+      build.push_back(i);
+    }
+  std::vector<std::vector<char>> code(P);
+  std::vector<hs_status> rc(P, HS_OK);
+  std::vector<std::string> err(P);
+  const unsigned nthr = std::max(1u, std::min<unsigned>(16, std::thread::hardware_concurrency()));
+  std::atomic<size_t> next{0};
+  auto worker = [&]() {
+    for (size_t w; (w = next.fetch_add(1)) < build.size();) {
+      const int i = build[w];
+      rc[i] = rtc_compile(src[i], "part" + std::to_string(i), &code[i]);
+      if (rc[i]) err[i] = hs_last_error();
+    }
+  };
+  std::vector<std::thread> th;
+  for (unsigned t = 0; t < std::min<size_t>(nthr, build.size()); ++t) th.emplace_back(worker);
+  for (auto& t : th) t.join();
+  for (int i : build)
+    if (rc[i]) return fail(rc[i], "%s", err[i].c_str());
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+    return fail(HS_E_HIP, "device attribute query failed");
+  std::lock_guard<std::mutex> lk(g_spec_mu);
+  for (int i : build) {
+    auto k = std::make_shared<SpecKernel>();
+    if (hipModuleLoadData(&k->mod, code[i].data()) != hipSuccess)
+      return fail(HS_E_HIP, "hipModuleLoadData failed");
+    if (hipModuleGetFunction(&k->fn, k->mod, "part_pass_spec") != hipSuccess)
+      return fail(HS_E_HIP, "hipModuleGetFunction failed");
+    k->block = 64 << parts[i].desc.wb;
+    int per_cu = 0;
+    if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k->fn, k->block, 0) != hipSuccess ||
+        per_cu < 1)
+      return fail(HS_E_HIP, "occupancy query failed for a specialized part");
+    const uint64_t cap = (uint64_t)per_cu * cus;
+    k->grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(parts[i].desc.tiles, cap));
+    g_spec[{device, hash[i]}] = k;
+  }
+  for (int i : todo) (*out)[i] = g_spec[{device, hash[i]}];
+  return HS_OK;
+}
+
+hs_status launch_specialized(const SpecKernel& k, void* state, uint64_t tiles, void* stream) {
+  void* args[] = {&state, &tiles};
+  hipError_t e = hipModuleLaunchKernel(k.fn, k.grid, 1, 1, k.block, 1, 1, 0, (hipStream_t)stream,
+                                       args, nullptr);
+  if (e != hipSuccess) return fail(HS_E_HIP, "hipModuleLaunchKernel: %s", hipGetErrorString(e));
+  return HS_OK;
+}
+
+}  // namespace hisv

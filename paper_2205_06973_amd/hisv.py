@@ -25,7 +25,7 @@ DTYPES = {"c64": 0, "c128": 1}
 KINDS = {"h": 0, "x": 1, "y": 2, "z": 3, "s": 4, "t": 5, "rx": 6, "ry": 7, "rz": 8,
          "p": 9, "u3": 10, "cx": 11, "cz": 12, "cp": 13, "swap": 14}
 STRATEGIES = {"nat": 0, "dfs": 1, "dagp": 2}
-EXEC = {"gate_per_pass": 0, "part_lds": 1, "part_fused": 2, "auto": 3}
+EXEC = {"gate_per_pass": 0, "part_lds": 1, "part_fused": 2, "auto": 3, "part_spec": 4}
 
 
 class HisvError(RuntimeError):
@@ -49,6 +49,7 @@ _dp = C.POINTER(C.c_double)
 _SIGS = {
     "hs_device_count": [C.POINTER(C.c_int)],
     "hs_max_part_qubits": [C.c_int, C.c_int, C.POINTER(C.c_int)],
+    "hs_tune": [C.c_char_p, C.c_int],
     "hs_state_create": [C.c_int, C.c_int, _vp, C.POINTER(_vp)],
     "hs_state_wrap": [C.c_int, C.c_int, _vp, C.c_size_t, _vp, C.POINTER(_vp)],
     "hs_state_set_basis": [_vp, _u64],
@@ -66,11 +67,15 @@ _SIGS = {
     "hs_plan_part_layout": [_vp, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                             C.POINTER(C.c_int)],
     "hs_plan_part_descriptors": [_vp, C.c_int, C.c_int, _i32p, _i32p, C.c_int, _dp, C.c_int],
+    "hs_plan_part_source": [_vp, C.c_int, C.c_int, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)],
+    "hs_plan_specialize": [_vp, C.c_int],
+    "hs_plan_part_unitary": [_vp, C.c_int, C.POINTER(C.c_int), _dp],
     "hs_plan_destroy": [_vp],
     "hs_simulate": [_vp, _vp, C.c_int],
     "hs_simulate_gate_per_pass": [_vp, _vp],
     "hs_simulate_part": [_vp, _vp, C.c_int, C.c_int],
     "hs_read_amplitudes": [_vp, _u64, _u64, _dp],
+    "hs_read_amplitudes_at": [_vp, C.POINTER(_u64), _u64, _dp],
     "hs_probabilities": [_vp, _u64, _u64, _dp],
     "hs_norm": [_vp, _dp],
     "hs_sync": [_vp],
@@ -135,6 +140,10 @@ def hs_device_count() -> int:
     v = C.c_int()
     _call("hs_device_count", C.byref(v))
     return v.value
+
+
+def hs_tune(key: str, value: int) -> None:
+    _call("hs_tune", key.encode(), int(value))
 
 
 def hs_max_part_qubits(dtype: str = "c64", exec_mode: str = "part_lds") -> int:
@@ -238,6 +247,27 @@ class Plan:
               ops.ctypes.data_as(_dp), max(no, 1))
         return hdr, ent, ops[:no]
 
+    def part_source(self, part: int, dtype: str = "c64") -> str:
+        n = C.c_size_t()
+        _call("hs_plan_part_source", self.handle, int(part), DTYPES[dtype], None, 0, C.byref(n))
+        buf = C.create_string_buffer(n.value + 1)
+        _call("hs_plan_part_source", self.handle, int(part), DTYPES[dtype], buf, n.value + 1,
+              C.byref(n))
+        return buf.value.decode()
+
+    def part_unitary(self, part: int):
+        """(qubits, U) of a part's fused form; U is 2^w x 2^w complex128."""
+        w = C.c_int()
+        _call("hs_plan_part_unitary", self.handle, int(part), C.byref(w), None)
+        R = 1 << w.value
+        out = np.zeros(w.value + 2 * R * R, dtype=np.float64)
+        _call("hs_plan_part_unitary", self.handle, int(part), C.byref(w), out.ctypes.data_as(_dp))
+        qubits = [int(v) for v in out[:w.value]]
+        return qubits, out[w.value:].view(np.complex128).reshape(R, R)
+
+    def specialize(self, dtype: str = "c64") -> None:
+        _call("hs_plan_specialize", self.handle, DTYPES[dtype])
+
     def close(self):
         if self.handle:
             lib().hs_plan_destroy(self.handle)
@@ -299,6 +329,13 @@ class State:
         out = np.zeros(2 * max(count, 1), dtype=np.float64)
         _call("hs_read_amplitudes", self.handle, int(first), int(count), out.ctypes.data_as(_dp))
         return out[:2 * count].view(np.complex128)
+
+    def amplitudes_at(self, indices) -> np.ndarray:
+        idx = np.ascontiguousarray(np.asarray(indices, dtype=np.uint64))
+        out = np.zeros(2 * max(idx.size, 1), dtype=np.float64)
+        _call("hs_read_amplitudes_at", self.handle, idx.ctypes.data_as(C.POINTER(_u64)), idx.size,
+              out.ctypes.data_as(_dp))
+        return out[:2 * idx.size].view(np.complex128)
 
     def probabilities(self, first: int = 0, count: int | None = None) -> np.ndarray:
         if count is None:

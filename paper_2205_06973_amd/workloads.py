@@ -86,6 +86,21 @@ def layered_circuit(n: int, layers: int, seed: int):
     return gates
 
 
+def layered_product_block_circuit(n: int, layers: int, seed: int):
+    """Layered circuit whose CX matchings stay inside the even and the odd qubits."""
+    rng = _rng(seed)
+    gates = []
+    for _ in range(layers):
+        for q in range(n):
+            th, ph, la = (float(v) for v in rng.uniform(0.0, TWO_PI, size=3))
+            gates.append(("u3", q, -1, (th, ph, la)))
+        for block in (list(range(0, n, 2)), list(range(1, n, 2))):
+            perm = [block[int(i)] for i in rng.permutation(len(block))]
+            for i in range(0, len(perm) - 1, 2):
+                gates.append(("cx", perm[i], perm[i + 1], ()))
+    return gates
+
+
 def qft_circuit(n: int):
     gates = []
     for j in range(n - 1, -1, -1):

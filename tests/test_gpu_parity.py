@@ -67,7 +67,7 @@ ALL = sv.ONE_QUBIT + sv.TWO_QUBIT
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-@pytest.mark.parametrize("mode", ["part_lds", "gate_per_pass"])
+@pytest.mark.parametrize("mode", ["part_lds", "part_spec", "gate_per_pass"])
 def test_random12_k4(dtype, mode):
     """The small workload: 12 qubits, 200 gates of {H, X, RZ, CX}, k = 4."""
     n, gates = wl.random12(0)
@@ -81,30 +81,50 @@ def test_random12_k4(dtype, mode):
     (9, 5, "dfs"), (10, 7, "dfs"), (12, 12, "nat"), (13, 6, "dfs"), (14, 8, "dfs"),
     (16, 4, "nat"), (17, 7, "dfs"),
 ])
-def test_random_all_kinds(n, k, strategy, dtype):
+@pytest.mark.parametrize("mode", ["part_lds", "part_spec"])
+def test_random_all_kinds(n, k, strategy, dtype, mode):
     kinds = ALL if n >= 2 else sv.ONE_QUBIT
     gates = wl.random_circuit(n, 150, kinds, seed=100 + n + k)
     if k > hisv.hs_max_part_qubits(dtype) and k < n:
         pytest.skip("part wider than the kernel tile for this dtype")
-    got, _ = run_hip(n, gates, dtype, k, strategy, "part_lds", init=(n * 7919) % (1 << n))
+    got, _ = run_hip(n, gates, dtype, k, strategy, mode, init=(n * 7919) % (1 << n))
     check(got, sv.simulate(n, gates, (n * 7919) % (1 << n)), dtype)
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-def test_layered_20_k6(dtype):
+@pytest.mark.parametrize("mode", ["part_lds", "part_spec"])
+def test_layered_20_k6(dtype, mode):
     n, gates = wl.layered28(3, n=20, layers=8)
-    got, _ = run_hip(n, gates, dtype, 6, "dfs")
+    got, _ = run_hip(n, gates, dtype, 6, "dfs", mode)
     check(got, sv.simulate(n, gates), dtype)
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-def test_qft_closed_form_18(dtype):
+@pytest.mark.parametrize("mode,strategy", [("part_lds", "dfs"), ("part_spec", "dagp")])
+def test_qft_closed_form_18(dtype, mode, strategy):
     n = 18
     x = wl.random_basis_index(n, 5)
-    got, _ = run_hip(n, wl.qft_circuit(n), dtype, 7, "dfs", init=x)
+    got, _ = run_hip(n, wl.qft_circuit(n), dtype, 7, strategy, mode, init=x)
     y = np.arange(1 << n)
     want = np.exp(2j * np.pi * ((x * y) % (1 << n)) / (1 << n)) / math.sqrt(1 << n)
     check(got, want, dtype)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n,k,mode", [(9, 4, "part_fused"), (12, 5, "part_fused"),
+                                      (16, 3, "part_fused"), (17, 5, "part_fused"),
+                                      (15, 5, "auto"), (18, 7, "auto")])
+def test_fused_and_auto(n, k, mode, dtype):
+    gates = wl.random_circuit(n, 160, ALL, seed=300 + n + k)
+    got, _ = run_hip(n, gates, dtype, k, "dfs", mode, init=(n * 131) % (1 << n))
+    check(got, sv.simulate(n, gates, (n * 131) % (1 << n)), dtype)
+
+
+def test_fused_rejects_wide_part():
+    n, gates = wl.random34(1, n=14, num_gates=100)
+    with pytest.raises(hisv.HisvError) as e:
+        run_hip(n, gates, "c64", 7, "dfs", "part_fused")
+    assert e.value.code == "HS_E_UNSUPPORTED"
 
 
 def test_empty_circuit_leaves_state():

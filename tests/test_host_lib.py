@@ -221,6 +221,38 @@ def test_layout_report():
     assert hisv.hs_max_part_qubits("c128") >= 6
 
 
+# ---- fused path: the part unitary ------------------------------------------------
+
+@pytest.mark.parametrize("seed,k", [(0, 2), (1, 4), (2, 5), (3, 3)])
+def test_fused_unitary_matches_oracle_columns(seed, k):
+    n = 11
+    gates = wl.random_circuit(n, 80, sv.ONE_QUBIT + sv.TWO_QUBIT, seed)
+    plan = hisv.Plan.partition(hisv.Circuit(n, gates), k, "dfs", seed=seed, trials=8)
+    parts = plan.part_of_gate()
+    for p in range(plan.num_parts):
+        qubits, U = plan.part_unitary(p)
+        w = len(qubits)
+        assert w == max(4, bin(plan.part_info(p)[0]).count("1"))
+        assert qubits == sorted(qubits)
+        slot = {q: b for b, q in enumerate(qubits)}
+        pg = [g for g, x in zip(gates, parts) if x == p]
+        inner = [(g[0], slot[g[1]], slot[g[2]] if g[2] >= 0 else -1, g[3]) for g in pg]
+        for c in range(1 << w):  # column c = the part applied to basis state c
+            np.testing.assert_allclose(U[:, c], sv.simulate(w, inner, c), atol=1e-13)
+        np.testing.assert_allclose(U @ U.conj().T, np.eye(1 << w), atol=1e-12)
+
+
+def test_fused_unitary_rejects_wide_parts():
+    n, gates = wl.random34(1, n=12, num_gates=100)
+    plan = hisv.Plan.partition(hisv.Circuit(n, gates), 7, "dfs")
+    widths = [bin(plan.part_info(p)[0]).count("1") for p in range(plan.num_parts)]
+    wide = [p for p, w in enumerate(widths) if w > 5]
+    assert wide
+    with pytest.raises(hisv.HisvError) as e:
+        plan.part_unitary(wide[0])
+    assert e.value.code == "HS_E_UNSUPPORTED"
+
+
 # ---- dagP-style partitioner ----------------------------------------------------
 
 @pytest.mark.parametrize("name,make", CIRCUITS)
