@@ -43,7 +43,7 @@ def part_pass_bytes(n: int, dtype: str) -> int:
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("kernels.hip", "layout.h", "compile.cpp"):
+    for f in ("kernels.hip", "layout.h", "compile.cpp", "specialize.cpp"):
         with open(os.path.join(ROOT, "paper_2205_06973_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -107,6 +107,8 @@ def main() -> int:
     ap.add_argument("--serving", type=int, default=120, help="serving requests (0 = skip)")
     ap.add_argument("--serving-rate", type=float, default=40.0, help="arrivals per second")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--tune", action="append", default=[], metavar="KEY=VALUE",
+                    help="layout knob passed to hs_tune before the plan is compiled")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="also run the plain copy kernel on this many GiB (counter calibration)")
     args = ap.parse_args()
@@ -126,6 +128,9 @@ def main() -> int:
         return 1
     log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
 
+    for kv in args.tune:
+        key, val = kv.split("=")
+        hisv.hs_tune(key, int(val))
     n, G = args.n, args.gates
     _, gates = wl.random34(args.seed, n=n, num_gates=G)
     circ = hisv.Circuit(n, gates)
@@ -166,6 +171,10 @@ def main() -> int:
     gpu_ms = e0.elapsed_time(e1)
     log(f"[bench] timed {args.steps} steps: wall {wall:.3f} s, events {gpu_ms:.1f} ms")
     norm = st.norm()
+    if not abs(norm - 1.0) < 1e-3:
+        # a unitary circuit keeps the norm: anything else is a wrong result
+        log(f"[bench] ERROR: norm after the timed steps is {norm}, not 1")
+        return 3
 
     launches = args.steps * P
     avg_launch_s = gpu_ms / 1e3 / launches

@@ -191,14 +191,17 @@ hs_status hs_plan_part_info(hs_plan p, int part, uint64_t* qubit_mask, int* num_
  * from a lower to a higher part id.  HS_OK or HS_E_BAD_PARTITION. */
 hs_status hs_plan_validate(hs_plan p);
 
-/* Kernel-level layout of a part as compiled for `dtype` and PART_LDS: tile
- * width m (qubits per gathered sub-state, the part's qubits plus the lowest
- * other qubits as padding), register stages, LDS round trips per tile. */
-hs_status hs_plan_part_layout(hs_plan p, int part, hs_dtype dtype, int* tile_qubits,
+/* Kernel-level layout of a part as compiled for `dtype` and `exec`
+ * (PART_SPEC: the specialized kernels; any other mode: the interpreter
+ * kernel): tile width m (qubits per gathered sub-state, the part's qubits
+ * plus the lowest other qubits as padding), register stages, LDS round
+ * trips per tile. */
+hs_status hs_plan_part_layout(hs_plan p, int part, hs_dtype dtype, hs_exec exec, int* tile_qubits,
                               int* stages, int* lds_round_trips);
 
-/* Introspection of the compiled descriptors of a part (PART_LDS, `dtype`),
- * so tests can replay them on the host.  header[24] = {m, lb, wb, rb,
+/* Introspection of the compiled descriptors of a part (`dtype`; `exec` as
+ * for hs_plan_part_layout), so tests can replay them on the host.
+ * header[24] = {m, lb, wb, rb,
  * entries, LDS round trips, ops, log2(tiles), tq[16]} (tq = tile bit ->
  * qubit).  entries[20 * entries] (filled if entries_cap >= entries): per
  * entry pos[16] (coordinate bit -> tile bit; lane bits, then wave bits, then
@@ -207,7 +210,7 @@ hs_status hs_plan_part_layout(hs_plan p, int part, hs_dtype dtype, int* tile_qub
  * ops[11 * ops] (filled if ops_cap >= ops): kind, b0, b1, c[8] with kinds
  * 0 dense 2x2, 1 real 2x2, 2 diagonal, 3 diag(1, d), 4 X, 5 CX, 6 CZ,
  * 7 controlled phase, 8 SWAP. */
-hs_status hs_plan_part_descriptors(hs_plan p, int part, hs_dtype dtype, int32_t* header,
+hs_status hs_plan_part_descriptors(hs_plan p, int part, hs_dtype dtype, hs_exec exec, int32_t* header,
                                    int32_t* entries, int entries_cap, double* ops, int ops_cap);
 
 /* The HIP source of a part's specialized kernel (PART_SPEC) for `dtype`,

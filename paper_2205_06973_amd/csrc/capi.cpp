@@ -28,18 +28,22 @@ Plan::~Plan() {
     for (auto& kv : dev[d]) device_plan_free(kv.second);
 }
 
-// Tunable knobs (hs_tune), read when a plan is compiled.
+// Tunable knobs (hs_tune), read when a plan is compiled.  Register bits per
+// lane differ by path: the interpreter kernel keeps the sub-state plus
+// dispatch temporaries in 128 VGPRs (complex64: 2^4, complex128: 2^3
+// amplitudes), the specialized kernels hold the current and the prefetched
+// tile (complex64: 2^5, complex128: 2^3).
 static std::mutex g_tune_mu;
-static int g_rb[2] = {4, 3};
+static int g_rb[2][2] = {{4, 3}, {5, 3}};     // [specialized][dtype]
 static int g_contig = 6;
-static int g_min_run[2] = {6, 6};
+static int g_min_run[2][2] = {{4, 4}, {3, 3}};  // [specialized][dtype]
 
-CompileOptions default_options(hs_dtype dtype) {
+CompileOptions default_options(hs_dtype dtype, bool spec) {
   CompileOptions o;
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  o.rb = g_rb[dtype];
+  o.rb = g_rb[spec][dtype];
   o.contig = g_contig;
-  o.min_run = g_min_run[dtype];
+  o.min_run = g_min_run[spec][dtype];
   if (dtype == HS_C64) {
     o.swizzle = 4;
     o.max_m = 14;  // 2^14 x 8 B = 128 KiB of LDS
@@ -87,10 +91,7 @@ hs_status plan_compile_fused(Plan* p) {
   return HS_OK;
 }
 
-hs_status plan_compile(Plan* p, hs_dtype dtype) {
-  std::lock_guard<std::mutex> lk(p->mu);
-  if (p->compiled[dtype]) return HS_OK;
-  const CompileOptions opt = default_options(dtype);
+static hs_status compile_all(Plan* p, const CompileOptions& opt, std::vector<CompiledPart>* out) {
   std::vector<CompiledPart> comp(p->parts.size());
   std::vector<Gate> pg;
   for (size_t i = 0; i < p->parts.size(); ++i) {
@@ -98,9 +99,28 @@ hs_status plan_compile(Plan* p, hs_dtype dtype) {
     for (int gi : p->parts[i]) pg.push_back(p->gates[gi]);
     if (hs_status rc = compile_part(p->n, pg, opt, &comp[i])) return rc;
   }
-  p->comp[dtype].swap(comp);
+  out->swap(comp);
+  return HS_OK;
+}
+
+hs_status plan_compile(Plan* p, hs_dtype dtype) {
+  std::lock_guard<std::mutex> lk(p->mu);
+  if (p->compiled[dtype]) return HS_OK;
+  if (hs_status rc = compile_all(p, default_options(dtype, false), &p->comp[dtype])) return rc;
   p->compiled[dtype] = true;
   return HS_OK;
+}
+
+hs_status plan_compile_spec(Plan* p, hs_dtype dtype) {
+  std::lock_guard<std::mutex> lk(p->mu);
+  if (p->scompiled[dtype]) return HS_OK;
+  if (hs_status rc = compile_all(p, default_options(dtype, true), &p->scomp[dtype])) return rc;
+  p->scompiled[dtype] = true;
+  return HS_OK;
+}
+
+const std::vector<CompiledPart>& compiled_parts(const Plan* p, hs_dtype dtype, hs_exec exec) {
+  return exec == HS_EXEC_PART_SPEC ? p->scomp[dtype] : p->comp[dtype];
 }
 
 }  // namespace hisv
@@ -122,16 +142,21 @@ hs_status hs_device_count(int* out) {
 hs_status hs_tune(const char* key, int value) {
   CHECK_ARG(key, "null key");
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  const std::string k(key);
+  std::string k(key);
+  int spec = 0;
+  if (k.rfind("spec_", 0) == 0) {
+    spec = 1;
+    k = k.substr(5);
+  }
   if (k == "rb_c64" || k == "rb_c128") {
     CHECK_ARG(value >= 1 && value <= 5, "register bits must be 1..5");
-    g_rb[k == "rb_c64" ? 0 : 1] = value;
-  } else if (k == "contig") {
+    g_rb[spec][k == "rb_c64" ? 0 : 1] = value;
+  } else if (k == "contig" && !spec) {
     CHECK_ARG(value >= 0 && value <= 6, "contig must be 0..6");
     g_contig = value;
   } else if (k == "min_run_c64" || k == "min_run_c128") {
     CHECK_ARG(value >= 0 && value <= 6, "min_run must be 0..6");
-    g_min_run[k == "min_run_c64" ? 0 : 1] = value;
+    g_min_run[spec][k == "min_run_c64" ? 0 : 1] = value;
   } else {
     return fail(HS_E_ARG, "unknown tuning key '%s'", key);
   }
@@ -322,26 +347,30 @@ hs_status hs_plan_validate(hs_plan p) {
   return HS_OK;
 }
 
-hs_status hs_plan_part_layout(hs_plan p, int part, hs_dtype dtype, int* tile_qubits, int* stages,
-                              int* lds_round_trips) {
+static hs_status compile_for(Plan* p, hs_dtype dtype, hs_exec exec) {
+  return exec == HS_EXEC_PART_SPEC ? plan_compile_spec(p, dtype) : plan_compile(p, dtype);
+}
+
+hs_status hs_plan_part_layout(hs_plan p, int part, hs_dtype dtype, hs_exec exec, int* tile_qubits,
+                              int* stages, int* lds_round_trips) {
   CHECK_ARG(p, "null plan");
   CHECK_ARG(dtype == HS_C64 || dtype == HS_C128, "bad dtype");
   CHECK_ARG(part >= 0 && part < (int)p->parts.size(), "part %d out of range", part);
-  if (hs_status rc = plan_compile(p, dtype)) return rc;
-  const CompiledPart& cp = p->comp[dtype][part];
+  if (hs_status rc = compile_for(p, dtype, exec)) return rc;
+  const CompiledPart& cp = compiled_parts(p, dtype, exec)[part];
   if (tile_qubits) *tile_qubits = cp.desc.m;
   if (stages) *stages = cp.desc.n_stages - 2;
   if (lds_round_trips) *lds_round_trips = cp.lds_round_trips;
   return HS_OK;
 }
 
-hs_status hs_plan_part_descriptors(hs_plan p, int part, hs_dtype dtype, int32_t* header,
+hs_status hs_plan_part_descriptors(hs_plan p, int part, hs_dtype dtype, hs_exec exec, int32_t* header,
                                    int32_t* entries, int entries_cap, double* ops, int ops_cap) {
   CHECK_ARG(p && header, "null argument");
   CHECK_ARG(dtype == HS_C64 || dtype == HS_C128, "bad dtype");
   CHECK_ARG(part >= 0 && part < (int)p->parts.size(), "part %d out of range", part);
-  if (hs_status rc = plan_compile(p, dtype)) return rc;
-  const CompiledPart& cp = p->comp[dtype][part];
+  if (hs_status rc = compile_for(p, dtype, exec)) return rc;
+  const CompiledPart& cp = compiled_parts(p, dtype, exec)[part];
   const PartDesc& d = cp.desc;
   header[0] = d.m;
   header[1] = d.lb;
@@ -377,12 +406,12 @@ hs_status hs_plan_part_descriptors(hs_plan p, int part, hs_dtype dtype, int32_t*
 
 static hs_status ensure_spec(Plan* p, hs_dtype dtype, int device,
                              std::vector<std::shared_ptr<SpecKernel>>** out) {
-  if (hs_status rc = plan_compile(p, dtype)) return rc;
+  if (hs_status rc = plan_compile_spec(p, dtype)) return rc;
   std::lock_guard<std::mutex> lk(p->mu);
   auto it = p->spec[dtype].find(device);
   if (it == p->spec[dtype].end()) {
     std::vector<std::shared_ptr<SpecKernel>> ks;
-    if (hs_status rc = specialize_plan(p->comp[dtype], dtype, device, &ks)) return rc;
+    if (hs_status rc = specialize_plan(p->scomp[dtype], dtype, device, &ks)) return rc;
     it = p->spec[dtype].emplace(device, std::move(ks)).first;
   }
   *out = &it->second;
@@ -393,8 +422,8 @@ hs_status hs_plan_part_source(hs_plan p, int part, hs_dtype dtype, char* buf, si
   CHECK_ARG(p, "null plan");
   CHECK_ARG(dtype == HS_C64 || dtype == HS_C128, "bad dtype");
   CHECK_ARG(part >= 0 && part < (int)p->parts.size(), "part %d out of range", part);
-  if (hs_status rc = plan_compile(p, dtype)) return rc;
-  const std::string src = specialize_part_source(p->comp[dtype][part], dtype, "part_pass_spec");
+  if (hs_status rc = plan_compile_spec(p, dtype)) return rc;
+  const std::string src = specialize_part_source(p->scomp[dtype][part], dtype, "part_pass_spec");
   if (len) *len = src.size();
   if (!buf) return HS_OK;
   CHECK_ARG(cap > src.size(), "buffer of %zu bytes is too small", cap);
@@ -416,7 +445,7 @@ static hs_status run_spec_parts(hs_state s, Plan* p, int first, int last) {
   if (hipSetDevice(s->device) != hipSuccess) return fail(HS_E_HIP, "hipSetDevice failed");
   if (hs_status rc = ensure_spec(p, s->dtype, s->device, &ks)) return rc;
   for (int i = first; i < last; ++i)
-    if (hs_status rc = launch_specialized(*(*ks)[i], s->ptr, p->comp[s->dtype][i].desc.tiles, s->stream))
+    if (hs_status rc = launch_specialized(*(*ks)[i], s->ptr, p->scomp[s->dtype][i].desc.tiles, s->stream))
       return rc;
   return HS_OK;
 }

@@ -120,7 +120,9 @@ struct Plan {
   // per dtype: compiled descriptors + uploaded copy (per device)
   std::mutex mu;
   bool compiled[2] = {false, false};
-  std::vector<CompiledPart> comp[2];
+  std::vector<CompiledPart> comp[2];    // for the interpreter kernel
+  bool scompiled[2] = {false, false};
+  std::vector<CompiledPart> scomp[2];   // for the specialized kernels
   std::map<int, DevicePlan*> dev[2];
   std::map<int, std::vector<std::shared_ptr<SpecKernel>>> spec[2];  // per device
   bool fused_built = false;
@@ -130,8 +132,11 @@ struct Plan {
 
 hs_status plan_build(int n, const std::vector<Gate>& gates, int k,
                      const std::vector<int32_t>& part_of_gate, Plan* p);
-CompileOptions default_options(hs_dtype dtype);
+CompileOptions default_options(hs_dtype dtype, bool spec = false);
 hs_status plan_compile(Plan* p, hs_dtype dtype);
+hs_status plan_compile_spec(Plan* p, hs_dtype dtype);
+// the compiled parts of a path (PART_SPEC -> specialized, else interpreter)
+const std::vector<CompiledPart>& compiled_parts(const Plan* p, hs_dtype dtype, hs_exec exec);
 
 // ---- state --------------------------------------------------------------------
 struct State {

@@ -231,15 +231,14 @@ __device__ __forceinline__ uint32_t thread_tile(const StageDesc& e, int nthr_bit
 
 // Move the tile between HBM and registers in layout `e`.  The address of
 // register j is (uniform part: tile base + wave bits + register bits) plus
-// the lane's byte offset, so every access is an SGPR base + one 32-bit VGPR
-// offset.  Lane bits of the load/store layouts are the tile's lowest
-// qubits, so the lane offset is small.
+// the lane's offset.  The lane offset is 64-bit: a gather/scatter layout's
+// lanes start with the lowest qubits but may also carry high ones.
 template <typename T, int RB, bool STORE>
 __device__ __forceinline__ void tile_io(cplx<T>* __restrict__ st, RegV<T, RB>& a, const StageDesc& e,
                                         const int8_t* tq, int lb, int wb, uint64_t tbase,
                                         uint32_t lane, uint32_t wave, bool active) {
   const uint64_t uni = tbase + coord_global(e, tq, lb, lb + wb, wave);
-  const uint32_t lane_bytes = (uint32_t)coord_global(e, tq, 0, lb, lane) * (uint32_t)sizeof(cplx<T>);
+  const uint64_t lane_bytes = coord_global(e, tq, 0, lb, lane) * sizeof(cplx<T>);
   uint64_t ro[RB > 0 ? RB : 1];
 #pragma unroll
   for (int r = 0; r < RB; ++r) ro[r] = uint64_t(1) << tq[e.pos[lb + wb + r]];

@@ -158,9 +158,11 @@ void emit_op(Emit& E, const HostOp& op) {
 void emit_thread_offsets(Emit& E, const StageDesc& e, const PartDesc& d, const char* lane_var,
                          const char* wave_var, const char* out_lane, const char* out_wave) {
   auto& o = E.o;
-  o << "    const unsigned " << out_lane << " = 0u";
+  // 64-bit: lanes may carry any tile qubit (up to n - 1)
+  o << "    const unsigned long long " << out_lane << " = 0ull";
   for (int c = 0; c < d.lb; ++c)
-    o << " | (((" << lane_var << " >> " << c << ") & 1u) << " << (int)d.tq[e.pos[c]] << ")";
+    o << " | ((unsigned long long)((" << lane_var << " >> " << c << ") & 1u) << "
+      << (int)d.tq[e.pos[c]] << ")";
   o << ";\n    const unsigned long long " << out_wave << " = 0ull";
   for (int c = 0; c < d.wb; ++c)
     o << " | ((unsigned long long)((" << wave_var << " >> " << c << ") & 1u) << "

@@ -64,9 +64,10 @@ _SIGS = {
     "hs_plan_part_of_gate": [_vp, _i32p],
     "hs_plan_part_info": [_vp, C.c_int, C.POINTER(_u64), C.POINTER(C.c_int)],
     "hs_plan_validate": [_vp],
-    "hs_plan_part_layout": [_vp, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
-                            C.POINTER(C.c_int)],
-    "hs_plan_part_descriptors": [_vp, C.c_int, C.c_int, _i32p, _i32p, C.c_int, _dp, C.c_int],
+    "hs_plan_part_layout": [_vp, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int),
+                            C.POINTER(C.c_int), C.POINTER(C.c_int)],
+    "hs_plan_part_descriptors": [_vp, C.c_int, C.c_int, C.c_int, _i32p, _i32p, C.c_int, _dp,
+                                 C.c_int],
     "hs_plan_part_source": [_vp, C.c_int, C.c_int, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)],
     "hs_plan_specialize": [_vp, C.c_int],
     "hs_plan_part_unitary": [_vp, C.c_int, C.POINTER(C.c_int), _dp],
@@ -228,21 +229,22 @@ class Plan:
     def validate(self) -> None:
         _call("hs_plan_validate", self.handle)
 
-    def part_layout(self, part: int, dtype: str = "c64") -> tuple[int, int, int]:
+    def part_layout(self, part: int, dtype: str = "c64", mode: str = "part_lds"):
+        """(tile qubits, register stages, LDS round trips) of a compiled part."""
         m, s, t = C.c_int(), C.c_int(), C.c_int()
-        _call("hs_plan_part_layout", self.handle, int(part), DTYPES[dtype], C.byref(m),
-              C.byref(s), C.byref(t))
+        _call("hs_plan_part_layout", self.handle, int(part), DTYPES[dtype], EXEC[mode],
+              C.byref(m), C.byref(s), C.byref(t))
         return m.value, s.value, t.value
 
-    def part_descriptors(self, part: int, dtype: str = "c64"):
+    def part_descriptors(self, part: int, dtype: str = "c64", mode: str = "part_lds"):
         """(header[24], entries[E, 20], ops[O, 11]) of a compiled part."""
         hdr = np.zeros(24, dtype=np.int32)
-        _call("hs_plan_part_descriptors", self.handle, int(part), DTYPES[dtype],
+        _call("hs_plan_part_descriptors", self.handle, int(part), DTYPES[dtype], EXEC[mode],
               hdr.ctypes.data_as(_i32p), None, 0, None, 0)
         ne, no = int(hdr[4]), int(hdr[6])
         ent = np.zeros((ne, 20), dtype=np.int32)
         ops = np.zeros((max(no, 1), 11), dtype=np.float64)
-        _call("hs_plan_part_descriptors", self.handle, int(part), DTYPES[dtype],
+        _call("hs_plan_part_descriptors", self.handle, int(part), DTYPES[dtype], EXEC[mode],
               hdr.ctypes.data_as(_i32p), ent.ctypes.data_as(_i32p), ne,
               ops.ctypes.data_as(_dp), max(no, 1))
         return hdr, ent, ops[:no]

@@ -26,7 +26,7 @@ PROFILES = os.path.join(ROOT, "profiles")
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("kernels.hip", "layout.h", "compile.cpp"):
+    for f in ("kernels.hip", "layout.h", "compile.cpp", "specialize.cpp"):
         with open(os.path.join(ROOT, "paper_2205_06973_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -34,8 +34,9 @@ def kernel_source_hash() -> str:
 
 def _short(name: str) -> str:
     base = name.split("(")[0]
-    for tag in ("part_pass_kernel", "gate_pass_1q", "gate_pass_2q", "set_basis_kernel",
-                "norm_partial", "norm_final", "readout_kernel", "copy_probe_kernel"):
+    for tag in ("part_pass_spec", "part_pass_kernel", "fused_pass_kernel", "gate_pass_1q",
+                "gate_pass_2q", "set_basis_kernel", "norm_partial", "norm_final", "readout_kernel",
+                "gather_kernel", "copy_probe_kernel"):
         if tag in base:
             tmpl = base[base.find(tag) + len(tag):]
             return tag + tmpl[:24]
@@ -72,8 +73,8 @@ def traffic(fetch_csv: str, write_csv: str, key: str, command: str, copy_bytes: 
     cw = [v for k, v in write.items() if k.startswith("copy_probe_kernel")][0]
     f_scale = copy_bytes / (sum(cf) / len(cf) * 1024.0)
     w_scale = copy_bytes / (sum(cw) / len(cw) * 1024.0)
-    pf = [v for k, vs in fetch.items() if k.startswith("part_pass_kernel") for v in vs]
-    pw = [v for k, vs in write.items() if k.startswith("part_pass_kernel") for v in vs]
+    pf = [v for k, vs in fetch.items() if k.startswith("part_pass") for v in vs]
+    pw = [v for k, vs in write.items() if k.startswith("part_pass") for v in vs]
     fb = sum(pf) / len(pf) * 1024.0 * f_scale
     wb = sum(pw) / len(pw) * 1024.0 * w_scale
     rec = {"bytes_per_launch": fb + wb, "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,

@@ -105,10 +105,10 @@ def replay_part(psi: np.ndarray, n: int, hdr, ent, ops) -> dict:
             "store_lane_qubits": [tq[t] for t in lanes_store]}
 
 
-def replay_plan(plan, n: int, psi0: np.ndarray, dtype: str = "c64"):
+def replay_plan(plan, n: int, psi0: np.ndarray, dtype: str = "c64", mode: str = "part_lds"):
     psi = np.array(psi0, dtype=np.complex128, copy=True)
     facts = []
     for p in range(plan.num_parts):
-        hdr, ent, ops = plan.part_descriptors(p, dtype)
+        hdr, ent, ops = plan.part_descriptors(p, dtype, mode)
         facts.append(replay_part(psi, n, hdr, ent, ops))
     return psi, facts

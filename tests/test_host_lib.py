@@ -181,10 +181,31 @@ def test_replay_of_compiled_parts_matches_oracle(n, k, strategy, dtype):
         pad = sorted(set(f["tq"]) - set(S))
         others = [q for q in range(n) if q not in S]
         assert pad == others[:len(pad)], "padding takes the lowest other qubits"
-        assert f["load_lane_qubits"] == list(range(f["lb"]))
-        assert f["store_lane_qubits"] == list(range(f["lb"]))
+        # gather/scatter lanes cover at least qubits 0..3 (contiguous runs)
+        run = min(4, f["lb"])
+        assert f["load_lane_qubits"][:run] == list(range(run))
+        assert f["store_lane_qubits"][:run] == list(range(run))
         assert f["m"] == f["lb"] + f["wb"] + f["rb"] <= n
         assert len(parts) == len(gates)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("n,k,strategy", [(7, 3, "dfs"), (12, 8, "dfs"), (14, 7, "dagp"),
+                                          (13, 13, "nat"), (16, 5, "dfs")])
+def test_replay_specialized_layouts(n, k, strategy, dtype):
+    """The specialized kernels' descriptors (more register bits, stage layouts
+    loaded directly when their lanes still cover qubits 0..2)."""
+    gates = wl.random_circuit(n, 150, sv.ONE_QUBIT + sv.TWO_QUBIT, seed=7 * n + k)
+    plan = hisv.Plan.partition(hisv.Circuit(n, gates), k, strategy, seed=1, trials=8)
+    psi0 = _random_state(n, k)
+    try:
+        got, facts = replay_plan(plan, n, psi0, dtype, "part_spec")
+    except hisv.HisvError as e:
+        assert e.code == "HS_E_UNSUPPORTED"
+        return
+    np.testing.assert_allclose(got, sv.simulate(n, gates, psi0), atol=1e-12, rtol=0)
+    for f in facts:
+        assert f["load_lane_qubits"][:min(3, f["lb"])] == list(range(min(3, f["lb"])))
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
