@@ -127,7 +127,13 @@ hs_status hs_device_count(int* out);
  * (0..6); "min_run_c64" / "min_run_c128" = gather and scatter straight in a
  * stage's layout when its lanes still cover qubits 0..min_run-1, instead of
  * re-laying out through LDS (0..6; 6 = only fully contiguous 64-amplitude
- * runs).  HS_E_ARG for an unknown key or value. */
+ * runs).  Launch shape of the part kernels: "xcd" (0/1) = each of the 8
+ * XCDs sweeps one contiguous eighth of the tiles; "grid" = 0 for one
+ * workgroup per tile, g in 1..64 for a persistent grid of g x the resident
+ * workgroups per CU; "prefetch" (0/1) = a persistent grid keeps the next
+ * tile's loads in flight.  A "spec_" prefix on any key sets it for the
+ * specialized kernels (PART_SPEC) instead of the interpreter kernel.
+ * HS_E_ARG for an unknown key or value. */
 hs_status hs_tune(const char* key, int value);
 
 /* Largest part width k that hs_simulate with PART_LDS / PART_FUSED accepts

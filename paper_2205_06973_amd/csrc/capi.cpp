@@ -29,14 +29,16 @@ Plan::~Plan() {
 }
 
 // Tunable knobs (hs_tune), read when a plan is compiled.  Register bits per
-// lane differ by path: the interpreter kernel keeps the sub-state plus
-// dispatch temporaries in 128 VGPRs (complex64: 2^4, complex128: 2^3
-// amplitudes), the specialized kernels hold the current and the prefetched
-// tile (complex64: 2^5, complex128: 2^3).
+// lane: the interpreter kernel keeps the sub-state plus dispatch temporaries
+// and the prefetched next tile in 128 VGPRs (complex64: 2^4, complex128: 2^3
+// amplitudes); the specialized kernels, one workgroup per tile, measured
+// best at the same widths.
 static std::mutex g_tune_mu;
-static int g_rb[2][2] = {{4, 3}, {5, 3}};     // [specialized][dtype]
+static int g_rb[2][2] = {{4, 3}, {4, 3}};     // [specialized][dtype]
 static int g_contig = 6;
 static int g_min_run[2][2] = {{4, 4}, {3, 3}};  // [specialized][dtype]
+// [specialized]: both paths default to one workgroup per tile, XCD-contiguous
+static LaunchShape g_launch[2];
 
 CompileOptions default_options(hs_dtype dtype, bool spec) {
   CompileOptions o;
@@ -44,6 +46,7 @@ CompileOptions default_options(hs_dtype dtype, bool spec) {
   o.rb = g_rb[spec][dtype];
   o.contig = g_contig;
   o.min_run = g_min_run[spec][dtype];
+  o.launch = g_launch[spec];
   if (dtype == HS_C64) {
     o.swizzle = 4;
     o.max_m = 14;  // 2^14 x 8 B = 128 KiB of LDS
@@ -98,6 +101,7 @@ static hs_status compile_all(Plan* p, const CompileOptions& opt, std::vector<Com
     pg.clear();
     for (int gi : p->parts[i]) pg.push_back(p->gates[gi]);
     if (hs_status rc = compile_part(p->n, pg, opt, &comp[i])) return rc;
+    comp[i].launch = opt.launch;
   }
   out->swap(comp);
   return HS_OK;
@@ -149,7 +153,10 @@ hs_status hs_tune(const char* key, int value) {
     k = k.substr(5);
   }
   if (k == "rb_c64" || k == "rb_c128") {
-    CHECK_ARG(value >= 1 && value <= 5, "register bits must be 1..5");
+    // the interpreter kernel (<= 1024 threads, 128 VGPRs a lane) spills beyond
+    // 2^4 complex64 / 2^3 complex128 amplitudes a lane
+    const int hi = spec ? 5 : (k == "rb_c64" ? 4 : 3);
+    CHECK_ARG(value >= 1 && value <= hi, "register bits must be 1..%d", hi);
     g_rb[spec][k == "rb_c64" ? 0 : 1] = value;
   } else if (k == "contig" && !spec) {
     CHECK_ARG(value >= 0 && value <= 6, "contig must be 0..6");
@@ -157,6 +164,12 @@ hs_status hs_tune(const char* key, int value) {
   } else if (k == "min_run_c64" || k == "min_run_c128") {
     CHECK_ARG(value >= 0 && value <= 6, "min_run must be 0..6");
     g_min_run[spec][k == "min_run_c64" ? 0 : 1] = value;
+  } else if (k == "xcd" || (k == "prefetch" && spec)) {
+    CHECK_ARG(value == 0 || value == 1, "%s must be 0 or 1", k.c_str());
+    (k == "xcd" ? g_launch[spec].xcd : g_launch[spec].prefetch) = value != 0;
+  } else if (k == "grid") {
+    CHECK_ARG(value >= 0 && value <= 64, "grid must be 0 (one workgroup per tile) or 1..64");
+    g_launch[spec].per_cu = value;
   } else {
     return fail(HS_E_ARG, "unknown tuning key '%s'", key);
   }
@@ -445,7 +458,7 @@ static hs_status run_spec_parts(hs_state s, Plan* p, int first, int last) {
   if (hipSetDevice(s->device) != hipSuccess) return fail(HS_E_HIP, "hipSetDevice failed");
   if (hs_status rc = ensure_spec(p, s->dtype, s->device, &ks)) return rc;
   for (int i = first; i < last; ++i)
-    if (hs_status rc = launch_specialized(*(*ks)[i], s->ptr, p->scomp[s->dtype][i].desc.tiles, s->stream))
+    if (hs_status rc = launch_specialized(*(*ks)[i], p->scomp[s->dtype][i], s->ptr, s->stream))
       return rc;
   return HS_OK;
 }

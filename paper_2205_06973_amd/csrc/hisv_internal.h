@@ -68,12 +68,24 @@ struct HostOp {
   double c[8];
 };
 
+// How a part-pass grid walks the tiles of a part.  Workgroup b of a launch
+// runs on XCD b % 8 and each XCD has its own L2; the hardware sustains more
+// HBM bandwidth when every XCD sweeps one contiguous run of tiles than when
+// consecutive tiles are dealt round-robin over the XCDs.
+struct LaunchShape {
+  bool xcd = true;        // XCD x takes tiles [x T/8, (x+1) T/8)
+  int per_cu = 0;         // 0: one workgroup per tile; g > 0: a persistent grid of
+                          // g x (resident workgroups per CU) x CUs
+  bool prefetch = false;  // persistent grid: keep the next tile's loads in flight
+};
+
 struct CompiledPart {
   PartDesc desc;                    // stage_off relative to this part's stages
   std::vector<StageDesc> stages;    // load, stages..., store (op ranges relative)
   std::vector<HostOp> ops;
   int rb_kernel = 0;
   int lds_round_trips = 0;
+  LaunchShape launch;
 };
 
 // A part applied as one dense unitary on matrix cores (the fused path):
@@ -98,6 +110,7 @@ struct CompileOptions {
   int max_m = 14;    // widest tile whose 2^m amplitudes fit the LDS
   int min_run = 6;   // load/store straight in a stage layout whose lanes cover
                      // at least qubits 0..min_run-1 (runs of 2^min_run amplitudes)
+  LaunchShape launch;
 };
 
 // Compile one part (its gates in circuit order) on an n-qubit state.
@@ -172,6 +185,6 @@ hs_status dev_sync(State* s);
 std::string specialize_part_source(const CompiledPart& cp, hs_dtype dt, const std::string& name);
 hs_status specialize_plan(const std::vector<CompiledPart>& parts, hs_dtype dt, int device,
                           std::vector<std::shared_ptr<SpecKernel>>* out);
-hs_status launch_specialized(const SpecKernel& k, void* state, uint64_t tiles, void* stream);
+hs_status launch_specialized(const SpecKernel& k, const CompiledPart& cp, void* state, void* stream);
 
 }  // namespace hisv

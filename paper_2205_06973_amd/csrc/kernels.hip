@@ -270,7 +270,7 @@ __device__ __forceinline__ void tile_io(cplx<T>* __restrict__ st, RegV<T, RB>& a
 template <typename T, int RB>
 __global__ void __launch_bounds__(1024)
 part_pass_kernel(cplx<T>* __restrict__ st, const PartDesc* __restrict__ pd,
-                 const StageDesc* __restrict__ sd, const OpDesc<T>* __restrict__ ops) {
+                 const StageDesc* __restrict__ sd, const OpDesc<T>* __restrict__ ops, uint32_t xcd) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
   constexpr int NR = 1 << RB;
@@ -284,19 +284,22 @@ part_pass_kernel(cplx<T>* __restrict__ st, const PartDesc* __restrict__ pd,
   const uint32_t thr = lane | (wave << lb);
   const bool active = lane < (1 << lb);
 
-  // Software pipeline: the loads of a workgroup's next tile are issued
-  // before the current tile is processed, so HBM traffic overlaps the
-  // register and LDS work of the stages.
-  RegV<T, RB> a, nxt;
-  uint64_t tile = blockIdx.x;
-  if (tile < tiles)
-    tile_io<T, RB, false>(st, a, sd[0], pd->tq, lb, wb, tile_base(tile, pd->tq, m), lane, wave, active);
-  for (; tile < tiles; tile += gridDim.x) {
+  // Tiles of this workgroup: with xcd set (grid and tile count multiples of
+  // 8), XCD x = blockIdx % 8 sweeps the contiguous run [x T/8, (x+1) T/8).
+  uint64_t tile = blockIdx.x, step = gridDim.x, end = tiles;
+  if (xcd) {
+    const uint64_t per = tiles >> 3;
+    const uint32_t x = blockIdx.x & 7u;
+    tile = x * per + (blockIdx.x >> 3);
+    step = gridDim.x >> 3;
+    end = (x + 1) * per;
+  }
+  // (no software prefetch of the next tile: with up to 1024 threads a lane
+  // has 128 VGPRs, and a second tile's registers would spill)
+  RegV<T, RB> a;
+  for (; tile < end; tile += step) {
     const uint64_t tbase = tile_base(tile, pd->tq, m);
-    const uint64_t next = tile + gridDim.x;
-    if (next < tiles)
-      tile_io<T, RB, false>(st, nxt, sd[0], pd->tq, lb, wb, tile_base(next, pd->tq, m), lane, wave,
-                            active);
+    tile_io<T, RB, false>(st, a, sd[0], pd->tq, lb, wb, tbase, lane, wave, active);
     // ---- execute: stages, re-laid out through LDS where the layout changes
     for (int s = 1; s < ne; ++s) {
       const StageDesc& e = sd[s];
@@ -340,7 +343,6 @@ part_pass_kernel(cplx<T>* __restrict__ st, const PartDesc* __restrict__ pd,
     }
     // ---- scatter (last entry is the store layout)
     tile_io<T, RB, true>(st, a, sd[ne - 1], pd->tq, lb, wb, tbase, lane, wave, active);
-    a = nxt;
   }
 }
 
@@ -699,7 +701,8 @@ struct DevicePlan {
   void* ops = nullptr;
   std::vector<PartDesc> h_parts;     // host copy (absolute offsets)
   std::vector<int> rb;               // register bits of the kernel per part
-  std::vector<unsigned> grid;        // persistent grid per part
+  std::vector<unsigned> grid;        // grid per part
+  std::vector<uint8_t> xcd;          // XCD-contiguous tile runs
   // fused path (uploaded on first use)
   bool fused_ready = false;
   FusedDesc* fparts = nullptr;
@@ -720,32 +723,41 @@ void device_plan_free(DevicePlan* d) {
 }
 
 template <typename T, int RB>
-static hs_status occupancy_grid(int dev, int block, size_t lds, uint64_t tiles, unsigned* grid) {
-  DevInfo d;
-  if (hs_status rc = device_info(dev, &d)) return rc;
+static hs_status resident_per_cu(int block, size_t lds, int* per_cu) {
   if (lds > 65536)
     HIP_TRY(hipFuncSetAttribute((const void*)part_pass_kernel<T, RB>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  int per_cu = 0;
-  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, part_pass_kernel<T, RB>, block, lds));
-  if (per_cu < 1) return fail(HS_E_UNSUPPORTED, "part kernel cannot be resident (block %d, lds %zu)",
-                              block, lds);
-  const uint64_t cap = (uint64_t)per_cu * d.cus;
-  *grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(tiles, cap));
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, part_pass_kernel<T, RB>, block, lds));
+  if (*per_cu < 1) return fail(HS_E_UNSUPPORTED, "part kernel cannot be resident (block %d, lds %zu)",
+                               block, lds);
   return HS_OK;
 }
 
 template <typename T>
-static hs_status occupancy_grid_rb(int rb, int dev, int block, size_t lds, uint64_t tiles,
-                                   unsigned* grid) {
+static hs_status resident_rb(int rb, int block, size_t lds, int* per_cu) {
   switch (rb) {
-    case 1: return occupancy_grid<T, 1>(dev, block, lds, tiles, grid);
-    case 2: return occupancy_grid<T, 2>(dev, block, lds, tiles, grid);
-    case 3: return occupancy_grid<T, 3>(dev, block, lds, tiles, grid);
-    case 4: return occupancy_grid<T, 4>(dev, block, lds, tiles, grid);
-    case 5: return occupancy_grid<T, 5>(dev, block, lds, tiles, grid);
+    case 1: return resident_per_cu<T, 1>(block, lds, per_cu);
+    case 2: return resident_per_cu<T, 2>(block, lds, per_cu);
+    case 3: return resident_per_cu<T, 3>(block, lds, per_cu);
+    case 4: return resident_per_cu<T, 4>(block, lds, per_cu);
     default: return fail(HS_E_UNSUPPORTED, "no kernel with %d register bits", rb);
   }
+}
+
+// Grid of one part-pass launch for launch shape `ls`: one workgroup per tile,
+// or a persistent grid sized by occupancy; XCD-contiguous tile runs need the
+// grid and the tile count to be multiples of 8.
+static void part_grid(const LaunchShape& ls, uint64_t tiles, int block, int per_cu, int cus,
+                      unsigned* grid, uint8_t* xcd) {
+  uint64_t g = tiles;
+  if (ls.per_cu > 0) g = std::min<uint64_t>(tiles, (uint64_t)ls.per_cu * per_cu * cus);
+  g = std::max<uint64_t>(1, std::min<uint64_t>(g, (uint64_t(1) << 31) / (uint64_t)block));
+  *xcd = 0;
+  if (ls.xcd && tiles % 8 == 0 && g >= 8) {
+    g &= ~uint64_t(7);
+    *xcd = 1;
+  }
+  *grid = (unsigned)g;
 }
 
 template <typename T>
@@ -755,6 +767,8 @@ static hs_status upload_plan(Plan* p, int dtype, int dev, DevicePlan** out) {
   std::vector<OpDesc<T>> ops;
   auto dp = std::make_unique<DevicePlan>();
   dp->device = dev;
+  DevInfo dinfo;
+  if (hs_status rc = device_info(dev, &dinfo)) return rc;
   for (const CompiledPart& cp : p->comp[dtype]) {
     PartDesc d = cp.desc;
     d.stage_off = (int)stages.size();
@@ -775,11 +789,14 @@ static hs_status upload_plan(Plan* p, int dtype, int dev, DevicePlan** out) {
     }
     parts.push_back(d);
     dp->rb.push_back(cp.rb_kernel);
-    unsigned g = 1;
     const int block = 64 << d.wb;
-    if (hs_status rc = occupancy_grid_rb<T>(cp.rb_kernel, dev, block, (size_t)d.lds_bytes, d.tiles, &g))
-      return rc;
+    int per_cu = 0;
+    if (hs_status rc = resident_rb<T>(cp.rb_kernel, block, (size_t)d.lds_bytes, &per_cu)) return rc;
+    unsigned g = 1;
+    uint8_t x = 0;
+    part_grid(cp.launch, d.tiles, block, per_cu, dinfo.cus, &g, &x);
     dp->grid.push_back(g);
+    dp->xcd.push_back(x);
   }
   if (ops.empty()) ops.push_back(OpDesc<T>{});
   HIP_TRY(hipMalloc(&dp->parts, parts.size() * sizeof(PartDesc)));
@@ -804,14 +821,19 @@ static hs_status launch_part(State* s, DevicePlan* dp, int part) {
   const StageDesc* sd = dp->stages + d.stage_off;
   const OpDesc<T>* ops = (const OpDesc<T>*)dp->ops;
   hipStream_t str = stream_of(s);
+  const uint32_t xcd = dp->xcd[part];
+#define HS_LAUNCH_PART(RB_)                                                                     \
+  hipLaunchKernelGGL((part_pass_kernel<T, RB_>), dim3(grid), dim3(block), lds, str, st, pd, sd, ops, \
+                     xcd);                                                                      \
+  break;
   switch (dp->rb[part]) {
-    case 1: hipLaunchKernelGGL((part_pass_kernel<T, 1>), dim3(grid), dim3(block), lds, str, st, pd, sd, ops); break;
-    case 2: hipLaunchKernelGGL((part_pass_kernel<T, 2>), dim3(grid), dim3(block), lds, str, st, pd, sd, ops); break;
-    case 3: hipLaunchKernelGGL((part_pass_kernel<T, 3>), dim3(grid), dim3(block), lds, str, st, pd, sd, ops); break;
-    case 4: hipLaunchKernelGGL((part_pass_kernel<T, 4>), dim3(grid), dim3(block), lds, str, st, pd, sd, ops); break;
-    case 5: hipLaunchKernelGGL((part_pass_kernel<T, 5>), dim3(grid), dim3(block), lds, str, st, pd, sd, ops); break;
+    case 1: HS_LAUNCH_PART(1)
+    case 2: HS_LAUNCH_PART(2)
+    case 3: HS_LAUNCH_PART(3)
+    case 4: HS_LAUNCH_PART(4)
     default: return fail(HS_E_UNSUPPORTED, "no kernel with %d register bits", dp->rb[part]);
   }
+#undef HS_LAUNCH_PART
   HIP_TRY(hipGetLastError());
   return HS_OK;
 }

@@ -7,9 +7,10 @@
 // their coefficients) into straight-line HIP source -- register indices, LDS
 // offsets and coefficients become compile-time constants -- compiles it with
 // hipRTC for gfx950 and caches the resulting kernel.  The computation is the
-// same Alg. 1 sweep (gather the tile, run the stages, scatter it back); the
-// generated kernel also keeps the loads of the next tile in flight while the
-// current tile is processed.
+// same Alg. 1 sweep (gather the tile, run the stages, scatter it back).  By
+// default a launch has one workgroup per tile and each XCD sweeps a
+// contiguous eighth of the tiles; a persistent grid that keeps the next
+// tile's loads in flight is the alternative shape.
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
@@ -233,7 +234,7 @@ std::string specialize_part_source(const CompiledPart& cp, hs_dtype dt, const st
     << "static __device__ inline __attribute__((always_inline)) unsigned sl(unsigned t) { unsigned f = 0u, h = t >> " << sw
     << "; while (h) { f ^= h & " << ((1 << sw) - 1) << "u; h >>= " << sw << "; } return t ^ f; }\n";
   o << "extern \"C\" __global__ void __launch_bounds__(" << (64 << d.wb) << ") " << name
-    << "(V* __restrict__ st, unsigned long long tiles) {\n";
+    << "(V* __restrict__ st, unsigned long long tiles, unsigned xcd) {\n";
   if (cp.lds_round_trips) o << "  __shared__ V lds[" << (1u << d.m) << "];\n";
   o << "  const unsigned lane = threadIdx.x & 63u;\n"
     << "  const unsigned wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);\n"
@@ -242,8 +243,11 @@ std::string specialize_part_source(const CompiledPart& cp, hs_dtype dt, const st
     << "  (void)thr; (void)active;\n";
   o << "  " << T << " ";
   for (int j = 0; j < N; ++j) o << "ar" << j << ", ai" << j << (j + 1 < N ? ", " : ";\n");
-  o << "  " << T << " ";
-  for (int j = 0; j < N; ++j) o << "nr" << j << ", ni" << j << (j + 1 < N ? ", " : ";\n");
+  const bool pf = cp.launch.prefetch && cp.launch.per_cu > 0;
+  if (pf) {
+    o << "  " << T << " ";
+    for (int j = 0; j < N; ++j) o << "nr" << j << ", ni" << j << (j + 1 < N ? ", " : ";\n");
+  }
   // tile base: insert a zero bit at every tile qubit (ascending)
   o << "  auto base_of = [&](unsigned long long t) -> unsigned long long {\n    unsigned long long b = t;\n";
   for (int i = 0; i < d.m; ++i) {
@@ -255,18 +259,35 @@ std::string specialize_part_source(const CompiledPart& cp, hs_dtype dt, const st
   o << "  {\n";
   emit_thread_offsets(E, cp.stages[0], d, "lane", "wave", "lo_ld", "wo_ld");
   emit_thread_offsets(E, cp.stages[ne - 1], d, "lane", "wave", "lo_st", "wo_st");
-  o << "  unsigned long long tile = blockIdx.x;\n"
-    << "  if (tile < tiles && active) {\n"
-    << "    const V* p = st + base_of(tile) + wo_ld + lo_ld;\n";
-  emit_io(E, cp.stages[0], d, false, "a", "p");
-  o << "  }\n"
-    << "  for (; tile < tiles; tile += gridDim.x) {\n"
-    << "    const unsigned long long tb = base_of(tile);\n"
-    << "    const unsigned long long nt = tile + gridDim.x;\n"
-    << "    if (nt < tiles && active) {\n"
-    << "      const V* p = st + base_of(nt) + wo_ld + lo_ld;\n";
-  emit_io(E, cp.stages[0], d, false, "n", "p");
-  o << "    }\n";
+  // tiles walked by this workgroup: with xcd set (grid and tiles multiples
+  // of 8), XCD x = blockIdx % 8 owns the contiguous run [x T/8, (x+1) T/8)
+  o << "  unsigned long long tile = blockIdx.x, step = gridDim.x, end = tiles;\n"
+    << "  if (xcd) {\n"
+    << "    const unsigned long long per = tiles >> 3;\n"
+    << "    tile = (unsigned long long)(blockIdx.x & 7u) * per + (blockIdx.x >> 3);\n"
+    << "    step = gridDim.x >> 3;\n"
+    << "    end = (unsigned long long)((blockIdx.x & 7u) + 1u) * per;\n"
+    << "  }\n";
+  if (pf) {
+    o << "  if (tile < end && active) {\n"
+      << "    const V* p = st + base_of(tile) + wo_ld + lo_ld;\n";
+    emit_io(E, cp.stages[0], d, false, "a", "p");
+    o << "  }\n";
+  }
+  o << "  for (; tile < end; tile += step) {\n"
+    << "    const unsigned long long tb = base_of(tile);\n";
+  if (pf) {
+    o << "    const unsigned long long nt = tile + step;\n"
+      << "    if (nt < end && active) {\n"
+      << "      const V* p = st + base_of(nt) + wo_ld + lo_ld;\n";
+    emit_io(E, cp.stages[0], d, false, "n", "p");
+    o << "    }\n";
+  } else {
+    o << "    if (active) {\n"
+      << "      const V* p = st + tb + wo_ld + lo_ld;\n";
+    emit_io(E, cp.stages[0], d, false, "a", "p");
+    o << "    }\n";
+  }
   for (int s = 1; s < ne; ++s) {
     const StageDesc& e = cp.stages[s];
     if (e.transition) emit_transition(E, cp.stages[s - 1], e, d, sw);
@@ -276,7 +297,8 @@ std::string specialize_part_source(const CompiledPart& cp, hs_dtype dt, const st
     << "      V* p = st + tb + wo_st + lo_st;\n";
   emit_io(E, cp.stages[ne - 1], d, true, "a", "p");
   o << "    }\n";
-  for (int j = 0; j < N; ++j) o << "    ar" << j << " = nr" << j << "; ai" << j << " = ni" << j << ";\n";
+  if (pf)
+    for (int j = 0; j < N; ++j) o << "    ar" << j << " = nr" << j << "; ai" << j << " = ni" << j << ";\n";
   o << "  }\n  }\n}\n";
   return o.str();
 }
@@ -287,7 +309,8 @@ struct SpecKernel {
   hipModule_t mod = nullptr;
   hipFunction_t fn = nullptr;
   int block = 64;
-  unsigned grid = 1;
+  int per_cu = 1;  // resident workgroups per CU (occupancy)
+  int cus = 1;
 };
 
 namespace {
@@ -378,17 +401,29 @@ hs_status specialize_plan(const std::vector<CompiledPart>& parts, hs_dtype dt, i
     if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k->fn, k->block, 0) != hipSuccess ||
         per_cu < 1)
       return fail(HS_E_HIP, "occupancy query failed for a specialized part");
-    const uint64_t cap = (uint64_t)per_cu * cus;
-    k->grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(parts[i].desc.tiles, cap));
+    k->per_cu = per_cu;
+    k->cus = cus;
     g_spec[{device, hash[i]}] = k;
   }
   for (int i : todo) (*out)[i] = g_spec[{device, hash[i]}];
   return HS_OK;
 }
 
-hs_status launch_specialized(const SpecKernel& k, void* state, uint64_t tiles, void* stream) {
-  void* args[] = {&state, &tiles};
-  hipError_t e = hipModuleLaunchKernel(k.fn, k.grid, 1, 1, k.block, 1, 1, 0, (hipStream_t)stream,
+hs_status launch_specialized(const SpecKernel& k, const CompiledPart& cp, void* state, void* stream) {
+  uint64_t tiles = cp.desc.tiles;
+  uint64_t grid = tiles;
+  if (cp.launch.per_cu > 0)
+    grid = std::min<uint64_t>(tiles, (uint64_t)cp.launch.per_cu * k.per_cu * k.cus);
+  // keep the launch's thread count within 31 bits; the kernel loops over the rest
+  grid = std::max<uint64_t>(1, std::min<uint64_t>(grid, (uint64_t(1) << 31) / (uint64_t)k.block));
+  unsigned xcd = 0;
+  if (cp.launch.xcd && tiles % 8 == 0 && grid >= 8) {
+    grid &= ~uint64_t(7);
+    xcd = 1;
+  }
+  unsigned g = (unsigned)grid;
+  void* args[] = {&state, &tiles, &xcd};
+  hipError_t e = hipModuleLaunchKernel(k.fn, g, 1, 1, k.block, 1, 1, 0, (hipStream_t)stream,
                                        args, nullptr);
   if (e != hipSuccess) return fail(HS_E_HIP, "hipModuleLaunchKernel: %s", hipGetErrorString(e));
   return HS_OK;
