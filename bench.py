@@ -15,6 +15,11 @@ Prints ONE JSON line on stdout:
              the 8 TB/s HBM peak; `traffic` from committed rocprofv3 counters
   gate_per_pass  the same GPU, one sweep per gate, on the circuit's first gates
   serving    p50/p99 latency and circuits/s of a short Poisson request stream
+  sweep      the same circuit distribution at n = 30..33 (k = 7), n = 34 at
+             k = 5 and 6, and a 33-qubit complex128 state: one timed step each
+  qft32      a 32-qubit QFT on a random basis state, k = 7 dagP partition:
+             gate-by-gate (specialized) vs fused-unitary (matrix cores) vs
+             AUTO, with the fused kernel's matrix-core roofline
   cpu_baseline  the oracle (numpy complex128) on a bounded sample
 """
 
@@ -33,6 +38,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "gates/s + HBM GB/s per part-pass at n=30..34; p50/p99 latency in serving loop"
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6}  # dense FP32 / FP64 matrix cores
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 
 
@@ -89,6 +95,109 @@ def cpu_baseline(n_target: int, seed: int, budget_s: float = 12.0, n_cpu: int = 
     }
 
 
+def timed_plan(st, plan, stream, steps=1):
+    """Seconds of `steps` whole-plan runs (one warm run first), HIP events on the state's stream."""
+    import torch
+    st.simulate(plan, "part_spec")
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        st.simulate(plan, "part_spec")
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / steps
+
+
+def run_sweep(args, buf, stream, log):
+    """The headline circuit distribution over n = 30..34, k = 5..7 and both dtypes."""
+    from paper_2205_06973_amd import hisv
+    from paper_2205_06973_amd import workloads as wl
+    cases = [(30, "c64", 7), (31, "c64", 7), (32, "c64", 7), (33, "c64", 7),
+             (34, "c64", 5), (34, "c64", 6), (33, "c128", 7)]
+    rows = []
+    for n, dt, k in cases:
+        amp = 8 if dt == "c64" else 16
+        if (1 << n) * amp > buf.numel() * buf.element_size():
+            continue
+        import torch
+        view = buf.view(torch.uint8)[: (1 << n) * amp].view(
+            torch.complex64 if dt == "c64" else torch.complex128)
+        st = hisv.State.wrap_tensor(view, stream)
+        st.set_basis(0)
+        _, gates = wl.random34(args.seed, n=n, num_gates=args.gates)
+        plan = hisv.Plan.partition(hisv.Circuit(n, gates), k, "dfs", seed=args.seed, trials=args.trials)
+        plan.specialize(dt)
+        sec = timed_plan(st, plan, stream)
+        norm = st.norm()
+        st.close()
+        P = plan.num_parts
+        gbs = part_pass_bytes(n, dt) * P / sec / 1e9
+        row = {"n": n, "dtype": dt, "k": k, "parts": P, "gates_per_s": len(gates) / sec,
+               "ms_per_circuit": sec * 1e3, "pass_GBps": gbs, "frac": gbs / HBM_PEAK_GBS,
+               "norm_after": norm}
+        log(f"[bench] sweep {row}")
+        if not abs(norm - 1.0) < 1e-3:
+            raise RuntimeError(f"norm drift in sweep case {row}")
+        rows.append(row)
+    return rows
+
+
+def run_qft(buf, stream, log):
+    """32-qubit QFT (H + controlled-phase ladder + swaps) on a random basis
+    state, dagP k = 7: gate-by-gate specialized kernels (a) vs the fused dense
+    unitary on matrix cores (b) vs AUTO; sampled amplitudes against the closed
+    form e^{2 pi i x y / 2^n} / 2^{n/2}."""
+    import numpy as np
+    import torch
+    from paper_2205_06973_amd import hisv
+    from paper_2205_06973_amd import workloads as wl
+    n, dt = 32, "c64"
+    if (1 << n) * 8 > buf.numel() * buf.element_size():
+        return None
+    view = buf.view(torch.uint8)[: (1 << n) * 8].view(torch.complex64)
+    st = hisv.State.wrap_tensor(view, stream)
+    gates = wl.qft_circuit(n)
+    x = wl.random_basis_index(n, 3)
+    plan = hisv.Plan.partition(hisv.Circuit(n, gates), 7, "dagp", seed=0)
+    plan.specialize(dt)
+    P = plan.num_parts
+    idx = np.unique(np.random.default_rng(1).integers(0, 1 << n, 4096, dtype=np.uint64))
+    want = np.exp(2j * np.pi * ((int(x) * idx.astype(object)) % (1 << n)).astype(np.float64)
+                  / (1 << n)) / 2 ** (n / 2)
+    out = {"n": n, "dtype": dt, "k": 7, "strategy": "dagp", "parts": P, "gates": len(gates)}
+    for mode in ("part_spec", "part_fused", "auto"):
+        st.set_basis(int(x))
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(P + 1)]
+        ev[0].record(stream)
+        for i in range(P):
+            st.simulate_part(plan, i, mode)
+            ev[i + 1].record(stream)
+        torch.cuda.synchronize()
+        per = [ev[i].elapsed_time(ev[i + 1]) for i in range(P)]
+        err = float(np.max(np.abs(st.amplitudes_at(idx) - want)))
+        ms = sum(per)
+        row = {"ms_per_circuit": ms, "gates_per_s": len(gates) / ms * 1e3,
+               "max_abs_err_sampled": err}
+        if mode == "part_fused":
+            w7 = [per[i] for i in range(P) if len(plan.part_unitary(i)[0]) == 7]
+            if w7:
+                avg = sum(w7) / len(w7)
+                flops = 8.0 * 128 * (1 << n)  # 8 flops per complex multiply-add, 2^w per amplitude
+                tf = flops / (avg / 1e3) / 1e12
+                row["w7_parts"] = len(w7)
+                row["mfma_roofline"] = {"bound": "mfma", "achieved": tf, "peak": MFMA_PEAK_TFLOPS[dt],
+                                        "unit": "TFLOP/s", "frac": tf / MFMA_PEAK_TFLOPS[dt],
+                                        "avg_launch_ms": avg}
+        out[mode] = row
+        log(f"[bench] qft32 {mode}: {row}")
+    st.close()
+    out["speedup_gate_by_gate_over_fused"] = out["part_fused"]["ms_per_circuit"] / out["part_spec"]["ms_per_circuit"]
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +220,8 @@ def main() -> int:
                     help="layout knob passed to hs_tune before the plan is compiled")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="also run the plain copy kernel on this many GiB (counter calibration)")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the n / k / dtype sweep")
+    ap.add_argument("--no-qft", action="store_true", help="skip the 32-qubit QFT comparison")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -205,7 +316,9 @@ def main() -> int:
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": "part_pass_kernel", "bytes_per_launch": bpl,
+            "kernel": {"part_spec": "part_pass_spec", "part_lds": "part_pass_kernel",
+                       "auto": "part_pass_kernel+fused_pass_kernel"}[args.mode],
+            "bytes_per_launch": bpl,
             "avg_launch_us": avg_launch_s * 1e6, "launches": launches,
         },
         "norm_after": norm,
@@ -230,6 +343,11 @@ def main() -> int:
         log(f"[bench] gate-per-pass: {gpp_rate:.1f} gates/s")
 
     st.close()
+
+    if not args.no_sweep:
+        out["sweep"] = run_sweep(args, buf, stream, log)
+    if not args.no_qft:
+        out["qft32"] = run_qft(buf, stream, log)
     del buf
     torch.cuda.empty_cache()
 

@@ -93,7 +93,10 @@ typedef enum { HS_PART_NAT = 0, HS_PART_DFS = 1, HS_PART_DAGP = 2 } hs_strategy;
  *                    register-resident sub-states, staged through LDS;
  *   PART_FUSED    -- one sweep per part; each part's gates are multiplied
  *                    into one dense 2^w x 2^w unitary applied on matrix cores;
- *   AUTO          -- per part, the cheaper of PART_LDS and PART_FUSED;
+ *   AUTO          -- per part, the cheaper by a cost model of PART_FUSED and
+ *                    the gate-by-gate kernel: PART_SPEC's when
+ *                    hs_plan_specialize has built them for the state's dtype
+ *                    and device, else PART_LDS's;
  *   PART_SPEC     -- one sweep per part, as PART_LDS, with each part's kernel
  *                    specialized at plan time: the part's layouts, register
  *                    operations and coefficients become compile-time
@@ -122,22 +125,26 @@ const char* hs_last_error(void);
 hs_status hs_device_count(int* out);
 
 /* Layout knobs read when a plan is next compiled (plans already compiled
- * keep theirs): "rb_c64" / "rb_c128" = register bits per lane (1..5, 2^rb
- * amplitudes each); "contig" = the tile always holds qubits 0..contig-1
+ * keep theirs): "rb_c64" / "rb_c128" = register bits per lane (2^rb
+ * amplitudes each; 1..4 / 1..3 for the interpreter kernel, 1..5 for the
+ * specialized kernels); "contig" = the tile always holds qubits 0..contig-1
  * (0..6); "min_run_c64" / "min_run_c128" = gather and scatter straight in a
  * stage's layout when its lanes still cover qubits 0..min_run-1, instead of
  * re-laying out through LDS (0..6; 6 = only fully contiguous 64-amplitude
  * runs).  Launch shape of the part kernels: "xcd" (0/1) = each of the 8
  * XCDs sweeps one contiguous eighth of the tiles; "grid" = 0 for one
  * workgroup per tile, g in 1..64 for a persistent grid of g x the resident
- * workgroups per CU; "prefetch" (0/1) = a persistent grid keeps the next
- * tile's loads in flight.  A "spec_" prefix on any key sets it for the
- * specialized kernels (PART_SPEC) instead of the interpreter kernel.
+ * workgroups per CU; "spec_prefetch" (0/1) = a persistent grid of the
+ * specialized kernels keeps the next tile's loads in flight.  A "spec_"
+ * prefix on a key sets it for the specialized kernels (PART_SPEC) instead of
+ * the interpreter kernel ("contig" has no prefix: it applies to both).
  * HS_E_ARG for an unknown key or value. */
 hs_status hs_tune(const char* key, int value);
 
-/* Largest part width k that hs_simulate with PART_LDS / PART_FUSED accepts
- * for the given dtype (the tile capacity of the kernels). */
+/* Largest part width k that hs_simulate with `exec` accepts for every part
+ * of a k-bounded plan on the given dtype: the LDS tile capacity less the
+ * coalescing pad for PART_LDS / PART_SPEC / AUTO, 7 for PART_FUSED (a
+ * 128 x 128 unitary), unbounded (64) for GATE_PER_PASS. */
 hs_status hs_max_part_qubits(hs_dtype dtype, hs_exec exec, int* out);
 
 /* ---- states (Sec. II.B) --------------------------------------------------- */
@@ -232,12 +239,12 @@ hs_status hs_plan_part_source(hs_plan p, int part, hs_dtype dtype, char* buf, si
 hs_status hs_plan_specialize(hs_plan p, hs_dtype dtype);
 
 /* The dense unitary U_p of a part as the fused path applies it: *w = the
- * number of qubits it acts on (4 or 5; parts of fewer qubits are widened
- * with the lowest other qubits, on which U acts as the identity).  If out is
+ * number of qubits it acts on (4..7; parts of fewer than 4 qubits are
+ * widened with the lowest other qubits, on which U acts as the identity).  If out is
  * not NULL it receives w doubles (the qubits, ascending; bit b of a row or
  * column index is the b-th of them) followed by the 2^w x 2^w matrix,
  * row-major, interleaved complex128.  Built in FP64 from the part's gates
- * in circuit order.  HS_E_UNSUPPORTED for parts wider than 5 qubits. */
+ * in circuit order.  HS_E_UNSUPPORTED for parts wider than 7 qubits. */
 hs_status hs_plan_part_unitary(hs_plan p, int part, int* w, double* out);
 
 hs_status hs_plan_destroy(hs_plan p);

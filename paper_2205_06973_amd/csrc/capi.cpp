@@ -176,12 +176,20 @@ hs_status hs_tune(const char* key, int value) {
   return HS_OK;
 }
 
+static hs_status check_exec(hs_exec exec);
+
 hs_status hs_max_part_qubits(hs_dtype dtype, hs_exec exec, int* out) {
   CHECK_ARG(out, "null output");
   CHECK_ARG(dtype == HS_C64 || dtype == HS_C128, "bad dtype %d", (int)dtype);
-  (void)exec;
-  const CompileOptions o = default_options(dtype);
-  *out = max_tile_qubits(o) - o.contig;
+  if (hs_status rc = check_exec(exec)) return rc;
+  if (exec == HS_EXEC_GATE_PER_PASS) {
+    *out = 64;
+  } else if (exec == HS_EXEC_PART_FUSED) {
+    *out = kMaxFusedQubits;
+  } else {
+    const CompileOptions o = default_options(dtype, exec == HS_EXEC_PART_SPEC);
+    *out = max_tile_qubits(o) - o.contig;
+  }
   return HS_OK;
 }
 
@@ -478,22 +486,41 @@ static hs_status check_exec(hs_exec exec) {
 }
 
 // Parts [first, last) on the interpreter LDS kernel, the fused kernel, or
-// (AUTO) whichever the cost model prefers per part.
+// (AUTO) whichever the cost model prefers per part.  AUTO's gate-by-gate side
+// is the specialized kernels when hs_plan_specialize has built them for this
+// dtype and device (no hipRTC work starts here), else the interpreter.
 static hs_status run_parts(hs_state s, Plan* p, int first, int last, hs_exec exec) {
   if (hs_status rc = plan_compile(p, s->dtype)) return rc;
   if (exec != HS_EXEC_PART_LDS)
     if (hs_status rc = plan_compile_fused(p)) return rc;
+  std::vector<std::shared_ptr<SpecKernel>>* ks = nullptr;
+  if (exec == HS_EXEC_AUTO) {
+    std::lock_guard<std::mutex> lk(p->mu);
+    auto it = p->spec[s->dtype].find(s->device);
+    if (it != p->spec[s->dtype].end()) ks = &it->second;
+  }
   for (int i = first; i < last; ++i) {
     bool fused = false;
     if (exec == HS_EXEC_PART_FUSED) {
       if (!p->fused[i].w)
-        return fail(HS_E_UNSUPPORTED, "part %d uses more than 5 qubits: no fused form", i);
+        return fail(HS_E_UNSUPPORTED, "part %d uses more than %d qubits: no fused form", i,
+                    kMaxFusedQubits);
       fused = true;
     } else if (exec == HS_EXEC_AUTO) {
-      fused = p->fused[i].w &&
-              fused_part_cost(p->fused[i], s->dtype) < lds_part_cost(p->comp[s->dtype][i]);
+      const double gate_cost = ks ? spec_part_cost(p->scomp[s->dtype][i])
+                                  : lds_part_cost(p->comp[s->dtype][i]);
+      fused = p->fused[i].w && fused_part_cost(p->fused[i], s->dtype) < gate_cost;
     }
-    if (hs_status rc = fused ? dev_run_fused(s, p, i) : dev_run_part(s, p, i)) return rc;
+    hs_status rc;
+    if (fused) {
+      rc = dev_run_fused(s, p, i);
+    } else if (ks) {
+      if (hipSetDevice(s->device) != hipSuccess) return fail(HS_E_HIP, "hipSetDevice failed");
+      rc = launch_specialized(*(*ks)[i], p->scomp[s->dtype][i], s->ptr, s->stream);
+    } else {
+      rc = dev_run_part(s, p, i);
+    }
+    if (rc) return rc;
   }
   return HS_OK;
 }

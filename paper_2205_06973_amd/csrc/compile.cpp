@@ -283,7 +283,8 @@ hs_status compile_fused(int n, const std::vector<Gate>& pg, FusedPart* out) {
   for (const Gate& g : pg) S |= g.mask();
   for (int q = 0; q < n && __builtin_popcountll(S) < 4; ++q) S |= 1ull << q;
   const int w = __builtin_popcountll(S);
-  if (w > 5) return fail(HS_E_UNSUPPORTED, "fused path takes parts of at most 5 qubits (got %d)", w);
+  if (w > kMaxFusedQubits)
+    return fail(HS_E_UNSUPPORTED, "fused path takes parts of at most %d qubits (got %d)", kMaxFusedQubits, w);
   if (n < w + 4) return fail(HS_E_UNSUPPORTED, "fused path needs n >= %d", w + 4);
   FusedPart f;
   f.w = w;
@@ -366,13 +367,35 @@ double lds_part_cost(const CompiledPart& cp) {
   return c;
 }
 
-// The fused kernel's matrix-core time is about 0.4 (w = 4) and 0.8 (w = 5)
-// of an HBM sweep for both precisions, mostly overlapped with the sweep.
+// The specialized kernels keep the sweep near the HBM rate: on the same
+// 30..34-qubit measurements an LDS re-layout costs about 0.03 sweep and the
+// register operations about a third of their interpreter cost.
+double spec_part_cost(const CompiledPart& cp) {
+  static const double op_cost[OP_NUM] = {0.066, 0.035, 0.038, 0.025, 0.01,
+                                         0.007, 0.007, 0.012, 0.01};
+  double c = 1.0 + 0.03 * cp.lds_round_trips;
+  for (const HostOp& op : cp.ops) c += op_cost[op.kind] / 3.0;
+  return c;
+}
+
+// The fused kernel does 8 * 2^w flops per amplitude on matrix cores against
+// 2 * s bytes of HBM traffic (s = 8 or 16 bytes per amplitude).  At the
+// FP32 / FP64 matrix peaks (157.3 / 78.6 TFLOP/s) against ~6 TB/s that is
+// about 0.02 * 2^w sweeps for either precision: w <= 5 stays HBM-bound (the
+// measured cost is 1.05 / 1.2 sweeps), w = 6 and 7 are matrix-core bound
+// (2.2 / 4.0 sweeps measured on a 32-qubit QFT).  When the part holds one of
+// qubits 0..3 the 16 columns of a wave are not one contiguous run and the
+// HBM-bound widths measured ~1.7 sweeps.
 double fused_part_cost(const FusedPart& f, hs_dtype dt) {
   (void)dt;
-  if (f.w == 4) return 1.05;
-  if (f.w == 5) return 1.2;
-  return 1e30;
+  const bool coalesced = f.pq[0] == 0 && f.pq[1] == 1 && f.pq[2] == 2 && f.pq[3] == 3;
+  switch (f.w) {
+    case 4: return coalesced ? 1.05 : 1.7;
+    case 5: return coalesced ? 1.2 : 1.8;
+    case 6: return 2.2;
+    case 7: return 4.0;
+    default: return 1e30;
+  }
 }
 
 }  // namespace hisv

@@ -173,6 +173,7 @@ hs_status dev_run_part(State* s, Plan* p, int part);
 hs_status dev_run_fused(State* s, Plan* p, int part);
 hs_status plan_compile_fused(Plan* p);
 // relative cost (one HBM sweep = 1) of a part on each path, for AUTO
+double spec_part_cost(const CompiledPart& cp);
 double lds_part_cost(const CompiledPart& cp);
 double fused_part_cost(const FusedPart& f, hs_dtype dt);
 hs_status dev_norm(State* s, double* out);

@@ -385,29 +385,41 @@ __device__ __forceinline__ uint64_t deposit(uint32_t v, const int8_t* q, int cou
   return g;
 }
 
+// U arrives in fragment order: fragment f = rb * (2^w / 4) + ks holds, in lane
+// l, U[16 rb + l % 16][4 ks + l / 16]; the real parts of all fragments come
+// first, then the imaginary parts.  For w <= 5 a wave keeps all of U in
+// registers; wider U (64x64, 128x128) is read fragment by fragment from the
+// L2-resident copy -- one contiguous 256-byte wave load per fragment, against
+// four matrix-core products that take far longer.
 template <typename T, int W>
 __global__ void __launch_bounds__(256)
-fused_pass_kernel(cplx<T>* __restrict__ st, const FusedDesc* __restrict__ fd, const T* __restrict__ umat) {
+fused_pass_kernel(cplx<T>* __restrict__ st, const FusedDesc* __restrict__ fd, const T* __restrict__ umat,
+                  uint32_t xcd) {
   using v4 = typename Mfma<T>::v4;
   constexpr int R = 1 << W;   // rows of U
   constexpr int RBK = R / 16; // 16-row blocks
   constexpr int KS = R / 4;   // K steps of 4
+  constexpr int NF = RBK * KS;
+  constexpr bool kRegU = W <= 5;
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t i16 = lane & 15, g4 = lane >> 4;
   const int m = fd->m;
   const uint64_t tiles = fd->tiles;
   const T* Ur = umat + fd->u_off;
-  const T* Ui = Ur + R * R;
-  T ur[RBK][KS], ui[RBK][KS], nui[RBK][KS];
+  const T* Ui = Ur + NF * 64;
+  T ur[kRegU ? RBK : 1][kRegU ? KS : 1], ui[kRegU ? RBK : 1][kRegU ? KS : 1],
+      nui[kRegU ? RBK : 1][kRegU ? KS : 1];
+  if (kRegU) {
 #pragma unroll
-  for (int rb = 0; rb < RBK; ++rb)
+    for (int rb = 0; rb < (kRegU ? RBK : 1); ++rb)
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const int idx = (rb * 16 + i16) * R + ks * 4 + g4;
-      ur[rb][ks] = Ur[idx];
-      ui[rb][ks] = Ui[idx];
-      nui[rb][ks] = -ui[rb][ks];
-    }
+      for (int ks = 0; ks < (kRegU ? KS : 1); ++ks) {
+        const int f = rb * KS + ks;
+        ur[rb][ks] = Ur[f * 64 + lane];
+        ui[rb][ks] = Ui[f * 64 + lane];
+        nui[rb][ks] = -ui[rb][ks];
+      }
+  }
   // lane parts of the addresses: B rows k = 4*ks + g4 (slots 0-1 from the
   // lane); D rows i = 16*rb + 4*g4 + v (FP32: slots 2-3 from the lane) or
   // 16*rb + 4*v + g4 (FP64: slots 0-1 from the lane); columns j = i16 on
@@ -416,16 +428,23 @@ fused_pass_kernel(cplx<T>* __restrict__ st, const FusedDesc* __restrict__ fd, co
   const uint64_t col = deposit(i16, fd->pq, 4);
   const uint64_t lane_ld = col + deposit(g4, fd->sq, 2);
   const uint64_t lane_st = f64 ? lane_ld : col + deposit(g4 << 2, fd->sq, W);
-  uint64_t row_ld[KS], row_st[RBK][4];
+  uint64_t row_ld[KS];
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks) row_ld[ks] = deposit(4 * ks, fd->sq, W);
-#pragma unroll
-  for (int rb = 0; rb < RBK; ++rb)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) row_st[rb][v] = deposit(16 * rb + (f64 ? 4 * v : v), fd->sq, W);
-  const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
-  for (uint64_t tile = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); tile < tiles;
-       tile += waves) {
+  // a workgroup's 4 waves take 4 consecutive tiles; with xcd set (grid and
+  // group count multiples of 8) XCD x = blockIdx % 8 sweeps a contiguous run
+  const uint64_t groups = (tiles + 3) >> 2;
+  uint64_t g = blockIdx.x, step = gridDim.x, end = groups;
+  if (xcd) {
+    const uint64_t per = groups >> 3;
+    const uint32_t x = blockIdx.x & 7u;
+    g = x * per + (blockIdx.x >> 3);
+    step = gridDim.x >> 3;
+    end = (x + 1) * per;
+  }
+  for (; g < end; g += step) {
+    const uint64_t tile = g * 4 + (threadIdx.x >> 6);
+    if (tile >= tiles) continue;
     const uint64_t base = tile_base(tile, fd->tq, m);
     T xr[KS], xi[KS];
 #pragma unroll
@@ -434,22 +453,33 @@ fused_pass_kernel(cplx<T>* __restrict__ st, const FusedDesc* __restrict__ fd, co
       xr[ks] = v.x;
       xi[ks] = v.y;
     }
-#pragma unroll
+#pragma unroll(kRegU ? RBK : 1)
     for (int rb = 0; rb < RBK; ++rb) {
       v4 yr = {0, 0, 0, 0}, yi = {0, 0, 0, 0};
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
-        yr = Mfma<T>::mma(ur[rb][ks], xr[ks], yr);
-        yr = Mfma<T>::mma(nui[rb][ks], xi[ks], yr);
-        yi = Mfma<T>::mma(ur[rb][ks], xi[ks], yi);
-        yi = Mfma<T>::mma(ui[rb][ks], xr[ks], yi);
+        T ar, ai, nai;
+        if (kRegU) {
+          ar = ur[kRegU ? rb : 0][kRegU ? ks : 0];
+          ai = ui[kRegU ? rb : 0][kRegU ? ks : 0];
+          nai = nui[kRegU ? rb : 0][kRegU ? ks : 0];
+        } else {
+          const int f = rb * KS + ks;
+          ar = Ur[f * 64 + lane];
+          ai = Ui[f * 64 + lane];
+          nai = -ai;
+        }
+        yr = Mfma<T>::mma(ar, xr[ks], yr);
+        yr = Mfma<T>::mma(nai, xi[ks], yr);
+        yi = Mfma<T>::mma(ar, xi[ks], yi);
+        yi = Mfma<T>::mma(ai, xr[ks], yi);
       }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         cplx<T> o;
         o.x = yr[v];
         o.y = yi[v];
-        st[base + row_st[rb][v] + lane_st] = o;
+        st[base + deposit(16 * rb + (f64 ? 4 * v : v), fd->sq, W) + lane_st] = o;
       }
     }
   }
@@ -709,6 +739,7 @@ struct DevicePlan {
   void* fmat = nullptr;
   std::vector<FusedDesc> h_fparts;
   std::vector<unsigned> fgrid;
+  std::vector<uint8_t> fxcd;
 };
 
 void device_plan_free(DevicePlan* d) {
@@ -868,8 +899,6 @@ template <typename T>
 static hs_status upload_fused(Plan* p, DevicePlan* dp) {
   std::vector<FusedDesc> fds;
   std::vector<T> mats;
-  DevInfo di;
-  if (hs_status rc = device_info(dp->device, &di)) return rc;
   for (const FusedPart& f : p->fused) {
     FusedDesc d{};
     d.w = f.w;
@@ -879,13 +908,26 @@ static hs_status upload_fused(Plan* p, DevicePlan* dp) {
     std::memcpy(d.sq, f.sq, sizeof d.sq);
     std::memcpy(d.pq, f.pq, sizeof d.pq);
     std::memcpy(d.tq, f.tq, sizeof d.tq);
-    for (const cd& z : f.u) mats.push_back((T)z.real());
-    for (const cd& z : f.u) mats.push_back((T)z.imag());
+    // fragment order (see fused_pass_kernel): real parts, then imaginary
+    const int R = 1 << f.w;
+    for (int part_im = 0; part_im < 2 && f.w > 0; ++part_im)
+      for (int rb = 0; rb < R / 16; ++rb)
+        for (int ks = 0; ks < R / 4; ++ks)
+          for (int l = 0; l < 64; ++l) {
+            const cd z = f.u[(size_t)(16 * rb + l % 16) * R + 4 * ks + l / 16];
+            mats.push_back((T)(part_im ? z.imag() : z.real()));
+          }
     fds.push_back(d);
-    // four wavefronts per block, enough blocks to cover every CU a few times
-    const uint64_t waves = f.tiles;
-    dp->fgrid.push_back((unsigned)std::max<uint64_t>(
-        1, std::min<uint64_t>((waves + 3) / 4, (uint64_t)di.cus * 8)));
+    // one workgroup of four wavefronts per four tiles, XCD-contiguous runs
+    const uint64_t groups = (f.tiles + 3) / 4;
+    uint64_t g = std::max<uint64_t>(1, std::min<uint64_t>(groups, (uint64_t(1) << 31) / 256));
+    uint8_t x = 0;
+    if (groups % 8 == 0 && g >= 8) {
+      g &= ~uint64_t(7);
+      x = 1;
+    }
+    dp->fgrid.push_back((unsigned)g);
+    dp->fxcd.push_back(x);
   }
   if (mats.empty()) mats.push_back(T(0));
   if (fds.empty()) fds.push_back(FusedDesc{});
@@ -905,12 +947,15 @@ static hs_status launch_fused(State* s, DevicePlan* dp, int part) {
   const FusedDesc* fd = dp->fparts + part;
   const T* um = (const T*)dp->fmat;
   hipStream_t str = stream_of(s);
-  if (d.w == 4)
-    hipLaunchKernelGGL((fused_pass_kernel<T, 4>), dim3(dp->fgrid[part]), dim3(256), 0, str, st, fd, um);
-  else if (d.w == 5)
-    hipLaunchKernelGGL((fused_pass_kernel<T, 5>), dim3(dp->fgrid[part]), dim3(256), 0, str, st, fd, um);
-  else
-    return fail(HS_E_UNSUPPORTED, "part %d has no fused form", part);
+  const dim3 grid(dp->fgrid[part]);
+  const uint32_t xcd = dp->fxcd[part];
+  switch (d.w) {
+    case 4: hipLaunchKernelGGL((fused_pass_kernel<T, 4>), grid, dim3(256), 0, str, st, fd, um, xcd); break;
+    case 5: hipLaunchKernelGGL((fused_pass_kernel<T, 5>), grid, dim3(256), 0, str, st, fd, um, xcd); break;
+    case 6: hipLaunchKernelGGL((fused_pass_kernel<T, 6>), grid, dim3(256), 0, str, st, fd, um, xcd); break;
+    case 7: hipLaunchKernelGGL((fused_pass_kernel<T, 7>), grid, dim3(256), 0, str, st, fd, um, xcd); break;
+    default: return fail(HS_E_UNSUPPORTED, "part %d has no fused form", part);
+  }
   HIP_TRY(hipGetLastError());
   return HS_OK;
 }

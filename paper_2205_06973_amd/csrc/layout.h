@@ -20,6 +20,7 @@
 namespace hisv {
 
 constexpr int kMaxTile = 16;   // widest tile (qubits)
+constexpr int kMaxFusedQubits = 7;  // widest dense unitary of the fused path (128 x 128)
 constexpr int kLaneBits = 6;   // 64-wide wavefronts
 
 // A layout: pos[c] is the tile bit carried by coordinate bit c, where the

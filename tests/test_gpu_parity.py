@@ -47,6 +47,9 @@ def run_hip(n, gates, dtype, k, strategy="dfs", mode="part_lds", init=0, seed=0,
     st = new_state(n, dtype, init)
     if mode == "gate_per_pass":
         st.simulate_gate_per_pass(c)
+    elif mode == "auto_spec":  # AUTO over specialized gate-by-gate kernels
+        plan.specialize(dtype)
+        st.simulate(plan, "auto")
     else:
         st.simulate(plan, mode)
     out = st.amplitudes()
@@ -113,17 +116,32 @@ def test_qft_closed_form_18(dtype, mode, strategy):
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("n,k,mode", [(9, 4, "part_fused"), (12, 5, "part_fused"),
                                       (16, 3, "part_fused"), (17, 5, "part_fused"),
-                                      (15, 5, "auto"), (18, 7, "auto")])
+                                      (10, 6, "part_fused"), (15, 6, "part_fused"),
+                                      (11, 7, "part_fused"), (16, 7, "part_fused"),
+                                      (15, 5, "auto"), (18, 7, "auto"),
+                                      (14, 4, "auto_spec"), (17, 6, "auto_spec")])
 def test_fused_and_auto(n, k, mode, dtype):
+    # n = w + 4 is the smallest state the fused kernel takes (one tile)
     gates = wl.random_circuit(n, 160, ALL, seed=300 + n + k)
     got, _ = run_hip(n, gates, dtype, k, "dfs", mode, init=(n * 131) % (1 << n))
     check(got, sv.simulate(n, gates, (n * 131) % (1 << n)), dtype)
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_fused_qft_closed_form(dtype):
+    # k = 7 parts of a QFT are dense 128 x 128 unitaries
+    n = 17
+    x = wl.random_basis_index(n, 9)
+    got, _ = run_hip(n, wl.qft_circuit(n), dtype, 7, "dagp", "part_fused", init=x)
+    y = np.arange(1 << n)
+    want = np.exp(2j * np.pi * ((x * y) % (1 << n)) / (1 << n)) / math.sqrt(1 << n)
+    check(got, want, dtype)
+
+
 def test_fused_rejects_wide_part():
     n, gates = wl.random34(1, n=14, num_gates=100)
     with pytest.raises(hisv.HisvError) as e:
-        run_hip(n, gates, "c64", 7, "dfs", "part_fused")
+        run_hip(n, gates, "c64", 8, "dfs", "part_fused")
     assert e.value.code == "HS_E_UNSUPPORTED"
 
 

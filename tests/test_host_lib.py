@@ -240,11 +240,14 @@ def test_layout_report():
         assert m <= n and stages >= 1 and trips >= 0
     assert hisv.hs_max_part_qubits("c64") >= 7
     assert hisv.hs_max_part_qubits("c128") >= 6
+    assert hisv.hs_max_part_qubits("c64", "part_fused") == 7
+    assert hisv.hs_max_part_qubits("c128", "part_fused") == 7
+    assert hisv.hs_max_part_qubits("c64", "gate_per_pass") == 64
 
 
 # ---- fused path: the part unitary ------------------------------------------------
 
-@pytest.mark.parametrize("seed,k", [(0, 2), (1, 4), (2, 5), (3, 3)])
+@pytest.mark.parametrize("seed,k", [(0, 2), (1, 4), (2, 5), (3, 3), (4, 6), (5, 7)])
 def test_fused_unitary_matches_oracle_columns(seed, k):
     n = 11
     gates = wl.random_circuit(n, 80, sv.ONE_QUBIT + sv.TWO_QUBIT, seed)
@@ -265,9 +268,9 @@ def test_fused_unitary_matches_oracle_columns(seed, k):
 
 def test_fused_unitary_rejects_wide_parts():
     n, gates = wl.random34(1, n=12, num_gates=100)
-    plan = hisv.Plan.partition(hisv.Circuit(n, gates), 7, "dfs")
+    plan = hisv.Plan.partition(hisv.Circuit(n, gates), 8, "dfs")
     widths = [bin(plan.part_info(p)[0]).count("1") for p in range(plan.num_parts)]
-    wide = [p for p, w in enumerate(widths) if w > 5]
+    wide = [p for p, w in enumerate(widths) if w > 7]
     assert wide
     with pytest.raises(hisv.HisvError) as e:
         plan.part_unitary(wide[0])
