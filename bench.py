@@ -47,26 +47,29 @@ def part_pass_bytes(n: int, dtype: str) -> int:
     return 2 * (1 << n) * (8 if dtype == "c64" else 16)
 
 
-def kernel_source_hash() -> str:
+def spec_kernel_hash(plan, dtype: str) -> str:
+    """Identity of the specialized part kernels a plan runs: the generated
+    source of every part plus the launcher that sizes their grids."""
     h = hashlib.sha256()
-    for f in ("kernels.hip", "layout.h", "compile.cpp", "specialize.cpp"):
-        with open(os.path.join(ROOT, "paper_2205_06973_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    with open(os.path.join(ROOT, "paper_2205_06973_amd", "csrc", "specialize.cpp"), "rb") as fh:
+        h.update(fh.read())
+    for i in range(plan.num_parts):
+        h.update(plan.part_source(i, dtype).encode())
     return h.hexdigest()[:16]
 
 
-def committed_traffic(n: int, dtype: str, k: int):
+def committed_traffic(n: int, dtype: str, k: int, khash: str):
     """Per-launch HBM bytes from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source and this workload; else None."""
+    was taken on these very kernels (same generated sources) and workload."""
     path = os.path.join(PROFILE_DIR, "part_pass_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
-    key = f"n{n}_{dtype}_k{k}"
-    if d.get("kernel_source_hash") != kernel_source_hash() or key not in d.get("workloads", {}):
+    rec = d.get("workloads", {}).get(f"n{n}_{dtype}_k{k}")
+    if not rec or rec.get("kernel_hash") != khash:
         return None
-    return d["workloads"][key]["bytes_per_launch"]
+    return rec["bytes_per_launch"]
 
 
 def cpu_baseline(n_target: int, seed: int, budget_s: float = 12.0, n_cpu: int = 24) -> dict:
@@ -222,6 +225,8 @@ def main() -> int:
                     help="also run the plain copy kernel on this many GiB (counter calibration)")
     ap.add_argument("--no-sweep", action="store_true", help="skip the n / k / dtype sweep")
     ap.add_argument("--no-qft", action="store_true", help="skip the 32-qubit QFT comparison")
+    ap.add_argument("--qft-only", action="store_true",
+                    help="run only the 32-qubit QFT comparison (for kernel profiles)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -242,6 +247,12 @@ def main() -> int:
     for kv in args.tune:
         key, val = kv.split("=")
         hisv.hs_tune(key, int(val))
+    if args.qft_only:
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            qbuf = torch.empty(1 << 32, dtype=torch.complex64, device="cuda")
+        print(json.dumps({"qft32": run_qft(qbuf, stream, log)}), flush=True)
+        return 0
     n, G = args.n, args.gates
     _, gates = wl.random34(args.seed, n=n, num_gates=G)
     circ = hisv.Circuit(n, gates)
@@ -291,7 +302,9 @@ def main() -> int:
     avg_launch_s = gpu_ms / 1e3 / launches
     bpl = part_pass_bytes(n, args.dtype)
     achieved = bpl / avg_launch_s / 1e9
-    traffic = committed_traffic(n, args.dtype, args.k)
+    # the committed counters were taken on the specialized kernels
+    khash = spec_kernel_hash(plan, args.dtype) if args.mode == "part_spec" else None
+    traffic = committed_traffic(n, args.dtype, args.k, khash) if khash else None
     out = {
         "metric": METRIC,
         "value": G * args.steps / wall,
@@ -319,7 +332,7 @@ def main() -> int:
             "kernel": {"part_spec": "part_pass_spec", "part_lds": "part_pass_kernel",
                        "auto": "part_pass_kernel+fused_pass_kernel"}[args.mode],
             "bytes_per_launch": bpl,
-            "avg_launch_us": avg_launch_s * 1e6, "launches": launches,
+            "avg_launch_us": avg_launch_s * 1e6, "launches": launches, "kernel_hash": khash,
         },
         "norm_after": norm,
     }
@@ -339,6 +352,10 @@ def main() -> int:
             "pass_GBps": bpl / (gpp_s / args.gpp_gates) / 1e9,
             "speedup_partitioned": out["value"] / gpp_rate,
             "passes_saved": G / P,
+            # a two-qubit sweep leaves the |00> amplitude of every quad alone
+            # (3/4 of the state moves), so in HBM bytes the saving is smaller
+            "traffic_passes_saved": (sum(1 for g in gates if g[2] < 0)
+                                     + 0.75 * sum(1 for g in gates if g[2] >= 0)) / P,
         }
         log(f"[bench] gate-per-pass: {gpp_rate:.1f} gates/s")
 

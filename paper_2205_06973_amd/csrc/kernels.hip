@@ -493,12 +493,27 @@ struct M2 {
   T c[8];
 };
 
+// Work items [first, end) with stride `step` of a thread in a streaming
+// kernel.  With xcd set (grid a multiple of 8, count a multiple of 8), XCD
+// x = blockIdx % 8 sweeps the contiguous eighth [x count/8, (x+1) count/8).
+struct Walk {
+  uint64_t first, step, end;
+};
+__device__ __forceinline__ Walk stream_walk(uint64_t count, uint32_t xcd) {
+  if (!xcd)
+    return {(uint64_t)blockIdx.x * blockDim.x + threadIdx.x, (uint64_t)gridDim.x * blockDim.x, count};
+  const uint64_t per = count >> 3;
+  const uint32_t x = blockIdx.x & 7u;
+  return {x * per + (uint64_t)(blockIdx.x >> 3) * blockDim.x + threadIdx.x,
+          (uint64_t)(gridDim.x >> 3) * blockDim.x, (x + 1) * per};
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256)
-gate_pass_1q(cplx<T>* __restrict__ st, int q, uint64_t npairs, M2<T> u) {
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+gate_pass_1q(cplx<T>* __restrict__ st, int q, uint64_t npairs, M2<T> u, uint32_t xcd) {
+  const Walk w = stream_walk(npairs, xcd);
   const uint64_t lowmask = (uint64_t(1) << q) - 1;
-  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npairs; p += stride) {
+  for (uint64_t p = w.first; p < w.end; p += w.step) {
     const uint64_t i0 = ((p >> q) << (q + 1)) | (p & lowmask);
     const uint64_t i1 = i0 | (uint64_t(1) << q);
     const cplx<T> x = st[i0], y = st[i1];
@@ -515,11 +530,12 @@ gate_pass_1q(cplx<T>* __restrict__ st, int q, uint64_t npairs, M2<T> u) {
 // kind: 0 CX(q0 control, q1 target), 1 CZ, 2 CP(c0, c1), 3 SWAP
 template <typename T>
 __global__ void __launch_bounds__(256)
-gate_pass_2q(cplx<T>* __restrict__ st, int q0, int q1, int kind, uint64_t nquads, T cr, T ci) {
+gate_pass_2q(cplx<T>* __restrict__ st, int q0, int q1, int kind, uint64_t nquads, T cr, T ci,
+             uint32_t xcd) {
   const int lo = min(q0, q1), hi = max(q0, q1);
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const Walk w = stream_walk(nquads, xcd);
   const uint64_t m0 = uint64_t(1) << q0, m1 = uint64_t(1) << q1;
-  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nquads; p += stride) {
+  for (uint64_t p = w.first; p < w.end; p += w.step) {
     uint64_t i = ((p >> lo) << (lo + 1)) | (p & ((uint64_t(1) << lo) - 1));
     i = ((i >> hi) << (hi + 1)) | (i & ((uint64_t(1) << hi) - 1));
     // a[b] with bit 0 of b = qubit q0, bit 1 = qubit q1
@@ -684,12 +700,25 @@ hs_status dev_set_basis(State* s, uint64_t x) {
   return HS_OK;
 }
 
+// Grid of a gate sweep over `work` items: one item per thread up to 2^31
+// threads, XCD-contiguous runs when the grid and the item count allow.
+static void sweep_grid(uint64_t work, unsigned* grid, uint32_t* xcd) {
+  uint64_t g = std::max<uint64_t>(1, std::min<uint64_t>((work + 255) / 256, (uint64_t(1) << 31) / 256));
+  *xcd = 0;
+  if (work % 8 == 0 && g >= 8) {
+    g &= ~uint64_t(7);
+    *xcd = 1;
+  }
+  *grid = (unsigned)g;
+}
+
 template <typename T>
 static hs_status gate_pass_t(State* s, const Gate& g) {
   const uint64_t N = uint64_t(1) << s->n;
   unsigned grid;
+  uint32_t xcd;
   if (g.arity() == 1) {
-    if (hs_status rc = stream_grid(s->device, N / 2, &grid)) return rc;
+    sweep_grid(N / 2, &grid, &xcd);
     cd u[4];
     gate_matrix(g, u);
     M2<T> m;
@@ -698,10 +727,10 @@ static hs_status gate_pass_t(State* s, const Gate& g) {
       m.c[2 * i + 1] = (T)u[i].imag();
     }
     hipLaunchKernelGGL(gate_pass_1q<T>, dim3(grid), dim3(256), 0, stream_of(s),
-                       (cplx<T>*)s->ptr, g.q0, N / 2, m);
+                       (cplx<T>*)s->ptr, g.q0, N / 2, m, xcd);
   } else {
     if (s->n < 2) return fail(HS_E_ARG, "two-qubit gate on a 1-qubit state");
-    if (hs_status rc = stream_grid(s->device, N / 4, &grid)) return rc;
+    sweep_grid(N / 4, &grid, &xcd);
     int kind = 0;
     T cr = 0, ci = 0;
     switch (g.kind) {
@@ -712,7 +741,7 @@ static hs_status gate_pass_t(State* s, const Gate& g) {
       default: return fail(HS_E_ARG, "unknown two-qubit kind %d", g.kind);
     }
     hipLaunchKernelGGL(gate_pass_2q<T>, dim3(grid), dim3(256), 0, stream_of(s),
-                       (cplx<T>*)s->ptr, g.q0, g.q1, kind, N / 4, cr, ci);
+                       (cplx<T>*)s->ptr, g.q0, g.q1, kind, N / 4, cr, ci, xcd);
   }
   HIP_TRY(hipGetLastError());
   return HS_OK;

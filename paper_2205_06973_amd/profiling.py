@@ -1,15 +1,22 @@
 """Turn rocprofv3 output into the committed kernel summaries under profiles/.
 
-    python -m paper_2205_06973_amd.profiling stats  <stats.csv> <out.txt> "<command>"
+    python -m paper_2205_06973_amd.profiling stats  <stats.csv> <out.txt> "<command>" [--kernel-hash H]
     python -m paper_2205_06973_amd.profiling traffic <fetch.csv> <write.csv> <key> "<command>" \
-        --copy-bytes B
+        --copy-bytes B --kernel-hash H [--txt out.txt]
+    python -m paper_2205_06973_amd.profiling mfma <counters.csv> <stats.csv> <out.txt> "<command>"
 
 `stats` condenses a `--kernel-trace --stats` kernel_stats.csv.  `traffic`
 reads two `--pmc` counter_collection.csv files (FETCH_SIZE in one run,
 WRITE_SIZE in the other; both in KiB per dispatch), scales each by what the
 same counter reads for the plain copy kernel of known size (B bytes read and
 B bytes written), and records the HBM bytes per part-pass launch, keyed by
-workload and tagged with the hash of the kernel sources it was taken on.
+workload and tagged with the kernel hash that bench.py printed for the
+profiled run (roofline.kernel_hash: the generated part kernels).
+`mfma` reads a `--pmc SQ_INSTS_VALU_MFMA_MOPS_F32 SQ_INSTS_VALU_MFMA_MOPS_F64
+SQ_VALU_MFMA_BUSY_CYCLES GRBM_GUI_ACTIVE` run and the matching kernel-trace
+stats: per matrix-core kernel, flops per dispatch (MOPS x 512), achieved
+TFLOP/s over the traced average duration, and the busy fraction of the SIMDs'
+matrix cores (GRBM_GUI_ACTIVE is summed over the 8 XCDs; 1024 SIMDs).
 """
 
 from __future__ import annotations
@@ -43,10 +50,13 @@ def _short(name: str) -> str:
     return base[:60]
 
 
-def stats(csv_path: str, out_path: str, command: str) -> None:
+def stats(csv_path: str, out_path: str, command: str, khash: str | None = None) -> None:
     rows = list(csv.DictReader(open(csv_path)))
     lines = [f"# rocprofv3 --kernel-trace --stats summary", f"# command: {command}",
-             f"# kernel source hash: {kernel_source_hash()}", "",
+             f"# kernel source hash: {kernel_source_hash()}"]
+    if khash:
+        lines.append(f"# kernel hash (generated part kernels): {khash}")
+    lines += ["",
              f"{'kernel':48s} {'calls':>7s} {'avg_us':>11s} {'min_us':>11s} {'max_us':>11s} {'total_ms':>11s} {'pct':>6s}"]
     for r in rows:
         lines.append(f"{_short(r['Name']):48s} {int(r['Calls']):7d} {float(r['AverageNs'])/1e3:11.2f} "
@@ -66,7 +76,8 @@ def _counter_per_kernel(path: str, counter: str) -> dict[str, list[float]]:
     return out
 
 
-def traffic(fetch_csv: str, write_csv: str, key: str, command: str, copy_bytes: int) -> dict:
+def traffic(fetch_csv: str, write_csv: str, key: str, command: str, copy_bytes: int,
+            khash: str, txt_out: str | None = None) -> dict:
     fetch = _counter_per_kernel(fetch_csv, "FETCH_SIZE")
     write = _counter_per_kernel(write_csv, "WRITE_SIZE")
     cf = [v for k, v in fetch.items() if k.startswith("copy_probe_kernel")][0]
@@ -79,11 +90,28 @@ def traffic(fetch_csv: str, write_csv: str, key: str, command: str, copy_bytes: 
     wb = sum(pw) / len(pw) * 1024.0 * w_scale
     rec = {"bytes_per_launch": fb + wb, "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
            "launches_counted": len(pf), "copy_fetch_scale": f_scale, "copy_write_scale": w_scale,
-           "command": command}
+           "command": command, "kernel_hash": khash}
+    n, dt = key.split("_")[0][1:], key.split("_")[1]
+    algo = 2 * (1 << int(n)) * (8 if dt == "c64" else 16)
+    kib_f, kib_w = sum(pf) / len(pf), sum(pw) / len(pw)
+    txt = [f"# HBM traffic per launch of the part-pass kernel, workload {key}",
+           f"# commands (run from /tmp with TMPDIR=/tmp, one counter per run): {command}",
+           f"# kernel hash (generated part kernels): {khash}", "",
+           f"calibration (copy_probe_kernel, {copy_bytes} B read + {copy_bytes} B written):",
+           f"  FETCH_SIZE {sum(cf) / len(cf):14.1f} KiB -> scale {f_scale:.4f}",
+           f"  WRITE_SIZE {sum(cw) / len(cw):14.1f} KiB -> scale {w_scale:.4f}", "",
+           f"part-pass kernel, mean over {len(pf)} launches:",
+           f"  FETCH_SIZE {kib_f:14.1f} KiB x {f_scale:.4f} = {fb / 1e9:.3f} GB",
+           f"  WRITE_SIZE {kib_w:14.1f} KiB x {w_scale:.4f} = {wb / 1e9:.3f} GB",
+           f"  total {(fb + wb) / 1e9:.3f} GB per launch; algorithmic 2 * 2^{n} * "
+           f"{8 if dt == 'c64' else 16} B = {algo / 1e9:.3f} GB (ratio {(fb + wb) / algo:.5f})"]
+    if txt_out:
+        with open(txt_out, "w") as f:
+            f.write("\n".join(txt) + "\n")
+    print("\n".join(txt))
     path = os.path.join(PROFILES, "part_pass_traffic.json")
     d = json.load(open(path)) if os.path.exists(path) else {}
-    if d.get("kernel_source_hash") != kernel_source_hash():
-        d = {"kernel_source_hash": kernel_source_hash(), "workloads": {}}
+    d = {"workloads": d.get("workloads", {})}
     d["workloads"][key] = rec
     with open(path, "w") as f:
         json.dump(d, f, indent=1)
@@ -91,12 +119,47 @@ def traffic(fetch_csv: str, write_csv: str, key: str, command: str, copy_bytes: 
     return rec
 
 
+def mfma(counters_csv: str, stats_csv: str, out_path: str, command: str) -> None:
+    ctr: dict[str, dict[str, list[float]]] = {}
+    for r in csv.DictReader(open(counters_csv)):
+        ctr.setdefault(_short(r["Kernel_Name"]), {}).setdefault(r["Counter_Name"], []).append(
+            float(r["Counter_Value"]))
+    avg_ns = {_short(r["Name"]): float(r["AverageNs"]) for r in csv.DictReader(open(stats_csv))}
+    peak = {"F32": 157.3, "F64": 78.6}
+    lines = ["# matrix-core counters per dispatch (rocprofv3 --pmc) and kernel-trace durations",
+             f"# command: {command}", f"# kernel source hash: {kernel_source_hash()}",
+             "# flops = MOPS * 512; util = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / 8 XCDs * 1024 SIMDs)",
+             "",
+             f"{'kernel':36s} {'calls':>6s} {'avg_us':>10s} {'GFLOP/call':>11s} {'TFLOP/s':>8s} "
+             f"{'peak':>6s} {'frac':>6s} {'busy_util':>9s}"]
+    for k, d in sorted(ctr.items()):
+        f32 = d.get("SQ_INSTS_VALU_MFMA_MOPS_F32", [0.0])
+        f64 = d.get("SQ_INSTS_VALU_MFMA_MOPS_F64", [0.0])
+        kind = "F64" if sum(f64) > sum(f32) else "F32"
+        mops = f64 if kind == "F64" else f32
+        if sum(mops) == 0 or k not in avg_ns:
+            continue
+        flops = sum(mops) / len(mops) * 512
+        busy = sum(d["SQ_VALU_MFMA_BUSY_CYCLES"]) / len(d["SQ_VALU_MFMA_BUSY_CYCLES"])
+        gui = sum(d["GRBM_GUI_ACTIVE"]) / len(d["GRBM_GUI_ACTIVE"]) / 8
+        tf = flops / avg_ns[k] / 1e3
+        lines.append(f"{k:36s} {len(mops):6d} {avg_ns[k] / 1e3:10.1f} {flops / 1e9:11.1f} {tf:8.2f} "
+                     f"{peak[kind]:6.1f} {tf / peak[kind]:6.3f} {busy / (gui * 1024):9.3f}")
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main(argv):
     if argv[0] == "stats":
-        stats(argv[1], argv[2], argv[3])
+        stats(argv[1], argv[2], argv[3],
+              argv[argv.index("--kernel-hash") + 1] if "--kernel-hash" in argv else None)
+    elif argv[0] == "mfma":
+        mfma(argv[1], argv[2], argv[3], argv[4])
     elif argv[0] == "traffic":
         cb = int(argv[argv.index("--copy-bytes") + 1])
-        traffic(argv[1], argv[2], argv[3], argv[4], cb)
+        txt = argv[argv.index("--txt") + 1] if "--txt" in argv else None
+        traffic(argv[1], argv[2], argv[3], argv[4], cb, argv[argv.index("--kernel-hash") + 1], txt)
     else:
         raise SystemExit(__doc__)
 
