@@ -17,6 +17,9 @@ Prints ONE JSON line on stdout:
   serving    p50/p99 latency and circuits/s of a short Poisson request stream
   sweep      the same circuit distribution at n = 30..33 (k = 7), n = 34 at
              k = 5 and 6, and a 33-qubit complex128 state: one timed step each
+  multilevel the same circuits with the multi-level partition (first level
+             bounded by the padded LDS tile, 13 qubits complex64 / 12
+             complex128; second level = register stages)
   qft32      a 32-qubit QFT on a random basis state, k = 7 dagP partition:
              gate-by-gate (specialized) vs fused-unitary (matrix cores) vs
              AUTO, with the fused kernel's matrix-core roofline
@@ -147,6 +150,41 @@ def run_sweep(args, buf, stream, log):
     return rows
 
 
+def run_multilevel(args, buf, stream, log):
+    """Multi-level plans (Sec. IV.B): level-1 parts fill the padded LDS tile."""
+    import torch
+    from paper_2205_06973_amd import hisv
+    from paper_2205_06973_amd import workloads as wl
+    rows = []
+    cases = [("random34", 34, "c64", "dfs"), ("random33", 33, "c128", "dfs"), ("qft32", 32, "c64", "dagp")]
+    for name, n, dt, strat in cases:
+        amp = 8 if dt == "c64" else 16
+        if (1 << n) * amp > buf.numel() * buf.element_size():
+            continue
+        view = buf.view(torch.uint8)[: (1 << n) * amp].view(
+            torch.complex64 if dt == "c64" else torch.complex128)
+        st = hisv.State.wrap_tensor(view, stream)
+        st.set_basis(0)
+        gates = wl.qft_circuit(n) if name == "qft32" else wl.random34(args.seed, n=n, num_gates=args.gates)[1]
+        plan = hisv.Plan.partition_multilevel(hisv.Circuit(n, gates), strategy=strat, dtype=dt,
+                                              seed=args.seed, trials=args.trials)
+        plan.specialize(dt)
+        sec = timed_plan(st, plan, stream)
+        norm = st.norm()
+        st.close()
+        P = plan.num_parts
+        gbs = part_pass_bytes(n, dt) * P / sec / 1e9
+        row = {"workload": name, "n": n, "dtype": dt, "strategy": strat, "tile_qubits": plan.k,
+               "pad_qubits": 6, "parts": P, "gates": len(gates), "gates_per_s": len(gates) / sec,
+               "ms_per_circuit": sec * 1e3, "pass_GBps": gbs, "frac": gbs / HBM_PEAK_GBS,
+               "norm_after": norm}
+        log(f"[bench] multilevel {row}")
+        if not abs(norm - 1.0) < 1e-3:
+            raise RuntimeError(f"norm drift in multi-level case {row}")
+        rows.append(row)
+    return rows
+
+
 def run_qft(buf, stream, log):
     """32-qubit QFT (H + controlled-phase ladder + swaps) on a random basis
     state, dagP k = 7: gate-by-gate specialized kernels (a) vs the fused dense
@@ -225,6 +263,7 @@ def main() -> int:
                     help="also run the plain copy kernel on this many GiB (counter calibration)")
     ap.add_argument("--no-sweep", action="store_true", help="skip the n / k / dtype sweep")
     ap.add_argument("--no-qft", action="store_true", help="skip the 32-qubit QFT comparison")
+    ap.add_argument("--no-multilevel", action="store_true", help="skip the multi-level partition runs")
     ap.add_argument("--qft-only", action="store_true",
                     help="run only the 32-qubit QFT comparison (for kernel profiles)")
     args = ap.parse_args()
@@ -363,6 +402,8 @@ def main() -> int:
 
     if not args.no_sweep:
         out["sweep"] = run_sweep(args, buf, stream, log)
+    if not args.no_multilevel:
+        out["multilevel"] = run_multilevel(args, buf, stream, log)
     if not args.no_qft:
         out["qft32"] = run_qft(buf, stream, log)
     del buf

@@ -186,6 +186,19 @@ hs_status hs_circuit_destroy(hs_circuit c);
 hs_status hs_partition(hs_circuit c, int k, hs_strategy strategy, uint64_t seed,
                        int trials, hs_plan* out);
 
+/* Multi-level partition (Sec. IV.B, multi-level paragraph).  Level 1 cuts
+ * the DAG into acyclic parts sized for one tile of the part-pass kernels:
+ * every tile gathers qubits 0..pad_qubits-1 anyway (coalescing padding), so
+ * a part's qubits together with those number at most tile_qubits.  Level 2
+ * -- register stages inside a part -- is formed when the plan is compiled.
+ * With pad_qubits = 6 and tile_qubits = 6 + hs_max_part_qubits(dtype,
+ * PART_SPEC) every part fits the specialized kernels' tile.  The plan's k
+ * is tile_qubits and hs_plan_validate checks the padded bound.
+ * HS_E_ARITY_GT_K if a gate with the padding exceeds tile_qubits; HS_E_ARG
+ * for pad_qubits outside [0, 64] or tile_qubits < 1. */
+hs_status hs_partition_multilevel(hs_circuit c, int tile_qubits, int pad_qubits,
+                                  hs_strategy strategy, uint64_t seed, int trials, hs_plan* out);
+
 /* Build a plan from a caller-given assignment part_of_gate[count] (ids
  * 0..P-1).  HS_E_BAD_PARTITION unless it passes hs_plan_validate's checks. */
 hs_status hs_plan_from_assignment(hs_circuit c, int k, const int32_t* part_of_gate,
@@ -200,8 +213,9 @@ hs_status hs_plan_part_of_gate(hs_plan p, int32_t* out);
 hs_status hs_plan_part_info(hs_plan p, int part, uint64_t* qubit_mask, int* num_gates);
 
 /* Exact check: every gate in exactly one non-empty part, every part uses at
- * most k qubits, the part-graph is acyclic and every cross-part edge goes
- * from a lower to a higher part id.  HS_OK or HS_E_BAD_PARTITION. */
+ * most k qubits (for a multi-level plan: together with its padding qubits),
+ * the part-graph is acyclic and every cross-part edge goes from a lower to a
+ * higher part id.  HS_OK or HS_E_BAD_PARTITION. */
 hs_status hs_plan_validate(hs_plan p);
 
 /* Kernel-level layout of a part as compiled for `dtype` and `exec`

@@ -21,6 +21,11 @@ What it follows
   exceeded").
 * Sec. IV.A, condition iii: the minimum number of parts; ``brute_min_parts``
   finds it by exhaustive search for DAGs of a handful of gates.
+* Sec. IV.B, multi-level paragraph: a part smaller than the limit is topped
+  up with qubits of the enclosing level for locality.  Reading used for a
+  multi-level first level: a fixed set of padding qubits is held by every
+  part, so the bound applies to the part's qubits together with the padding
+  (``padding`` below; empty for a plain partition).
 """
 
 from __future__ import annotations
@@ -79,13 +84,14 @@ def is_acyclic(num_nodes: int, edges) -> bool:
     return seen == num_nodes
 
 
-def check_partition(n: int, gates, part_of_gate, limit: int) -> list[str]:
+def check_partition(n: int, gates, part_of_gate, limit: int, padding=()) -> list[str]:
     """Every violated condition, as text; an empty list means valid.
 
     Conditions: one part id per gate in [0, P); every id used (non-empty
-    parts); L(V_i) <= limit; the part-graph is acyclic; and, because parts
-    are executed in increasing id, every cross-part edge goes from a lower
-    to a higher id (the ids are a topological order of the part-graph).
+    parts); |L(V_i) u padding| <= limit; the part-graph is acyclic; and,
+    because parts are executed in increasing id, every cross-part edge goes
+    from a lower to a higher id (the ids are a topological order of the
+    part-graph).
     """
     errors = []
     G = len(gates)
@@ -105,7 +111,7 @@ def check_partition(n: int, gates, part_of_gate, limit: int) -> list[str]:
         if not members[p]:
             errors.append(f"part {p} is empty")
     for p in range(P):
-        ws = working_set(gates, members[p])
+        ws = working_set(gates, members[p]) | set(padding)
         if len(ws) > limit:
             errors.append(f"part {p} uses {len(ws)} qubits > {limit}")
     for g in gates:
@@ -122,16 +128,18 @@ def check_partition(n: int, gates, part_of_gate, limit: int) -> list[str]:
     return errors
 
 
-def nat_partition(gates, limit: int) -> list[int]:
-    """Natural topological order cutoff (Sec. IV.B.1)."""
+def nat_partition(gates, limit: int, padding=()) -> list[int]:
+    """Natural topological order cutoff (Sec. IV.B.1); with padding, each
+    part's qubits together with the padding qubits stay within the limit."""
     part = []
+    pad = set(padding)
     current: set[int] = set()
     pid = 0
     for g in gates:
         qs = set(gate_qubits(g))
-        if len(qs) > limit:
+        if len(qs | pad) > limit:
             raise ValueError("a gate uses more qubits than the limit")
-        if current and len(current | qs) > limit:
+        if current and len(current | qs | pad) > limit:
             pid += 1
             current = set()
         current |= qs

@@ -58,13 +58,14 @@ CompileOptions default_options(hs_dtype dtype, bool spec) {
 }
 
 hs_status plan_build(int n, const std::vector<Gate>& gates, int k,
-                     const std::vector<int32_t>& part_of_gate, Plan* p) {
+                     const std::vector<int32_t>& part_of_gate, Plan* p, uint64_t pad) {
   p->n = n;
   p->k = k;
+  p->pad = pad;
   p->gates = gates;
   p->dag = build_dag(gates);
   p->part_of_gate = part_of_gate;
-  const std::string err = check_partition(gates, p->dag, part_of_gate, k);
+  const std::string err = check_partition(gates, p->dag, part_of_gate, k, pad);
   if (!err.empty()) return fail(HS_E_BAD_PARTITION, "invalid partition: %s", err.c_str());
   int P = 0;
   for (int32_t v : part_of_gate) P = std::max(P, v + 1);
@@ -327,6 +328,39 @@ hs_status hs_partition(hs_circuit c, int k, hs_strategy strategy, uint64_t seed,
   return HS_OK;
 }
 
+// Multi-level: level 1 bounds each part together with the padding qubits
+// 0..pad_qubits-1 by the tile; level 2 (register stages) is the compile step.
+hs_status hs_partition_multilevel(hs_circuit c, int tile_qubits, int pad_qubits,
+                                  hs_strategy strategy, uint64_t seed, int trials, hs_plan* out) {
+  CHECK_ARG(c && out, "null argument");
+  CHECK_ARG(pad_qubits >= 0 && pad_qubits <= 64, "pad_qubits = %d outside [0, 64]", pad_qubits);
+  const int np = std::min(pad_qubits, c->n);
+  const uint64_t pad = np >= 64 ? ~uint64_t(0) : (uint64_t(1) << np) - 1;
+  CHECK_ARG(tile_qubits >= 1, "tile_qubits = %d < 1", tile_qubits);
+  for (const Gate& g : c->gates)
+    if (__builtin_popcountll(g.mask() | pad) > tile_qubits)
+      return fail(HS_E_ARITY_GT_K, "a gate and the %d padding qubits do not fit %d tile qubits", np,
+                  tile_qubits);
+  std::vector<int32_t> part;
+  const Dag dag = build_dag(c->gates);
+  switch (strategy) {
+    case HS_PART_NAT: partition_nat(c->gates, tile_qubits, &part, pad); break;
+    case HS_PART_DFS:
+      CHECK_ARG(trials >= 1, "DFS needs trials >= 1");
+      partition_dfs(c->gates, dag, tile_qubits, seed, trials, &part, pad);
+      break;
+    case HS_PART_DAGP: partition_dagp(c->gates, dag, c->n, tile_qubits, seed, &part, pad); break;
+    default: return fail(HS_E_ARG, "unknown strategy %d", (int)strategy);
+  }
+  auto* p = new hs_plan_();
+  if (hs_status rc = plan_build(c->n, c->gates, tile_qubits, part, p, pad)) {
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return HS_OK;
+}
+
 hs_status hs_plan_from_assignment(hs_circuit c, int k, const int32_t* part_of_gate, hs_plan* out) {
   CHECK_ARG(c && out, "null argument");
   CHECK_ARG(part_of_gate || c->gates.empty(), "null assignment");
@@ -363,7 +397,7 @@ hs_status hs_plan_part_info(hs_plan p, int part, uint64_t* qubit_mask, int* num_
 
 hs_status hs_plan_validate(hs_plan p) {
   CHECK_ARG(p, "null plan");
-  const std::string err = check_partition(p->gates, p->dag, p->part_of_gate, p->k);
+  const std::string err = check_partition(p->gates, p->dag, p->part_of_gate, p->k, p->pad);
   if (!err.empty()) return fail(HS_E_BAD_PARTITION, "invalid partition: %s", err.c_str());
   return HS_OK;
 }

@@ -51,6 +51,7 @@ struct Ctx {
   const std::vector<Gate>* gates;
   const Dag* dag;
   int n, k;
+  uint64_t pad;  // qubits every part holds anyway (multi-level tiles)
   Rng rng;
   std::vector<int> side;   // scratch: -1 outside V, 0 / 1 inside
   std::vector<int> cnt0, cnt1;
@@ -118,7 +119,7 @@ std::pair<int, int> best_prefix_cut(const Ctx& c, const std::vector<int>& ord, i
   for (int i = 1; i < N; ++i) {
     pre |= (*c.gates)[ord[i - 1]].mask();
     if (i < lo || i > hi) continue;
-    const int cost = __builtin_popcountll(pre) + __builtin_popcountll(suf[i]);
+    const int cost = __builtin_popcountll(pre & ~c.pad) + __builtin_popcountll(suf[i] & ~c.pad);
     if (cost < best_cost) {
       best_cost = cost;
       best = i;
@@ -160,6 +161,7 @@ void refine(Ctx& c, const std::vector<int>& V, int lo, int hi) {
       std::vector<int>& to = s ? c.cnt0 : c.cnt1;
       int gain = 0;
       for (int t = 0; t < nq; ++t) {
+        if (c.pad >> q[t] & 1) continue;  // held by both sides anyway
         if (from[q[t]] == 1) ++gain;  // qubit leaves the source side
         if (to[q[t]] == 0) --gain;    // qubit joins the destination side
       }
@@ -178,7 +180,7 @@ void refine(Ctx& c, const std::vector<int>& V, int lo, int hi) {
 
 void bisect_rec(Ctx& c, std::vector<int> V, int depth) {
   if (V.empty()) return;
-  if (__builtin_popcountll(mask_of(c, V)) <= c.k || V.size() == 1 || depth > 60) {
+  if (__builtin_popcountll(mask_of(c, V) | c.pad) <= c.k || V.size() == 1 || depth > 60) {
     c.parts.push_back(std::move(V));
     return;
   }
@@ -220,7 +222,7 @@ void bisect_rec(Ctx& c, std::vector<int> V, int depth) {
 }
 
 // Merge phase on the part-graph, then topological renumbering.
-int merge_and_number(const std::vector<Gate>& gates, const Dag& dag, int k,
+int merge_and_number(const std::vector<Gate>& gates, const Dag& dag, int k, uint64_t pad,
                      std::vector<std::vector<int>>& parts, std::vector<int32_t>* out) {
   const int P = (int)parts.size();
   std::vector<int> pid(gates.size());
@@ -281,12 +283,12 @@ int merge_and_number(const std::vector<Gate>& gates, const Dag& dag, int k,
       // prefer partners sharing the most qubits
       std::vector<std::pair<int, int>> cand;
       for (int b = a + 1; b < P; ++b)
-        if (alive[b] && __builtin_popcountll(mask[a] | mask[b]) <= k)
-          cand.push_back({-__builtin_popcountll(mask[a] & mask[b]), b});
+        if (alive[b] && __builtin_popcountll(mask[a] | mask[b] | pad) <= k)
+          cand.push_back({-__builtin_popcountll(mask[a] & mask[b] & ~pad), b});
       std::sort(cand.begin(), cand.end());
       for (auto [negov, b] : cand) {
         (void)negov;
-        if (!alive[b] || __builtin_popcountll(mask[a] | mask[b]) > k) continue;
+        if (!alive[b] || __builtin_popcountll(mask[a] | mask[b] | pad) > k) continue;
         if (reach_via_other(a, b) || reach_via_other(b, a)) continue;
         // merge b into a
         alive[b] = 0;
@@ -333,19 +335,19 @@ int merge_and_number(const std::vector<Gate>& gates, const Dag& dag, int k,
 }  // namespace
 
 int partition_dagp(const std::vector<Gate>& gates, const Dag& dag, int n, int k, uint64_t seed,
-                   std::vector<int32_t>* part) {
+                   std::vector<int32_t>* part, uint64_t pad) {
   // a few seeded restarts of bisection + merge; keep the fewest parts
   int best = -1;
   std::vector<int32_t> cand;
   for (int r = 0; r < 6; ++r) {
-    Ctx c{&gates, &dag, n, k, Rng((seed ^ 0xda6bull) + 7919ull * r), {}, {}, {}, {}};
+    Ctx c{&gates, &dag, n, k, pad, Rng((seed ^ 0xda6bull) + 7919ull * r), {}, {}, {}, {}};
     c.side.assign(gates.size(), -1);
     c.cnt0.assign(64, 0);
     c.cnt1.assign(64, 0);
     std::vector<int> all(gates.size());
     std::iota(all.begin(), all.end(), 0);
     if (!gates.empty()) bisect_rec(c, std::move(all), 0);
-    const int np = merge_and_number(gates, dag, k, c.parts, &cand);
+    const int np = merge_and_number(gates, dag, k, pad, c.parts, &cand);
     if (best < 0 || np < best) {
       best = np;
       part->swap(cand);

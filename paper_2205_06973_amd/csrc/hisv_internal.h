@@ -51,16 +51,19 @@ Dag build_dag(const std::vector<Gate>& gates);
 
 // Contiguous cutoff of `order` (a topological order) into parts of at most k
 // qubits; part_of_gate is indexed by gate id.  Returns the number of parts.
+// `pad` = qubits every part holds anyway (the padding of a multi-level tile):
+// a part's qubits together with them must number at most k.
 int cutoff_partition(const std::vector<Gate>& gates, const std::vector<int>& order, int k,
-                     std::vector<int32_t>* part_of_gate);
-int partition_nat(const std::vector<Gate>& gates, int k, std::vector<int32_t>* part);
+                     std::vector<int32_t>* part_of_gate, uint64_t pad = 0);
+int partition_nat(const std::vector<Gate>& gates, int k, std::vector<int32_t>* part,
+                  uint64_t pad = 0);
 int partition_dfs(const std::vector<Gate>& gates, const Dag& dag, int k, uint64_t seed,
-                  int trials, std::vector<int32_t>* part);
+                  int trials, std::vector<int32_t>* part, uint64_t pad = 0);
 int partition_dagp(const std::vector<Gate>& gates, const Dag& dag, int n, int k,
-                   uint64_t seed, std::vector<int32_t>* part);
+                   uint64_t seed, std::vector<int32_t>* part, uint64_t pad = 0);
 // Exact validity check; returns "" when valid, else the first violation.
 std::string check_partition(const std::vector<Gate>& gates, const Dag& dag,
-                            const std::vector<int32_t>& part, int k);
+                            const std::vector<int32_t>& part, int k, uint64_t pad = 0);
 
 // ---- part compilation (kernel descriptors) --------------------------------------
 struct HostOp {
@@ -125,6 +128,7 @@ struct SpecKernel;  // a part's specialized kernel (specialize.cpp)
 
 struct Plan {
   int n = 0, k = 0;
+  uint64_t pad = 0;  // multi-level plans: qubits counted in every part's bound
   std::vector<Gate> gates;
   Dag dag;
   std::vector<int32_t> part_of_gate;
@@ -144,7 +148,7 @@ struct Plan {
 };
 
 hs_status plan_build(int n, const std::vector<Gate>& gates, int k,
-                     const std::vector<int32_t>& part_of_gate, Plan* p);
+                     const std::vector<int32_t>& part_of_gate, Plan* p, uint64_t pad = 0);
 CompileOptions default_options(hs_dtype dtype, bool spec = false);
 hs_status plan_compile(Plan* p, hs_dtype dtype);
 hs_status plan_compile_spec(Plan* p, hs_dtype dtype);

@@ -38,13 +38,13 @@ Dag build_dag(const std::vector<Gate>& gates) {
 }
 
 int cutoff_partition(const std::vector<Gate>& gates, const std::vector<int>& order, int k,
-                     std::vector<int32_t>* part) {
+                     std::vector<int32_t>* part, uint64_t pad) {
   part->assign(gates.size(), -1);
   uint64_t cur = 0;
   int pid = -1;
   for (int gi : order) {
     const uint64_t m = gates[gi].mask();
-    if (pid < 0 || __builtin_popcountll(cur | m) > k) {
+    if (pid < 0 || __builtin_popcountll(cur | m | pad) > k) {
       ++pid;
       cur = 0;
     }
@@ -54,10 +54,10 @@ int cutoff_partition(const std::vector<Gate>& gates, const std::vector<int>& ord
   return pid + 1;
 }
 
-int partition_nat(const std::vector<Gate>& gates, int k, std::vector<int32_t>* part) {
+int partition_nat(const std::vector<Gate>& gates, int k, std::vector<int32_t>* part, uint64_t pad) {
   std::vector<int> order(gates.size());
   for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
-  return cutoff_partition(gates, order, k, part);
+  return cutoff_partition(gates, order, k, part, pad);
 }
 
 namespace {
@@ -106,14 +106,14 @@ void random_dfs_order(const Dag& dag, Rng& rng, std::vector<int>* order) {
 }  // namespace
 
 int partition_dfs(const std::vector<Gate>& gates, const Dag& dag, int k, uint64_t seed,
-                  int trials, std::vector<int32_t>* part) {
-  int best = partition_nat(gates, k, part);
+                  int trials, std::vector<int32_t>* part, uint64_t pad) {
+  int best = partition_nat(gates, k, part, pad);
   std::vector<int> order;
   std::vector<int32_t> cand;
   for (int t = 1; t < trials; ++t) {
     Rng rng(seed * 0x100000001B3ull + (uint64_t)t);
     random_dfs_order(dag, rng, &order);
-    const int np = cutoff_partition(gates, order, k, &cand);
+    const int np = cutoff_partition(gates, order, k, &cand, pad);
     if (np < best) {
       best = np;
       part->swap(cand);
@@ -123,7 +123,7 @@ int partition_dfs(const std::vector<Gate>& gates, const Dag& dag, int k, uint64_
 }
 
 std::string check_partition(const std::vector<Gate>& gates, const Dag& dag,
-                            const std::vector<int32_t>& part, int k) {
+                            const std::vector<int32_t>& part, int k, uint64_t pad) {
   const int G = (int)gates.size();
   if ((int)part.size() != G) return "assignment length differs from the gate count";
   if (G == 0) return "";
@@ -141,8 +141,9 @@ std::string check_partition(const std::vector<Gate>& gates, const Dag& dag,
   }
   for (int p = 0; p < P; ++p) {
     if (!cnt[p]) return "part " + std::to_string(p) + " is empty";
-    if (__builtin_popcountll(mask[p]) > k)
-      return "part " + std::to_string(p) + " uses more than k qubits";
+    if (__builtin_popcountll(mask[p] | pad) > k)
+      return "part " + std::to_string(p) + (pad ? " with the padding qubits" : "") +
+             " uses more than k qubits";
   }
   // Every cross-part edge must go from a lower to a higher id: then the ids
   // are a topological order of the part-graph, which is therefore acyclic.

@@ -44,7 +44,11 @@ def simulate(n, gates, dtype, k, strategy, mode="part_spec", init=0, extra=None)
     st = hisv.State.wrap_tensor(buf, torch.cuda.current_stream())
     st.set_basis(init)
     for gs in [gates] + ([extra] if extra else []):
-        plan = hisv.Plan.partition(hisv.Circuit(n, gs), k, strategy, seed=0, trials=32)
+        if strategy.startswith("ml-"):  # multi-level: parts fill the kernel tile
+            plan = hisv.Plan.partition_multilevel(hisv.Circuit(n, gs), strategy=strategy[3:],
+                                                  dtype=dtype, seed=0, trials=32)
+        else:
+            plan = hisv.Plan.partition(hisv.Circuit(n, gs), k, strategy, seed=0, trials=32)
         st.simulate(plan, mode)
     st.sync()
     return st, buf
@@ -103,9 +107,10 @@ def test_layered28_round_trip(dtype):
     assert report("layered28 U^-1 U", np.abs(got - want), n) <= TOL[dtype]
 
 
-def test_qft32_closed_form():
+@pytest.mark.parametrize("strategy", ["dagp", "ml-dagp"])
+def test_qft32_closed_form(strategy):
     n, gates, x = wl.qft32(0)
-    st, buf = simulate(n, gates, "c64", 7, "dagp", init=x)
+    st, buf = simulate(n, gates, "c64", 7, strategy, init=x)
     idx = sample_indices(n, 1 << 18, 4)
     want = np.exp(2j * np.pi * ((np.uint64(x) * idx) % np.uint64(1 << n)).astype(np.float64)
                   / (1 << n)) / math.sqrt(1 << n)
@@ -114,10 +119,11 @@ def test_qft32_closed_form():
     assert abs(st.norm() - 1) <= 1e-5
 
 
-@pytest.mark.parametrize("n,dtype", [(34, "c64"), (33, "c128")])
-def test_random34_product_block(n, dtype):
+@pytest.mark.parametrize("n,dtype,strategy", [(34, "c64", "dfs"), (33, "c128", "dfs"),
+                                              (34, "c64", "ml-dfs"), (33, "c128", "ml-dfs")])
+def test_random34_product_block(n, dtype, strategy):
     gates = wl.product_block_circuit(n, 1000, wl.RANDOM34_KINDS, seed=5)
-    st, buf = simulate(n, gates, dtype, 7, "dfs")
+    st, buf = simulate(n, gates, dtype, 7, strategy)
     pe, po = product_factors(n, gates)
     idx = sample_indices(n, 1 << 16, 6)
     d = np.abs(st.amplitudes_at(idx) - product_amp(idx, n, pe, po))

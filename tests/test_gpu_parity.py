@@ -199,3 +199,35 @@ def test_errors_through_the_abi():
         st.amplitudes(500, 100)
     with pytest.raises(hisv.HisvError):
         st.set_basis(1 << 9)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n,strategy", [(12, "dfs"), (14, "nat"), (17, "dagp"), (18, "dfs")])
+@pytest.mark.parametrize("mode", ["part_lds", "part_spec"])
+def test_multilevel_parity(n, strategy, mode, dtype):
+    """Multi-level plans: parts fill the widest tile (14 / 13 qubits with padding)."""
+    gates = wl.random_circuit(n, 300, ALL, seed=700 + n)
+    init = (n * 104729) % (1 << n)
+    print(f"[case] multilevel n={n} {dtype} {strategy} {mode}", flush=True)
+    plan = hisv.Plan.partition_multilevel(hisv.Circuit(n, gates), strategy=strategy, dtype=dtype,
+                                          seed=2, trials=8)
+    st = new_state(n, dtype, init)
+    st.simulate(plan, mode)
+    got = st.amplitudes()
+    st.close()
+    check(got, sv.simulate(n, gates, init), dtype)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_multilevel_qft_closed_form(dtype):
+    n = 18
+    x = wl.random_basis_index(n, 11)
+    plan = hisv.Plan.partition_multilevel(hisv.Circuit(n, wl.qft_circuit(n)), strategy="dagp",
+                                          dtype=dtype)
+    st = new_state(n, dtype, x)
+    st.simulate(plan, "part_spec")
+    got = st.amplitudes()
+    st.close()
+    y = np.arange(1 << n)
+    want = np.exp(2j * np.pi * ((x * y) % (1 << n)) / (1 << n)) / math.sqrt(1 << n)
+    check(got, want, dtype)

@@ -325,3 +325,54 @@ def test_replay_dagp_plan(dtype):
     psi0 = _random_state(n, 3)
     got, _ = replay_plan(plan, n, psi0, dtype)
     np.testing.assert_allclose(got, sv.simulate(n, gates, psi0), atol=1e-12, rtol=0)
+
+
+# ---- multi-level partition (first level bounded by the padded tile) ---------------
+
+@pytest.mark.parametrize("name,make", CIRCUITS)
+@pytest.mark.parametrize("tile,pad", [(5, 2), (8, 4), (10, 6)])
+def test_multilevel_nat_matches_oracle_exactly(name, make, tile, pad):
+    n, gates = make()
+    c = hisv.Circuit(n, gates)
+    plan = hisv.Plan.partition_multilevel(c, tile, pad, "nat")
+    padding = list(range(min(pad, n)))
+    assert plan.part_of_gate().tolist() == op.nat_partition(gates, tile, padding)
+    plan.validate()
+
+
+@pytest.mark.parametrize("name,make", CIRCUITS)
+@pytest.mark.parametrize("strategy", ["dfs", "dagp"])
+def test_multilevel_valid_and_fewer_parts(name, make, strategy):
+    n, gates = make()
+    c = hisv.Circuit(n, gates)
+    tile, pad = 10, 6
+    plan = hisv.Plan.partition_multilevel(c, tile, pad, strategy, seed=3, trials=16)
+    parts = plan.part_of_gate().tolist()
+    padding = list(range(min(pad, n)))
+    assert op.check_partition(n, gates, parts, tile, padding) == []
+    # never more parts than a plain partition bounded by the unpadded width
+    plain = hisv.Plan.partition(c, tile - pad, strategy, seed=3, trials=16)
+    assert plan.num_parts <= plain.num_parts
+
+
+def test_multilevel_errors():
+    c = hisv.Circuit(8, [("cx", 5, 6, ())])
+    with pytest.raises(hisv.HisvError) as e:
+        hisv.Plan.partition_multilevel(c, 4, 3, "nat")
+    assert e.value.code == "HS_E_ARITY_GT_K"
+    with pytest.raises(hisv.HisvError) as e:
+        hisv.Plan.partition_multilevel(c, 8, 65, "nat")
+    assert e.value.code == "HS_E_ARG"
+
+
+@pytest.mark.parametrize("n,dtype", [(14, "c64"), (15, "c128"), (16, "c64")])
+def test_replay_multilevel_specialized(n, dtype):
+    """Multi-level parts fill the widest tile; replay its descriptors on the host."""
+    gates = wl.random_circuit(n, 160, sv.ONE_QUBIT + sv.TWO_QUBIT, seed=500 + n)
+    plan = hisv.Plan.partition_multilevel(hisv.Circuit(n, gates), strategy="dfs", dtype=dtype,
+                                          seed=1, trials=8)
+    psi0 = _random_state(n, 3)
+    got, facts = replay_plan(plan, n, psi0, dtype, "part_spec")
+    np.testing.assert_allclose(got, sv.simulate(n, gates, psi0), atol=1e-12, rtol=0)
+    assert plan.k == (13 if dtype == "c64" else 12)
+    assert max(f["m"] for f in facts) == min(n, plan.k)

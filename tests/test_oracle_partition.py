@@ -80,3 +80,27 @@ def test_nat_large_random_valid():
     for k in (3, 5, 7):
         parts = op.nat_partition(gates, k)
         assert op.check_partition(n, gates, parts, k) == []
+
+
+def test_nat_padded_examples(golden_dir):
+    """Multi-level first level: the padding qubits count toward every part."""
+    with open(os.path.join(golden_dir, "nat_padded_examples.json")) as f:
+        d = json.load(f)
+    for case in d["cases"]:
+        gates = _gates(case["gates"])
+        got = op.nat_partition(gates, case["limit"], case["padding"])
+        assert got == case["parts"]
+        assert op.check_partition(8, gates, got, case["limit"], case["padding"]) == []
+        if "parts_without_padding" in case:
+            assert op.nat_partition(gates, case["limit"]) == case["parts_without_padding"]
+    tw = d["too_wide"]
+    with pytest.raises(ValueError):
+        op.nat_partition(_gates([tw["gate"]]), tw["limit"], tw["padding"])
+
+
+def test_checker_counts_padding():
+    gates = [("h", 2, -1, ()), ("cx", 2, 3, ())]
+    # {2} u {0,1} = 3 qubits; {2,3} u {0,1} = 4
+    assert op.check_partition(4, gates, [0, 0], 4, padding=(0, 1)) == []
+    assert any("qubits >" in e for e in op.check_partition(4, gates, [0, 0], 3, padding=(0, 1)))
+    assert op.check_partition(4, gates, [0, 0], 3) == []
