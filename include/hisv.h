@@ -135,7 +135,10 @@ hs_status hs_device_count(int* out);
  * XCDs sweeps one contiguous eighth of the tiles; "grid" = 0 for one
  * workgroup per tile, g in 1..64 for a persistent grid of g x the resident
  * workgroups per CU; "spec_prefetch" (0/1) = a persistent grid of the
- * specialized kernels keeps the next tile's loads in flight.  A "spec_"
+ * specialized kernels keeps the next tile's loads in flight;
+ * "spec_lds_limit_kib" (16..160, default 64) = the specialized kernels run
+ * each LDS re-layout in 2 or 4 rounds, over half or a quarter of the tile,
+ * when the tile's LDS image is larger.  A "spec_"
  * prefix on a key sets it for the specialized kernels (PART_SPEC) instead of
  * the interpreter kernel ("contig" has no prefix: it applies to both).
  * HS_E_ARG for an unknown key or value. */

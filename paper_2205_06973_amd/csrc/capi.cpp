@@ -30,11 +30,13 @@ Plan::~Plan() {
 
 // Tunable knobs (hs_tune), read when a plan is compiled.  Register bits per
 // lane: the interpreter kernel keeps the sub-state plus dispatch temporaries
-// and the prefetched next tile in 128 VGPRs (complex64: 2^4, complex128: 2^3
-// amplitudes); the specialized kernels, one workgroup per tile, measured
-// best at the same widths.
+// in at most 128 VGPRs (complex64: 2^4, complex128: 2^3 amplitudes).  The
+// specialized kernels hold 2^5 / 2^4: the widest tiles (14 / 13 qubits) then
+// take 512 threads, so two workgroups share a CU (1024-thread workgroups of
+// the narrower widths measured 15-20% slower per pass); k <= 7 parts run at
+// the same rate either way.
 static std::mutex g_tune_mu;
-static int g_rb[2][2] = {{4, 3}, {4, 3}};     // [specialized][dtype]
+static int g_rb[2][2] = {{4, 3}, {5, 4}};     // [specialized][dtype]
 static int g_contig = 6;
 static int g_min_run[2][2] = {{4, 4}, {3, 3}};  // [specialized][dtype]
 // [specialized]: both paths default to one workgroup per tile, XCD-contiguous
@@ -168,6 +170,9 @@ hs_status hs_tune(const char* key, int value) {
   } else if (k == "xcd" || (k == "prefetch" && spec)) {
     CHECK_ARG(value == 0 || value == 1, "%s must be 0 or 1", k.c_str());
     (k == "xcd" ? g_launch[spec].xcd : g_launch[spec].prefetch) = value != 0;
+  } else if (k == "lds_limit_kib" && spec) {
+    CHECK_ARG(value >= 16 && value <= 160, "lds_limit_kib must be 16..160");
+    g_launch[spec].lds_limit = (size_t)value * 1024;
   } else if (k == "grid") {
     CHECK_ARG(value >= 0 && value <= 64, "grid must be 0 (one workgroup per tile) or 1..64");
     g_launch[spec].per_cu = value;

@@ -63,8 +63,14 @@ Layout make_layout(int m, int lb, int wb, uint32_t regs) {
   return L;
 }
 
-// Pad `regs` to exactly rb tile bits with the highest free tile bits.
-uint32_t pad_regs(uint32_t regs, int m, int rb) {
+// Pad `regs` to exactly rb tile bits: first with bits of `keep` (the
+// previous layout's register bits, highest first), then with the highest
+// free tile bits.  Keeping register bits across stages lets consecutive
+// layouts coincide (no re-layout) or share a register bit (a re-layout can
+// then run in two halves through half the LDS).
+uint32_t pad_regs(uint32_t regs, int m, int rb, uint32_t keep = 0) {
+  for (int t = m - 1; t >= 0 && __builtin_popcount(regs) < rb; --t)
+    if (keep >> t & 1) regs |= 1u << t;
   for (int t = m - 1; t >= 0 && __builtin_popcount(regs) < rb; --t) regs |= 1u << t;
   return regs;
 }
@@ -189,7 +195,12 @@ hs_status compile_part(int n, const std::vector<Gate>& pg, const CompileOptions&
   out->ops.clear();
 
   std::vector<Layout> lay;
-  for (const Stage& s : st) lay.push_back(make_layout(m, lb, wb, pad_regs(s.bits, m, rb)));
+  uint32_t prev_regs = pad_regs(0u, m, rb);  // the registers of a fresh load layout
+  for (const Stage& s : st) {
+    const uint32_t regs = pad_regs(s.bits, m, rb, prev_regs);
+    lay.push_back(make_layout(m, lb, wb, regs));
+    prev_regs = regs;
+  }
   // load and store layouts: lanes on tile bits 0..lb-1 (contiguous global runs)
   auto io_layout = [&](const Layout& near) {
     if (lanes_are_low(near, lb) || low_run(near, lb) >= std::min(opt.min_run, lb)) return near;

@@ -80,6 +80,9 @@ struct LaunchShape {
   int per_cu = 0;         // 0: one workgroup per tile; g > 0: a persistent grid of
                           // g x (resident workgroups per CU) x CUs
   bool prefetch = false;  // persistent grid: keep the next tile's loads in flight
+  // specialized kernels: LDS re-layouts run in 2 or 4 rounds when the tile's
+  // LDS image exceeds this many bytes (two workgroups then share a CU)
+  size_t lds_limit = 65536;
 };
 
 struct CompiledPart {

@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
+#include <algorithm>
 #include <cinttypes>
 #include <cmath>
 #include <cstring>
@@ -188,28 +189,98 @@ void emit_io(Emit& E, const StageDesc& e, const PartDesc& d, bool store, const c
   }
 }
 
-void emit_transition(Emit& E, const StageDesc& from, const StageDesc& to, const PartDesc& d, int sw) {
+// Tile bits removed from LDS indices when a re-layout runs in 2^s rounds:
+// round h moves only the amplitudes whose split bits equal h, so the LDS
+// holds 2^(m-s) amplitudes.  Any tile bit can split: as a register bit of a
+// layout it selects half of each thread's registers, as a wave or lane bit
+// half of the threads.  Register bits are cheapest (no idle threads), then
+// wave bits (whole wavefronts wait), then lane bits.
+std::vector<int> split_bits(const StageDesc& from, const StageDesc& to, const PartDesc& d, int s) {
+  auto cost = [&](const StageDesc& e, int t) {
+    for (int c = 0; c < d.m; ++c)
+      if (e.pos[c] == t) return c >= d.lb + d.wb ? 0 : (c >= d.lb ? 1 : 2);
+    return 3;
+  };
+  std::vector<std::pair<int, int>> cand;
+  for (int t = 0; t < d.m; ++t) cand.push_back({cost(from, t) + cost(to, t), -t});
+  std::sort(cand.begin(), cand.end());
+  std::vector<int> out;
+  for (int i = 0; i < s && i < (int)cand.size(); ++i) out.push_back(-cand[i].second);
+  std::sort(out.begin(), out.end());
+  return out;
+}
+
+// tile index with the split bits removed
+uint32_t compress(uint32_t x, const std::vector<int>& sb) {
+  for (int i = (int)sb.size() - 1; i >= 0; --i) {
+    const int t = sb[i];
+    x = (x & ((1u << t) - 1u)) | ((x >> (t + 1)) << t);
+  }
+  return x;
+}
+
+void emit_transition(Emit& E, const StageDesc& from, const StageDesc& to, const PartDesc& d, int sw,
+                     int nsplit) {
   auto& o = E.o;
   const int N = 1 << E.rb;
+  const int tb = d.lb + d.wb;
+  const std::vector<int> sb = split_bits(from, to, d, nsplit);
+  auto is_split = [&](int t) { return std::find(sb.begin(), sb.end(), t) != sb.end(); };
+  auto cpos = [&](int t) {
+    int c = t;
+    for (int b : sb) c -= b < t;
+    return c;
+  };
+  // LDS slot of this thread's coordinates (split bits dropped)
   auto thread_slot = [&](const StageDesc& e, const char* name) {
     o << "    const unsigned " << name << " = sl(0u";
-    for (int c = 0; c < d.lb + d.wb; ++c)
-      o << " | (((thr >> " << c << ") & 1u) << " << (int)e.pos[c] << ")";
+    for (int c = 0; c < tb; ++c)
+      if (!is_split(e.pos[c]))
+        o << " | (((thr >> " << c << ") & 1u) << " << cpos(e.pos[c]) << ")";
     o << ");\n";
+  };
+  // condition on this thread's coordinates for round h ("" = always)
+  auto thread_cond = [&](const StageDesc& e, int h) {
+    std::string c;
+    for (int i = 0; i < (int)sb.size(); ++i)
+      for (int k = 0; k < tb; ++k)
+        if (e.pos[k] == sb[i])
+          c += (c.empty() ? "" : " && ") + std::string("((thr >> ") + std::to_string(k) + ") & 1u) == " +
+               std::to_string(h >> i & 1) + "u";
+    return c;
+  };
+  // does register j of layout e belong to round h?
+  auto reg_in_round = [&](const StageDesc& e, int j, int h) {
+    for (int i = 0; i < (int)sb.size(); ++i)
+      for (int r = 0; r < E.rb; ++r)
+        if (e.pos[tb + r] == sb[i] && (j >> r & 1) != (h >> i & 1)) return false;
+    return true;
   };
   o << "    {\n";
   thread_slot(from, "wb_");
-  o << "    __syncthreads();\n";
-  if (d.lb < 6) o << "    if (active) {\n";
-  for (int j = 0; j < N; ++j)
-    o << "      lds[wb_ ^ " << slot(reg_tile_offset(from, d.lb, d.wb, E.rb, j), sw) << "u] = make_v(ar" << j
-      << ", ai" << j << ");\n";
-  if (d.lb < 6) o << "    }\n";
-  o << "    __syncthreads();\n";
   thread_slot(to, "rb_");
-  for (int j = 0; j < N; ++j)
-    o << "      { const V v = lds[rb_ ^ " << slot(reg_tile_offset(to, d.lb, d.wb, E.rb, j), sw)
-      << "u]; ar" << j << " = v.x; ai" << j << " = v.y; }\n";
+  const std::string dst = sb.empty() ? "a" : "n";
+  for (int h = 0; h < (1 << sb.size()); ++h) {
+    o << "    __syncthreads();\n";
+    std::string wc = thread_cond(from, h);
+    if (d.lb < 6) wc = wc.empty() ? "active" : "active && " + wc;
+    o << "    if (" << (wc.empty() ? "true" : wc) << ") {\n";
+    for (int j = 0; j < N; ++j)
+      if (reg_in_round(from, j, h))
+        o << "      lds[wb_ ^ " << slot(compress(reg_tile_offset(from, d.lb, d.wb, E.rb, j), sb), sw)
+          << "u] = make_v(ar" << j << ", ai" << j << ");\n";
+    o << "    }\n    __syncthreads();\n";
+    const std::string rc = thread_cond(to, h);
+    o << "    if (" << (rc.empty() ? "true" : rc) << ") {\n";
+    for (int j = 0; j < N; ++j)
+      if (reg_in_round(to, j, h))
+        o << "      { const V v = lds[rb_ ^ "
+          << slot(compress(reg_tile_offset(to, d.lb, d.wb, E.rb, j), sb), sw) << "u]; " << dst << "r"
+          << j << " = v.x; " << dst << "i" << j << " = v.y; }\n";
+    o << "    }\n";
+  }
+  if (!sb.empty())
+    for (int j = 0; j < N; ++j) o << "    ar" << j << " = nr" << j << "; ai" << j << " = ni" << j << ";\n";
   o << "    }\n";
 }
 
@@ -225,6 +296,14 @@ std::string specialize_part_source(const CompiledPart& cp, hs_dtype dt, const st
   const int ne = (int)cp.stages.size();
   auto& o = E.o;
   const std::string T = E.T();
+  const bool pf = cp.launch.prefetch && cp.launch.per_cu > 0;
+  // LDS re-layouts run in 2^nsplit rounds so that the tile's LDS image stays
+  // within the limit (more workgroups per CU)
+  const size_t vbytes = E.f32 ? 8 : 16;
+  int nsplit = 0;
+  while (cp.lds_round_trips && ((size_t(1) << (d.m - nsplit)) * vbytes) > cp.launch.lds_limit &&
+         nsplit < 2)
+    ++nsplit;
   // hipRTC predefines the HIP language keywords; an offline hipcc build of
   // the same source (used to inspect it) takes them from the runtime header
   o << "#ifndef __HIPCC_RTC__\n#include <hip/hip_runtime.h>\n#endif\n";
@@ -235,7 +314,7 @@ std::string specialize_part_source(const CompiledPart& cp, hs_dtype dt, const st
     << "; while (h) { f ^= h & " << ((1 << sw) - 1) << "u; h >>= " << sw << "; } return t ^ f; }\n";
   o << "extern \"C\" __global__ void __launch_bounds__(" << (64 << d.wb) << ") " << name
     << "(V* __restrict__ st, unsigned long long tiles, unsigned xcd) {\n";
-  if (cp.lds_round_trips) o << "  __shared__ V lds[" << (1u << d.m) << "];\n";
+  if (cp.lds_round_trips) o << "  __shared__ V lds[" << (1u << (d.m - nsplit)) << "];\n";
   o << "  const unsigned lane = threadIdx.x & 63u;\n"
     << "  const unsigned wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);\n"
     << "  const unsigned thr = lane | (wave << " << d.lb << ");\n"
@@ -243,8 +322,7 @@ std::string specialize_part_source(const CompiledPart& cp, hs_dtype dt, const st
     << "  (void)thr; (void)active;\n";
   o << "  " << T << " ";
   for (int j = 0; j < N; ++j) o << "ar" << j << ", ai" << j << (j + 1 < N ? ", " : ";\n");
-  const bool pf = cp.launch.prefetch && cp.launch.per_cu > 0;
-  if (pf) {
+  if (pf || nsplit) {
     o << "  " << T << " ";
     for (int j = 0; j < N; ++j) o << "nr" << j << ", ni" << j << (j + 1 < N ? ", " : ";\n");
   }
@@ -290,7 +368,7 @@ std::string specialize_part_source(const CompiledPart& cp, hs_dtype dt, const st
   }
   for (int s = 1; s < ne; ++s) {
     const StageDesc& e = cp.stages[s];
-    if (e.transition) emit_transition(E, cp.stages[s - 1], e, d, sw);
+    if (e.transition) emit_transition(E, cp.stages[s - 1], e, d, sw, nsplit);
     for (int i = e.op_begin; i < e.op_end; ++i) emit_op(E, cp.ops[i]);
   }
   o << "    if (active) {\n"

@@ -208,13 +208,10 @@ class Plan:
                              pad_qubits: int = 6, strategy: str = "dfs", seed: int = 0,
                              trials: int = 32, dtype: str = "c64") -> "Plan":
         """Parts whose qubits together with qubits 0..pad_qubits-1 number at
-        most tile_qubits.  Default: the widest tile whose LDS image is at most
-        64 KiB, so two workgroups share a CU (13 qubits complex64, 12
-        complex128); a 128 KiB tile leaves one workgroup per CU and measured
-        ~30% slower per pass."""
+        most tile_qubits.  Default: the widest tile of the specialized kernels
+        for dtype (14 qubits complex64, 13 complex128)."""
         if tile_qubits is None:
-            tile_qubits = min(pad_qubits + hs_max_part_qubits(dtype, "part_spec"),
-                              13 if dtype == "c64" else 12)
+            tile_qubits = pad_qubits + hs_max_part_qubits(dtype, "part_spec")
         h = _vp()
         _call("hs_partition_multilevel", circuit.handle, int(tile_qubits), int(pad_qubits),
               STRATEGIES[strategy], int(seed), int(trials), C.byref(h))

@@ -231,3 +231,25 @@ def test_multilevel_qft_closed_form(dtype):
     y = np.arange(1 << n)
     want = np.exp(2j * np.pi * ((x * y) % (1 << n)) / (1 << n)) / math.sqrt(1 << n)
     check(got, want, dtype)
+
+
+@pytest.mark.parametrize("dtype,tile", [("c64", 14), ("c128", 13)])
+@pytest.mark.parametrize("lds_kib", [64, 16])
+@pytest.mark.parametrize("n,strategy", [(15, "dfs"), (18, "dagp")])
+def test_split_relayout_parity(n, strategy, dtype, tile, lds_kib):
+    """Widest tiles, with LDS re-layouts run in 2 (64 KiB limit) or 4 (16 KiB)
+    rounds over a quarter or half of the tile."""
+    gates = wl.random_circuit(n, 300, ALL, seed=900 + n + tile)
+    init = (n * 7) % (1 << n)
+    print(f"[case] split n={n} {dtype} tile={tile} lds={lds_kib}KiB {strategy}", flush=True)
+    hisv.hs_tune("spec_lds_limit_kib", lds_kib)
+    try:
+        plan = hisv.Plan.partition_multilevel(hisv.Circuit(n, gates), tile, 6, strategy, seed=4,
+                                              trials=8)
+        st = new_state(n, dtype, init)
+        st.simulate(plan, "part_spec")
+        got = st.amplitudes()
+        st.close()
+    finally:
+        hisv.hs_tune("spec_lds_limit_kib", 64)
+    check(got, sv.simulate(n, gates, init), dtype)

@@ -374,5 +374,5 @@ def test_replay_multilevel_specialized(n, dtype):
     psi0 = _random_state(n, 3)
     got, facts = replay_plan(plan, n, psi0, dtype, "part_spec")
     np.testing.assert_allclose(got, sv.simulate(n, gates, psi0), atol=1e-12, rtol=0)
-    assert plan.k == (13 if dtype == "c64" else 12)
+    assert plan.k == (14 if dtype == "c64" else 13)
     assert max(f["m"] for f in facts) == min(n, plan.k)
