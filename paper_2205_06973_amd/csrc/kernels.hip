@@ -389,8 +389,14 @@ __device__ __forceinline__ uint64_t deposit(uint32_t v, const int8_t* q, int cou
 // l, U[16 rb + l % 16][4 ks + l / 16]; the real parts of all fragments come
 // first, then the imaginary parts.  For w <= 5 a wave keeps all of U in
 // registers; wider U (64x64, 128x128) is read fragment by fragment from the
-// L2-resident copy -- one contiguous 256-byte wave load per fragment, against
-// four matrix-core products that take far longer.
+// L2-resident copy -- one contiguous 256-byte wave load per fragment.  In
+// FP32 a wave then takes two tiles (32 columns) so that each fragment feeds
+// eight matrix-core products, halving the L2 traffic for U.
+template <typename T, int W>
+constexpr int fused_tiles_per_wave() {
+  return (W >= 6 && sizeof(T) == 4) ? 2 : 1;
+}
+
 template <typename T, int W>
 __global__ void __launch_bounds__(256)
 fused_pass_kernel(cplx<T>* __restrict__ st, const FusedDesc* __restrict__ fd, const T* __restrict__ umat,
@@ -401,6 +407,7 @@ fused_pass_kernel(cplx<T>* __restrict__ st, const FusedDesc* __restrict__ fd, co
   constexpr int KS = R / 4;   // K steps of 4
   constexpr int NF = RBK * KS;
   constexpr bool kRegU = W <= 5;
+  constexpr int CG = fused_tiles_per_wave<T, W>();
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t i16 = lane & 15, g4 = lane >> 4;
   const int m = fd->m;
@@ -431,9 +438,10 @@ fused_pass_kernel(cplx<T>* __restrict__ st, const FusedDesc* __restrict__ fd, co
   uint64_t row_ld[KS];
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks) row_ld[ks] = deposit(4 * ks, fd->sq, W);
-  // a workgroup's 4 waves take 4 consecutive tiles; with xcd set (grid and
-  // group count multiples of 8) XCD x = blockIdx % 8 sweeps a contiguous run
-  const uint64_t groups = (tiles + 3) >> 2;
+  // a workgroup's 4 waves take 4 * CG consecutive tiles; with xcd set (grid
+  // and group count multiples of 8) XCD x = blockIdx % 8 sweeps a contiguous
+  // run
+  const uint64_t groups = (tiles + 4 * CG - 1) / (4 * CG);
   uint64_t g = blockIdx.x, step = gridDim.x, end = groups;
   if (xcd) {
     const uint64_t per = groups >> 3;
@@ -443,19 +451,31 @@ fused_pass_kernel(cplx<T>* __restrict__ st, const FusedDesc* __restrict__ fd, co
     end = (x + 1) * per;
   }
   for (; g < end; g += step) {
-    const uint64_t tile = g * 4 + (threadIdx.x >> 6);
-    if (tile >= tiles) continue;
-    const uint64_t base = tile_base(tile, fd->tq, m);
-    T xr[KS], xi[KS];
+    const uint64_t tile0 = (g * 4 + (threadIdx.x >> 6)) * CG;
+    if (tile0 >= tiles) continue;
+    uint64_t base[CG];
+    bool valid[CG];
+    T xr[CG][KS], xi[CG][KS];
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const cplx<T> v = st[base + row_ld[ks] + lane_ld];
-      xr[ks] = v.x;
-      xi[ks] = v.y;
+    for (int c = 0; c < CG; ++c) {
+      valid[c] = tile0 + c < tiles;
+      base[c] = valid[c] ? tile_base(tile0 + c, fd->tq, m) : 0;
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        cplx<T> v = {0, 0};
+        if (valid[c]) v = st[base[c] + row_ld[ks] + lane_ld];
+        xr[c][ks] = v.x;
+        xi[c][ks] = v.y;
+      }
     }
 #pragma unroll(kRegU ? RBK : 1)
     for (int rb = 0; rb < RBK; ++rb) {
-      v4 yr = {0, 0, 0, 0}, yi = {0, 0, 0, 0};
+      v4 yr[CG], yi[CG];
+#pragma unroll
+      for (int c = 0; c < CG; ++c) {
+        yr[c] = v4{0, 0, 0, 0};
+        yi[c] = v4{0, 0, 0, 0};
+      }
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
         T ar, ai, nai;
@@ -469,17 +489,24 @@ fused_pass_kernel(cplx<T>* __restrict__ st, const FusedDesc* __restrict__ fd, co
           ai = Ui[f * 64 + lane];
           nai = -ai;
         }
-        yr = Mfma<T>::mma(ar, xr[ks], yr);
-        yr = Mfma<T>::mma(nai, xi[ks], yr);
-        yi = Mfma<T>::mma(ar, xi[ks], yi);
-        yi = Mfma<T>::mma(ai, xr[ks], yi);
+#pragma unroll
+        for (int c = 0; c < CG; ++c) {
+          yr[c] = Mfma<T>::mma(ar, xr[c][ks], yr[c]);
+          yr[c] = Mfma<T>::mma(nai, xi[c][ks], yr[c]);
+          yi[c] = Mfma<T>::mma(ar, xi[c][ks], yi[c]);
+          yi[c] = Mfma<T>::mma(ai, xr[c][ks], yi[c]);
+        }
       }
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        cplx<T> o;
-        o.x = yr[v];
-        o.y = yi[v];
-        st[base + deposit(16 * rb + (f64 ? 4 * v : v), fd->sq, W) + lane_st] = o;
+      for (int c = 0; c < CG; ++c) {
+        if (!valid[c]) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          cplx<T> o;
+          o.x = yr[c][v];
+          o.y = yi[c][v];
+          st[base[c] + deposit(16 * rb + (f64 ? 4 * v : v), fd->sq, W) + lane_st] = o;
+        }
       }
     }
   }
@@ -947,8 +974,15 @@ static hs_status upload_fused(Plan* p, DevicePlan* dp) {
             mats.push_back((T)(part_im ? z.imag() : z.real()));
           }
     fds.push_back(d);
-    // one workgroup of four wavefronts per four tiles, XCD-contiguous runs
-    const uint64_t groups = (f.tiles + 3) / 4;
+    // one workgroup of four wavefronts per 4 * (tiles per wave) tiles,
+    // XCD-contiguous runs
+    uint64_t per_wg = 4;
+    switch (f.w) {
+      case 6: per_wg *= fused_tiles_per_wave<T, 6>(); break;
+      case 7: per_wg *= fused_tiles_per_wave<T, 7>(); break;
+      default: break;
+    }
+    const uint64_t groups = (f.tiles + per_wg - 1) / per_wg;
     uint64_t g = std::max<uint64_t>(1, std::min<uint64_t>(groups, (uint64_t(1) << 31) / 256));
     uint8_t x = 0;
     if (groups % 8 == 0 && g >= 8) {
