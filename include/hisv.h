@@ -128,7 +128,7 @@ hs_status hs_device_count(int* out);
  * keep theirs): "rb_c64" / "rb_c128" = register bits per lane (2^rb
  * amplitudes each; 1..4 / 1..3 for the interpreter kernel, 1..5 for the
  * specialized kernels); "contig" = the tile always holds qubits 0..contig-1
- * (0..6); "min_run_c64" / "min_run_c128" = gather and scatter straight in a
+ * (0..8, default 6); "min_run_c64" / "min_run_c128" = gather and scatter straight in a
  * stage's layout when its lanes still cover qubits 0..min_run-1, instead of
  * re-laying out through LDS (0..6; 6 = only fully contiguous 64-amplitude
  * runs).  Launch shape of the part kernels: "xcd" (0/1) = each of the 8

@@ -162,7 +162,7 @@ hs_status hs_tune(const char* key, int value) {
     CHECK_ARG(value >= 1 && value <= hi, "register bits must be 1..%d", hi);
     g_rb[spec][k == "rb_c64" ? 0 : 1] = value;
   } else if (k == "contig" && !spec) {
-    CHECK_ARG(value >= 0 && value <= 6, "contig must be 0..6");
+    CHECK_ARG(value >= 0 && value <= 8, "contig must be 0..8");
     g_contig = value;
   } else if (k == "min_run_c64" || k == "min_run_c128") {
     CHECK_ARG(value >= 0 && value <= 6, "min_run must be 0..6");
