@@ -19,7 +19,9 @@ Prints ONE JSON line on stdout:
   gate_per_pass  the same GPU, one sweep per gate, on the circuit's first gates
   serving    p50/p99 latency and circuits/s of a short Poisson request stream
   sweep      the same circuit distribution at n = 30..33 (k = 7), n = 34 at
-             k = 5 and 6, and a 33-qubit complex128 state: one timed step each
+             k = 5 and 6, a 33-qubit complex128 state, and the largest states
+             that fit (35-qubit complex64, 34-qubit complex128; 256 GiB):
+             one timed step each
   multilevel the same circuits with the multi-level partition (first level
              bounded by the padded LDS tile, 13 qubits complex64 / 12
              complex128; second level = register stages)
@@ -124,7 +126,8 @@ def run_sweep(args, buf, stream, log):
     from paper_2205_06973_amd import hisv
     from paper_2205_06973_amd import workloads as wl
     cases = [(30, "c64", 7), (31, "c64", 7), (32, "c64", 7), (33, "c64", 7),
-             (34, "c64", 5), (34, "c64", 6), (33, "c128", 7)]
+             (34, "c64", 5), (34, "c64", 6), (33, "c128", 7),
+             (35, "c64", 7), (34, "c128", 7)]  # the last two: 256 GiB states
     rows = []
     for n, dt, k in cases:
         amp = 8 if dt == "c64" else 16
@@ -416,12 +419,23 @@ def main() -> int:
 
     st.close()
 
-    if not args.no_sweep:
-        out["sweep"] = run_sweep(args, buf, stream, log)
-    if not args.no_multilevel:
-        out["multilevel"] = run_multilevel(args, buf, stream, log)
-    if not args.no_qft:
-        out["qft32"] = run_qft(buf, stream, log)
+    if not (args.no_sweep and args.no_multilevel and args.no_qft):
+        # the extra sections share one buffer: 256 GiB (a 35-qubit complex64 or
+        # 34-qubit complex128 state) when the device has room, else the
+        # headline's
+        big = None
+        if torch.cuda.mem_get_info()[0] + buf.numel() * buf.element_size() >= (256 << 30) + (4 << 30):
+            del buf
+            torch.cuda.empty_cache()
+            with torch.cuda.stream(stream):
+                big = torch.empty(1 << 35, dtype=torch.complex64, device="cuda")
+            buf = big
+        if not args.no_sweep:
+            out["sweep"] = run_sweep(args, buf, stream, log)
+        if not args.no_multilevel:
+            out["multilevel"] = run_multilevel(args, buf, stream, log)
+        if not args.no_qft:
+            out["qft32"] = run_qft(buf, stream, log)
     del buf
     torch.cuda.empty_cache()
 

@@ -131,6 +131,23 @@ def test_random34_product_block(n, dtype, strategy):
     assert abs(st.norm() - 1) <= (1e-5 if dtype == "c64" else 1e-12)
 
 
+@pytest.mark.parametrize("n,dtype", [(35, "c64"), (34, "c128")])
+def test_largest_state_round_trip(n, dtype):
+    """The largest power-of-two states that fit 288 GB of HBM (256 GiB)."""
+    if torch.cuda.mem_get_info()[0] < (1 << n) * (8 if dtype == "c64" else 16) + (4 << 30):
+        pytest.skip("device memory below the 256 GiB state plus 4 GiB headroom")
+    _, gates = wl.random34(1, n=n, num_gates=200)
+    st, buf = simulate(n, gates, dtype, 7, "dfs", extra=sv.inverse_circuit(gates))
+    idx = sample_indices(n, 1 << 14, 8)
+    got = st.amplitudes_at(idx)
+    want = np.zeros(idx.size, dtype=np.complex128)
+    want[idx == 0] = 1.0
+    assert report(f"random{n} {dtype} U^-1 U", np.abs(got - want), n) <= TOL[dtype]
+    assert abs(st.norm() - 1) <= (1e-5 if dtype == "c64" else 1e-12)
+    st.close()
+    del buf
+
+
 @pytest.mark.parametrize("n,dtype", [(34, "c64"), (33, "c128")])
 def test_random34_round_trip(n, dtype):
     _, gates = wl.random34(0, n=n)
