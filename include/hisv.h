@@ -167,6 +167,10 @@ hs_status hs_state_wrap(int n, hs_dtype dtype, void* dev_ptr, size_t bytes,
 hs_status hs_state_set_basis(hs_state s, uint64_t x);
 
 hs_status hs_state_info(hs_state s, int* n, hs_dtype* dtype, void** dev_ptr);
+
+/* Wait for the state's stream, free library-owned memory and the handle.
+ * The handle is gone even on error; HS_E_HIP reports a failed wait or free
+ * (work enqueued on the state did not complete). */
 hs_status hs_state_destroy(hs_state s);
 
 /* ---- circuits (Sec. II.B: a sequence of gates) ----------------------------- */

@@ -223,7 +223,7 @@ hs_status hs_state_create(int n, hs_dtype dtype, void* hip_stream, hs_state* out
   if (hs_status rc = new_state(n, dtype, hip_stream, &s)) return rc;
   hipError_t e = hipMalloc(&s->ptr, s->bytes);
   if (e != hipSuccess) {
-    hipGetLastError();
+    (void)hipGetLastError();  // clear the sticky error of the failed allocation
     delete s;
     return fail(HS_E_NOMEM, "hipMalloc(%zu): %s", (size_t(1) << n) * amp_bytes(dtype),
                 hipGetErrorString(e));
@@ -265,12 +265,21 @@ hs_status hs_state_info(hs_state s, int* n, hs_dtype* dtype, void** dev_ptr) {
 
 hs_status hs_state_destroy(hs_state s) {
   if (!s) return HS_OK;
-  hipSetDevice(s->device);
-  if (s->stream) hipStreamSynchronize((hipStream_t)s->stream);
-  else hipDeviceSynchronize();
-  if (s->owned && s->ptr) hipFree(s->ptr);
-  if (s->scratch) hipFree(s->scratch);
+  // release everything even if the device reports an error; report the
+  // first one (a failed wait means work on the state did not complete)
+  hipError_t e = hipSetDevice(s->device);
+  const hipError_t w = s->stream ? hipStreamSynchronize((hipStream_t)s->stream) : hipDeviceSynchronize();
+  if (e == hipSuccess) e = w;
+  if (s->owned && s->ptr) {
+    const hipError_t f = hipFree(s->ptr);
+    if (e == hipSuccess) e = f;
+  }
+  if (s->scratch) {
+    const hipError_t f = hipFree(s->scratch);
+    if (e == hipSuccess) e = f;
+  }
   delete s;
+  if (e != hipSuccess) return fail(HS_E_HIP, "state teardown: %s", hipGetErrorString(e));
   return HS_OK;
 }
 

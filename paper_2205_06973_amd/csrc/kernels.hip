@@ -468,7 +468,8 @@ fused_pass_kernel(cplx<T>* __restrict__ st, const FusedDesc* __restrict__ fd, co
         xi[c][ks] = v.y;
       }
     }
-#pragma unroll(kRegU ? RBK : 1)
+    constexpr int kRbUnroll = kRegU ? RBK : 1;
+#pragma unroll kRbUnroll
     for (int rb = 0; rb < RBK; ++rb) {
       v4 yr[CG], yi[CG];
 #pragma unroll
@@ -798,14 +799,15 @@ struct DevicePlan {
   std::vector<uint8_t> fxcd;
 };
 
+// Best effort: called from destructors, where an error cannot be returned.
 void device_plan_free(DevicePlan* d) {
   if (!d) return;
-  hipSetDevice(d->device);
-  if (d->parts) hipFree(d->parts);
-  if (d->stages) hipFree(d->stages);
-  if (d->ops) hipFree(d->ops);
-  if (d->fparts) hipFree(d->fparts);
-  if (d->fmat) hipFree(d->fmat);
+  (void)hipSetDevice(d->device);
+  if (d->parts) (void)hipFree(d->parts);
+  if (d->stages) (void)hipFree(d->stages);
+  if (d->ops) (void)hipFree(d->ops);
+  if (d->fparts) (void)hipFree(d->fparts);
+  if (d->fmat) (void)hipFree(d->fmat);
   delete d;
 }
 
