@@ -35,6 +35,7 @@ struct Request {
   size_t bytes = 0;  // state + plan descriptors
   State st;
   int stream = -1;
+  double work = 0;  // estimated device work: part-passes x state bytes
   hipEvent_t done = nullptr;
   Clock::time_point t_submit, t_done;
   ReqStatus status = RQ_QUEUED;
@@ -52,7 +53,7 @@ struct hs_server_ {
   uint64_t completed = 0;
   uint64_t next_ticket = 1;
   std::vector<hipStream_t> streams;
-  std::vector<int> load;  // requests running per stream
+  std::vector<double> load;  // estimated outstanding work per stream
   hipStream_t read_stream = nullptr;
   std::mutex mu;
   std::condition_variable cv;
@@ -73,7 +74,9 @@ size_t plan_bytes(const Plan& p, hs_dtype dt) {
   return b;
 }
 
-// Launch everything for an admitted request (called with the lock held).
+// Launch everything for an admitted request (called with the lock held) on
+// the stream with the least outstanding work, so that small requests do not
+// queue behind large ones when another stream is nearly idle.
 hs_status launch(hs_server_* sv, Request* r) {
   int best = 0;
   for (int i = 1; i < (int)sv->streams.size(); ++i)
@@ -97,7 +100,7 @@ hs_status launch(hs_server_* sv, Request* r) {
   e = hipEventCreateWithFlags(&r->done, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventRecord(r->done, s);
   if (e != hipSuccess) return fail(HS_E_HIP, "event: %s", hipGetErrorString(e));
-  sv->load[best]++;
+  sv->load[best] += r->work;
   return HS_OK;
 }
 
@@ -112,7 +115,7 @@ void worker_main(hs_server_* sv) {
       if (hipEventQuery(r->done) == hipSuccess) {
         r->t_done = Clock::now();
         r->status = RQ_DONE;
-        sv->load[r->stream]--;
+        sv->load[r->stream] -= r->work;
         sv->completed++;
         sv->running[i] = sv->running.back();
         sv->running.pop_back();
@@ -209,6 +212,7 @@ hs_status hs_server_submit(hs_server sv, int n, const hs_gate* gates, size_t cou
   if (hs_status rc = plan_build(n, gs, k, part, r->plan.get())) return rc;
   if (hs_status rc = plan_compile(r->plan.get(), dtype)) return rc;
   r->bytes = (size_t(1) << n) * amp_bytes(dtype) + plan_bytes(*r->plan, dtype);
+  r->work = (double)r->plan->parts.size() * (double)((size_t(1) << n) * amp_bytes(dtype));
   if (r->bytes > sv->budget)
     return fail(HS_E_ADMISSION, "request needs %zu bytes, budget is %zu", r->bytes, sv->budget);
   r->t_submit = Clock::now();
