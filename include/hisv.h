@@ -131,7 +131,9 @@ hs_status hs_device_count(int* out);
  * (0..8, default 6); "min_run_c64" / "min_run_c128" = gather and scatter straight in a
  * stage's layout when its lanes still cover qubits 0..min_run-1, instead of
  * re-laying out through LDS (0..6; 6 = only fully contiguous 64-amplitude
- * runs).  Launch shape of the part kernels: "xcd" (0/1) = each of the 8
+ * runs); "min_tile" (0..16) = pad every tile with the lowest free qubits up
+ * to this many qubits, for longer contiguous runs (0 = lanes + registers;
+ * capped at the kernel's widest tile).  Launch shape of the part kernels: "xcd" (0/1) = each of the 8
  * XCDs sweeps one contiguous eighth of the tiles; "grid" = 0 for one
  * workgroup per tile, g in 1..64 for a persistent grid of g x the resident
  * workgroups per CU; "spec_prefetch" (0/1) = a persistent grid of the

@@ -41,6 +41,7 @@ static int g_contig = 6;
 static int g_min_run[2][2] = {{4, 4}, {3, 3}};  // [specialized][dtype]
 // [specialized]: both paths default to one workgroup per tile, XCD-contiguous
 static LaunchShape g_launch[2];
+static int g_min_tile[2] = {0, 0};             // [specialized]
 
 CompileOptions default_options(hs_dtype dtype, bool spec) {
   CompileOptions o;
@@ -49,6 +50,7 @@ CompileOptions default_options(hs_dtype dtype, bool spec) {
   o.contig = g_contig;
   o.min_run = g_min_run[spec][dtype];
   o.launch = g_launch[spec];
+  o.min_tile = g_min_tile[spec];
   if (dtype == HS_C64) {
     o.swizzle = 4;
     o.max_m = 14;  // 2^14 x 8 B = 128 KiB of LDS
@@ -170,6 +172,9 @@ hs_status hs_tune(const char* key, int value) {
   } else if (k == "xcd" || (k == "prefetch" && spec)) {
     CHECK_ARG(value == 0 || value == 1, "%s must be 0 or 1", k.c_str());
     (k == "xcd" ? g_launch[spec].xcd : g_launch[spec].prefetch) = value != 0;
+  } else if (k == "min_tile") {
+    CHECK_ARG(value >= 0 && value <= 16, "min_tile must be 0..16");
+    g_min_tile[spec] = value;
   } else if (k == "lds_limit_kib" && spec) {
     CHECK_ARG(value >= 16 && value <= 160, "lds_limit_kib must be 16..160");
     g_launch[spec].lds_limit = (size_t)value * 1024;

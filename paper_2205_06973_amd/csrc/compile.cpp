@@ -145,7 +145,9 @@ hs_status compile_part(int n, const std::vector<Gate>& pg, const CompileOptions&
   for (const Gate& g : pg) S |= g.mask();
   const int C = std::min(opt.contig, n);
   const uint64_t need = S | ((C >= 64) ? ~0ull : ((1ull << C) - 1));
-  int m = std::max(__builtin_popcountll(need), std::min(n, kLaneBits + opt.rb));
+  int m = std::max(__builtin_popcountll(need),
+                   std::min(n, std::max(kLaneBits + opt.rb,
+                                        std::min(opt.min_tile, max_tile_qubits(opt)))));
   if (m > max_tile_qubits(opt))
     return fail(HS_E_UNSUPPORTED, "part needs a %d-qubit tile; the kernel holds at most %d",
                 m, max_tile_qubits(opt));

@@ -116,6 +116,8 @@ struct CompileOptions {
   int max_m = 14;    // widest tile whose 2^m amplitudes fit the LDS
   int min_run = 6;   // load/store straight in a stage layout whose lanes cover
                      // at least qubits 0..min_run-1 (runs of 2^min_run amplitudes)
+  int min_tile = 0;  // pad tiles with the lowest free qubits up to this many
+                     // (longer contiguous runs per tile); 0 = lanes + registers
   LaunchShape launch;
 };
 

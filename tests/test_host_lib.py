@@ -376,3 +376,19 @@ def test_replay_multilevel_specialized(n, dtype):
     np.testing.assert_allclose(got, sv.simulate(n, gates, psi0), atol=1e-12, rtol=0)
     assert plan.k == (14 if dtype == "c64" else 13)
     assert max(f["m"] for f in facts) == min(n, plan.k)
+
+
+@pytest.mark.parametrize("mode,key", [("part_lds", "min_tile"), ("part_spec", "spec_min_tile")])
+def test_replay_min_tile_padding(mode, key):
+    """Tiles padded with extra low qubits still compute the part exactly."""
+    n = 15
+    gates = wl.random_circuit(n, 120, sv.ONE_QUBIT + sv.TWO_QUBIT, seed=77)
+    hisv.hs_tune(key, 13)
+    try:
+        plan = hisv.Plan.partition(hisv.Circuit(n, gates), 5, "dfs", seed=2, trials=8)
+        psi0 = _random_state(n, 9)
+        got, facts = replay_plan(plan, n, psi0, "c64", mode)
+    finally:
+        hisv.hs_tune(key, 0)
+    np.testing.assert_allclose(got, sv.simulate(n, gates, psi0), atol=1e-12, rtol=0)
+    assert min(f["m"] for f in facts) == 13
