@@ -83,18 +83,22 @@ def committed_traffic(n: int, dtype: str, k: int, khash: str):
 def cpu_baseline(n_target: int, seed: int, budget_s: float = 12.0, n_cpu: int = 24) -> dict:
     """The oracle as it stands, one host thread, on the first gates of the same
     circuit distribution at n_cpu qubits; per-gate time scaled by 2^(n_target-n_cpu)."""
+    from threadpoolctl import threadpool_limits
+
     from oracle import statevector as sv  # test infrastructure: this leg only
     from paper_2205_06973_amd import workloads as wl
     _, gates = wl.random34(seed, n=n_cpu)
     psi = sv.basis_state(n_cpu, 0)
-    t0 = time.perf_counter()
     done = 0
-    while done < len(gates):
-        sv.apply_gate(psi, gates[done])
-        done += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
+    # elementwise numpy only; the BLAS pool is pinned to one thread regardless
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        while done < len(gates):
+            sv.apply_gate(psi, gates[done])
+            done += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        dt = time.perf_counter() - t0
     per_gate = dt / done
     scale = 2.0 ** (n_target - n_cpu)
     return {
