@@ -413,6 +413,8 @@ def main() -> int:
             "gates_timed": args.gpp_gates, "gates_per_s": gpp_rate,
             "pass_GBps": bpl / (gpp_s / args.gpp_gates) / 1e9,
             "speedup_partitioned": out["value"] / gpp_rate,
+            # like for like: both sides' kernel time from HIP events
+            "speedup_partitioned_kernels": (G * args.steps / (gpu_ms / 1e3)) / gpp_rate,
             "passes_saved": G / P,
             # a two-qubit sweep leaves the |00> amplitude of every quad alone
             # (3/4 of the state moves), so in HBM bytes the saving is smaller
