@@ -392,3 +392,23 @@ def test_replay_min_tile_padding(mode, key):
         hisv.hs_tune(key, 0)
     np.testing.assert_allclose(got, sv.simulate(n, gates, psi0), atol=1e-12, rtol=0)
     assert min(f["m"] for f in facts) == 13
+
+
+def test_partition_quality_against_exact_optimum():
+    """Graded against the brute-force optimum (the role the ILP plays in
+    Sec. V.A) on small random DAGs: no heuristic beats the optimum, DFS and
+    dagP reach it almost always, Nat only sometimes."""
+    ratios = {"nat": [], "dfs": [], "dagp": []}
+    for seed in range(16):
+        for k in (2, 3):
+            n = 5
+            gates = wl.random_circuit(n, 8, ("h", "rz", "cx", "cz"), seed=1000 + seed)
+            best = op.brute_min_parts(n, gates, k)
+            c = hisv.Circuit(n, gates)
+            for s in ratios:
+                p = hisv.Plan.partition(c, k, s, seed=seed, trials=32)
+                assert p.num_parts >= best
+                ratios[s].append(p.num_parts / best)
+    mean = {s: sum(v) / len(v) for s, v in ratios.items()}
+    assert mean["dfs"] <= 1.02 and mean["dagp"] <= 1.05
+    assert mean["nat"] >= mean["dfs"]
