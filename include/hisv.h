@@ -64,20 +64,28 @@ typedef enum { HS_C64 = 0, HS_C128 = 1 } hs_dtype;
  * s = sin t/2), RZ(t) = diag(e^{-it/2}, e^{it/2}), P(l) = diag(1, e^{il}),
  * U3(t, f, l) = [[c, -e^{il} s], [e^{if} s, e^{i(f+l)} c]];
  * CX(q0 = control, q1 = target); CZ, CP(l) multiply amplitudes with both
- * qubits set by -1 and e^{il}; SWAP exchanges the two qubits. */
+ * qubits set by -1 and e^{il}; SWAP exchanges the two qubits.
+ * Three-qubit kinds (Sec. III.A footnote: gates on more qubits are
+ * decomposed): CCX (Toffoli; controls q0, q1, target q2) and CSWAP
+ * (Fredkin; control q0 exchanges q1 and q2).  hs_circuit_load replaces each
+ * with one- and two-qubit gates -- CCX by H, T, T^dagger and six CX (the
+ * standard exact decomposition, no global phase), CSWAP by CX(q2, q1) CCX
+ * CX(q2, q1) -- so partitions and kernels only ever see arity <= 2. */
 typedef enum {
   HS_H = 0, HS_X = 1, HS_Y = 2, HS_Z = 3, HS_S = 4, HS_T = 5,
   HS_RX = 6, HS_RY = 7, HS_RZ = 8, HS_P = 9, HS_U3 = 10,
-  HS_CX = 11, HS_CZ = 12, HS_CP = 13, HS_SWAP = 14
+  HS_CX = 11, HS_CZ = 12, HS_CP = 13, HS_SWAP = 14,
+  HS_CCX = 15, HS_CSWAP = 16
 } hs_kind;
 
-/* One gate: q1 = -1 for one-qubit kinds; p[] holds the angles (unused ones
+/* One gate: q1 = -1 for one-qubit kinds; q2 = the third qubit of the
+ * three-qubit kinds and 0 for all others; p[] holds the angles (unused ones
  * ignored).  40 bytes, naturally aligned. */
 typedef struct {
   int32_t kind;
   int32_t q0;
   int32_t q1;
-  int32_t reserved;  /* must be 0 */
+  int32_t q2;
   double p[3];
 } hs_gate;
 
@@ -177,10 +185,15 @@ hs_status hs_state_destroy(hs_state s);
 
 /* ---- circuits (Sec. II.B: a sequence of gates) ----------------------------- */
 
-/* Copy and validate `count` gates on n qubits.  HS_E_QUBIT_RANGE for a qubit
- * outside [0, n) or a two-qubit gate on one qubit; HS_E_ARG for an unknown
- * kind, a one-qubit gate with q1 != -1 or reserved != 0. */
+/* Copy and validate `count` gates on n qubits; three-qubit kinds are
+ * replaced by their one- and two-qubit decompositions (see hs_kind).
+ * HS_E_QUBIT_RANGE for a qubit outside [0, n) or a gate with repeated
+ * qubits; HS_E_ARG for an unknown kind, a one-qubit gate with q1 != -1, a
+ * non-zero q2 on a one- or two-qubit kind, or a non-finite angle. */
 hs_status hs_circuit_load(int n, const hs_gate* gates, size_t count, hs_circuit* out);
+
+/* *count = the number of gates after decomposition: gate ids in partitions
+ * (hs_plan_part_of_gate) index this sequence. */
 hs_status hs_circuit_info(hs_circuit c, int* n, size_t* count);
 hs_status hs_circuit_destroy(hs_circuit c);
 
@@ -209,14 +222,18 @@ hs_status hs_partition_multilevel(hs_circuit c, int tile_qubits, int pad_qubits,
                                   hs_strategy strategy, uint64_t seed, int trials, hs_plan* out);
 
 /* Build a plan from a caller-given assignment part_of_gate[count] (ids
- * 0..P-1).  HS_E_BAD_PARTITION unless it passes hs_plan_validate's checks. */
-hs_status hs_plan_from_assignment(hs_circuit c, int k, const int32_t* part_of_gate,
+ * 0..P-1, one per gate of the circuit after decomposition: count must equal
+ * hs_circuit_info's count, else HS_E_ARG).  HS_E_BAD_PARTITION unless it
+ * passes hs_plan_validate's checks. */
+hs_status hs_plan_from_assignment(hs_circuit c, int k, const int32_t* part_of_gate, size_t count,
                                   hs_plan* out);
 
 hs_status hs_plan_num_parts(hs_plan p, int* parts);
 
-/* part_of_gate[count] (caller-owned, count = the circuit's gate count). */
-hs_status hs_plan_part_of_gate(hs_plan p, int32_t* out);
+/* *count = the plan's gate count (after decomposition); if out is not NULL
+ * it receives the part id of every gate, out[0 .. *count) -- HS_E_ARG if
+ * cap < *count. */
+hs_status hs_plan_part_of_gate(hs_plan p, int32_t* out, size_t cap, size_t* count);
 
 /* Qubit mask (bit q set if the part uses qubit q) and gate count of a part. */
 hs_status hs_plan_part_info(hs_plan p, int part, uint64_t* qubit_mask, int* num_gates);

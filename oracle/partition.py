@@ -35,7 +35,9 @@ from collections import deque
 
 
 def gate_qubits(gate) -> tuple[int, ...]:
-    _, q0, q1, _ = gate
+    _, q0, q1, _ = gate[:4]
+    if len(gate) > 4:  # three-qubit kinds carry their third qubit last
+        return (q0, q1, gate[4])
     return (q0,) if q1 < 0 else (q0, q1)
 
 

@@ -33,6 +33,13 @@ basis-ordering convention is needed:
   CZ(a, b):  negate amplitudes with bit a = bit b = 1;
   CP(l)(a,b): multiply amplitudes with bit a = bit b = 1 by e^{il};
   SWAP(a, b): exchange amplitudes with (bit a, bit b) = (1, 0) and (0, 1).
+Three-qubit gates (the paper decomposes gates on more qubits, Sec. III.A
+footnote; the oracle applies them whole, by definition), written as
+(name, q0, q1, params, q2):
+  CCX(a, b, t): for indices with bit a = bit b = 1, swap the pair differing
+                in bit t;
+  CSWAP(c, x, y): for indices with bit c = 1, exchange amplitudes with
+                (bit x, bit y) = (1, 0) and (0, 1).
 
 Everything is float64 / complex128 numpy; no blocking, fusion or reordering.
 """
@@ -45,6 +52,7 @@ import numpy as np
 
 ONE_QUBIT = ("h", "x", "y", "z", "s", "t", "rx", "ry", "rz", "p", "u3")
 TWO_QUBIT = ("cx", "cz", "cp", "swap")
+THREE_QUBIT = ("ccx", "cswap")
 
 
 def gate_matrix_1q(name: str, params=()) -> np.ndarray:
@@ -147,8 +155,34 @@ def apply_2q(psi: np.ndarray, name: str, a: int, b: int, params=()) -> None:
         raise ValueError(f"not a two-qubit gate: {name!r}")
 
 
+def apply_3q(psi: np.ndarray, name: str, a: int, b: int, c: int) -> None:
+    """In place: CCX(a, b -> c) or CSWAP(a; b <-> c), by index arithmetic."""
+    n = num_qubits_of(psi)
+    idx = np.arange(1 << n, dtype=np.int64)
+
+    def bit(q):
+        return (idx >> q) & 1
+
+    if name == "ccx":
+        sel = idx[(bit(a) == 1) & (bit(b) == 1) & (bit(c) == 0)]
+        other = sel | (1 << c)
+    elif name == "cswap":
+        sel = idx[(bit(a) == 1) & (bit(b) == 1) & (bit(c) == 0)]
+        other = sel ^ (1 << b) ^ (1 << c)
+    else:
+        raise ValueError(f"not a three-qubit gate: {name!r}")
+    tmp = psi[sel].copy()
+    psi[sel] = psi[other]
+    psi[other] = tmp
+
+
 def check_gate(n: int, gate) -> None:
-    name, q0, q1, _ = gate
+    name, q0, q1, _ = gate[:4]
+    if name in THREE_QUBIT:
+        q2 = gate[4] if len(gate) > 4 else -1
+        if not all(0 <= q < n for q in (q0, q1, q2)) or len({q0, q1, q2}) != 3:
+            raise ValueError(f"bad three-qubit gate {gate!r} for n={n}")
+        return
     if name in ONE_QUBIT:
         if not (0 <= q0 < n) or q1 != -1:
             raise ValueError(f"bad one-qubit gate {gate!r} for n={n}")
@@ -160,11 +194,13 @@ def check_gate(n: int, gate) -> None:
 
 
 def apply_gate(psi: np.ndarray, gate) -> None:
-    name, q0, q1, params = gate
+    name, q0, q1, params = gate[:4]
     n = num_qubits_of(psi)
     check_gate(n, gate)
     if name in ONE_QUBIT:
         apply_1q(psi, q0, gate_matrix_1q(name, params))
+    elif name in THREE_QUBIT:
+        apply_3q(psi, name, q0, q1, gate[4])
     else:
         apply_2q(psi, name, q0, q1, params)
 
@@ -198,9 +234,9 @@ def norm(psi: np.ndarray) -> float:
 
 def inverse_gate(gate):
     """The gate whose matrix is the adjoint of ``gate``'s (for round trips)."""
-    name, q0, q1, p = gate
+    name, q0, q1, p = gate[:4]
     p = tuple(p)
-    if name in ("h", "x", "y", "z", "cx", "cz", "swap"):
+    if name in ("h", "x", "y", "z", "cx", "cz", "swap", "ccx", "cswap"):
         return gate
     if name == "s":
         return ("p", q0, q1, (-math.pi / 2,))
@@ -265,10 +301,10 @@ def simulate_alg1(n: int, gates, part_of_gate, init=0) -> np.ndarray:
         parts.setdefault(int(p), []).append(gi)
     for p in sorted(parts):
         gate_list = [gates[i] for i in parts[p]]
-        qubits = sorted({q for g in gate_list for q in (g[1], g[2]) if q >= 0})
+        qubits = sorted({q for g in gate_list for q in (g[1], g[2]) + tuple(g[4:5]) if q >= 0})
         slot = {q: j for j, q in enumerate(qubits)}
         inner_gates = [(g[0], slot[g[1]], slot[g[2]] if g[2] >= 0 else -1, g[3])
-                       for g in gate_list]
+                       + ((slot[g[4]],) if len(g) > 4 else ()) for g in gate_list]
         for addr in gather_addresses(n, qubits):
             in_sv = psi[addr].copy()            # Gather
             for g in inner_gates:               # Execute

@@ -296,9 +296,9 @@ hs_status hs_circuit_load(int n, const hs_gate* gates, size_t count, hs_circuit*
   CHECK_ARG(gates || count == 0, "null gate array");
   auto* c = new hs_circuit_();
   c->n = n;
-  c->gates.resize(count);
+  c->gates.reserve(count);
   for (size_t i = 0; i < count; ++i) {
-    if (hs_status rc = validate_gate(n, gates[i], &c->gates[i])) {
+    if (hs_status rc = expand_gate(n, gates[i], &c->gates)) {
       delete c;
       return rc;
     }
@@ -380,9 +380,12 @@ hs_status hs_partition_multilevel(hs_circuit c, int tile_qubits, int pad_qubits,
   return HS_OK;
 }
 
-hs_status hs_plan_from_assignment(hs_circuit c, int k, const int32_t* part_of_gate, hs_plan* out) {
+hs_status hs_plan_from_assignment(hs_circuit c, int k, const int32_t* part_of_gate, size_t count,
+                                  hs_plan* out) {
   CHECK_ARG(c && out, "null argument");
   CHECK_ARG(part_of_gate || c->gates.empty(), "null assignment");
+  CHECK_ARG(count == c->gates.size(), "assignment has %zu entries, the circuit %zu gates", count,
+            c->gates.size());
   CHECK_ARG(k >= 1, "k = %d < 1", k);
   std::vector<int32_t> part(part_of_gate, part_of_gate + c->gates.size());
   auto* p = new hs_plan_();
@@ -400,8 +403,12 @@ hs_status hs_plan_num_parts(hs_plan p, int* parts) {
   return HS_OK;
 }
 
-hs_status hs_plan_part_of_gate(hs_plan p, int32_t* out) {
-  CHECK_ARG(p && (out || p->gates.empty()), "null argument");
+hs_status hs_plan_part_of_gate(hs_plan p, int32_t* out, size_t cap, size_t* count) {
+  CHECK_ARG(p, "null plan");
+  if (count) *count = p->part_of_gate.size();
+  if (!out) return HS_OK;
+  CHECK_ARG(cap >= p->part_of_gate.size(), "buffer of %zu entries for %zu gates", cap,
+            p->part_of_gate.size());
   std::copy(p->part_of_gate.begin(), p->part_of_gate.end(), out);
   return HS_OK;
 }

@@ -29,7 +29,7 @@ bool kind_is_1q(int kind) { return kind >= HS_H && kind <= HS_U3; }
 bool kind_is_2q(int kind) { return kind >= HS_CX && kind <= HS_SWAP; }
 
 hs_status validate_gate(int n, const hs_gate& g, Gate* out) {
-  if (g.reserved != 0) return fail(HS_E_ARG, "gate reserved field must be 0");
+  if (g.q2 != 0) return fail(HS_E_ARG, "q2 must be 0 for gate kind %d", g.kind);
   if (kind_is_1q(g.kind)) {
     if (g.q1 != -1) return fail(HS_E_ARG, "one-qubit gate kind %d needs q1 = -1", g.kind);
     if (g.q0 < 0 || g.q0 >= n)
@@ -47,6 +47,67 @@ hs_status validate_gate(int n, const hs_gate& g, Gate* out) {
   out->q0 = g.q0;
   out->q1 = g.q1;
   for (int i = 0; i < 3; ++i) out->p[i] = g.p[i];
+  return HS_OK;
+}
+
+// A gate as it enters a circuit: one- and two-qubit kinds are validated and
+// appended; the three-qubit kinds are replaced by one- and two-qubit gates.
+//   CCX(a, b, t) = H(t) CX(b,t) Tdg(t) CX(a,t) T(t) CX(b,t) Tdg(t) CX(a,t)
+//                  T(b) T(t) H(t) CX(a,b) T(a) Tdg(b) CX(a,b)
+//   (the standard exact Toffoli decomposition, in circuit order), and
+//   CSWAP(c, x, y) = CX(y, x) CCX(c, x, y) CX(y, x).
+hs_status expand_gate(int n, const hs_gate& g, std::vector<Gate>* out) {
+  if (g.kind != HS_CCX && g.kind != HS_CSWAP) {
+    Gate v;
+    if (hs_status rc = validate_gate(n, g, &v)) return rc;
+    out->push_back(v);
+    return HS_OK;
+  }
+  const int a = g.q0, b = g.q1, c = g.q2;
+  if (a < 0 || a >= n || b < 0 || b >= n || c < 0 || c >= n)
+    return fail(HS_E_QUBIT_RANGE, "qubits (%d, %d, %d) outside [0, %d)", a, b, c, n);
+  if (a == b || a == c || b == c)
+    return fail(HS_E_QUBIT_RANGE, "three-qubit gate needs distinct qubits (%d, %d, %d)", a, b, c);
+  auto one = [&](int kind, int q, double p0) {
+    Gate v{};
+    v.kind = kind;
+    v.q0 = q;
+    v.q1 = -1;
+    v.p[0] = p0;
+    out->push_back(v);
+  };
+  auto cx = [&](int ctl, int tgt) {
+    Gate v{};
+    v.kind = HS_CX;
+    v.q0 = ctl;
+    v.q1 = tgt;
+    out->push_back(v);
+  };
+  const double tdg = -M_PI / 4;
+  auto ccx = [&](int x, int y, int t) {
+    one(HS_H, t, 0);
+    cx(y, t);
+    one(HS_P, t, tdg);
+    cx(x, t);
+    one(HS_T, t, 0);
+    cx(y, t);
+    one(HS_P, t, tdg);
+    cx(x, t);
+    one(HS_T, y, 0);
+    one(HS_T, t, 0);
+    one(HS_H, t, 0);
+    cx(x, y);
+    one(HS_T, x, 0);
+    one(HS_P, y, tdg);
+    cx(x, y);
+  };
+  if (g.kind == HS_CCX) {
+    ccx(a, b, c);
+  } else {
+    cx(c, b);
+    ccx(a, b, c);
+    cx(c, b);
+  }
   return HS_OK;
 }
 

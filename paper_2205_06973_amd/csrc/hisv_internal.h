@@ -34,6 +34,9 @@ struct Gate {
 bool kind_is_1q(int kind);
 bool kind_is_2q(int kind);
 hs_status validate_gate(int n, const hs_gate& g, Gate* out);
+// Validate a gate and append it, or the one- and two-qubit gates that
+// replace a three-qubit kind, to *out.
+hs_status expand_gate(int n, const hs_gate& g, std::vector<Gate>* out);
 // 2x2 matrix (row-major) of a one-qubit gate, in FP64.
 void gate_matrix(const Gate& g, cd u[4]);
 

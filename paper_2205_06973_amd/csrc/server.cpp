@@ -199,11 +199,12 @@ hs_status hs_server_submit(hs_server sv, int n, const hs_gate* gates, size_t cou
   r->n = n;
   r->dtype = dtype;
   r->init = init_basis;
-  std::vector<Gate> gs(count);
-  for (size_t i = 0; i < count; ++i) {
-    if (hs_status rc = validate_gate(n, gates[i], &gs[i])) return rc;
-    if (gs[i].arity() > k) return fail(HS_E_ARITY_GT_K, "gate wider than k = %d", k);
-  }
+  std::vector<Gate> gs;
+  gs.reserve(count);
+  for (size_t i = 0; i < count; ++i)
+    if (hs_status rc = expand_gate(n, gates[i], &gs)) return rc;
+  for (const Gate& g : gs)
+    if (g.arity() > k) return fail(HS_E_ARITY_GT_K, "gate wider than k = %d", k);
   std::vector<int32_t> part;
   const Dag dag = build_dag(gs);
   if (strategy == HS_PART_NAT) partition_nat(gs, k, &part);

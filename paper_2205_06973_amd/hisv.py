@@ -23,7 +23,7 @@ STATUS = {0: "HS_OK", 1: "HS_E_ARG", 2: "HS_E_QUBIT_RANGE", 3: "HS_E_ARITY_GT_K"
           8: "HS_E_STATE", 9: "HS_E_UNSUPPORTED"}
 DTYPES = {"c64": 0, "c128": 1}
 KINDS = {"h": 0, "x": 1, "y": 2, "z": 3, "s": 4, "t": 5, "rx": 6, "ry": 7, "rz": 8,
-         "p": 9, "u3": 10, "cx": 11, "cz": 12, "cp": 13, "swap": 14}
+         "p": 9, "u3": 10, "cx": 11, "cz": 12, "cp": 13, "swap": 14, "ccx": 15, "cswap": 16}
 STRATEGIES = {"nat": 0, "dfs": 1, "dagp": 2}
 EXEC = {"gate_per_pass": 0, "part_lds": 1, "part_fused": 2, "auto": 3, "part_spec": 4}
 
@@ -37,7 +37,7 @@ class HisvError(RuntimeError):
 
 class hs_gate(C.Structure):
     _fields_ = [("kind", C.c_int32), ("q0", C.c_int32), ("q1", C.c_int32),
-                ("reserved", C.c_int32), ("p", C.c_double * 3)]
+                ("q2", C.c_int32), ("p", C.c_double * 3)]
 
 
 _vp = C.c_void_p
@@ -60,9 +60,9 @@ _SIGS = {
     "hs_circuit_destroy": [_vp],
     "hs_partition": [_vp, C.c_int, C.c_int, _u64, C.c_int, C.POINTER(_vp)],
     "hs_partition_multilevel": [_vp, C.c_int, C.c_int, C.c_int, _u64, C.c_int, C.POINTER(_vp)],
-    "hs_plan_from_assignment": [_vp, C.c_int, _i32p, C.POINTER(_vp)],
+    "hs_plan_from_assignment": [_vp, C.c_int, _i32p, C.c_size_t, C.POINTER(_vp)],
     "hs_plan_num_parts": [_vp, C.POINTER(C.c_int)],
-    "hs_plan_part_of_gate": [_vp, _i32p],
+    "hs_plan_part_of_gate": [_vp, _i32p, C.c_size_t, C.POINTER(C.c_size_t)],
     "hs_plan_part_info": [_vp, C.c_int, C.POINTER(_u64), C.POINTER(C.c_int)],
     "hs_plan_validate": [_vp],
     "hs_plan_part_layout": [_vp, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int),
@@ -155,14 +155,16 @@ def hs_max_part_qubits(dtype: str = "c64", exec_mode: str = "part_lds") -> int:
 
 
 def gates_to_array(gates) -> C.Array:
-    """(name, q0, q1, params) tuples -> hs_gate[]."""
+    """(name, q0, q1, params[, q2]) tuples -> hs_gate[] (q2: the third qubit
+    of "ccx" / "cswap")."""
     arr = (hs_gate * max(1, len(gates)))()
-    for i, (name, q0, q1, params) in enumerate(gates):
+    for i, gate in enumerate(gates):
+        name, q0, q1, params = gate[:4]
         g = arr[i]
         g.kind = KINDS[name]
         g.q0 = int(q0)
         g.q1 = int(q1)
-        g.reserved = 0
+        g.q2 = int(gate[4]) if len(gate) > 4 else 0
         for j, v in enumerate(tuple(params)[:3]):
             g.p[j] = float(v)
     return arr
@@ -176,6 +178,13 @@ class Circuit:
         h = _vp()
         _call("hs_circuit_load", self.n, arr, len(self.gates), C.byref(h))
         self.handle = h
+
+    @property
+    def num_gates(self) -> int:
+        """Gates after three-qubit kinds are decomposed (the ids partitions use)."""
+        n, cnt = C.c_int(), C.c_size_t()
+        _call("hs_circuit_info", self.handle, C.byref(n), C.byref(cnt))
+        return cnt.value
 
     def close(self):
         if self.handle:
@@ -222,7 +231,7 @@ class Plan:
         arr = np.ascontiguousarray(np.asarray(part_of_gate, dtype=np.int32))
         h = _vp()
         _call("hs_plan_from_assignment", circuit.handle, int(k),
-              arr.ctypes.data_as(_i32p), C.byref(h))
+              arr.ctypes.data_as(_i32p), arr.size, C.byref(h))
         return cls(h, circuit, k)
 
     @property
@@ -232,9 +241,13 @@ class Plan:
         return v.value
 
     def part_of_gate(self) -> np.ndarray:
-        out = np.zeros(max(1, len(self.circuit.gates)), dtype=np.int32)
-        _call("hs_plan_part_of_gate", self.handle, out.ctypes.data_as(_i32p))
-        return out[:len(self.circuit.gates)]
+        """Part id of every gate (of the decomposed sequence)."""
+        cnt = C.c_size_t()
+        _call("hs_plan_part_of_gate", self.handle, None, 0, C.byref(cnt))
+        out = np.zeros(max(1, cnt.value), dtype=np.int32)
+        _call("hs_plan_part_of_gate", self.handle, out.ctypes.data_as(_i32p), out.size,
+              C.byref(cnt))
+        return out[:cnt.value]
 
     def part_info(self, part: int) -> tuple[int, int]:
         mask, ng = _u64(), C.c_int()

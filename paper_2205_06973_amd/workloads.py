@@ -5,6 +5,8 @@ arithmetic (no gate matrices, no partitioning), so the oracle and the HIP
 path can both be fed from it.  A gate is a plain tuple
 ``(name, q0, q1, params)``: ``q1 == -1`` for a one-qubit gate, ``params`` a
 tuple of up to three floats, and for ``cx`` q0 is the control, q1 the target.
+The three-qubit kinds carry their third qubit last:
+``("ccx", c0, c1, (), target)`` and ``("cswap", control, x, (), y)``.
 
 The paper measures on QASMBench circuits (30-37 qubits, 60-5,731 gates,
 Table I), which are not available here; the circuits below stand in for
@@ -23,6 +25,12 @@ them at the same scale.  Their recipes are:
   final state factorises into an even part and an odd part.
 * ``serving_stream``: Poisson arrivals of layered circuits with n ~ U{lo..hi},
   depth ~ U{lo..hi} layers, complex64 with probability 0.7 else complex128.
+* ``adder_circuit``: the ripple-carry adder of Cuccaro, Draper, Kutin and
+  Moulton (2004), written from its MAJ / UMA definition: on a basis input it
+  maps (a, b) to (a, a + b) with the carry out in its own qubit -- a
+  Toffoli-heavy circuit whose output is known exactly at any size (a 16-bit
+  adder has 34 qubits).  Layout: qubit 0 is the carry-in ancilla, b_i is
+  qubit 1 + 2 i, a_i is qubit 2 + 2 i, the carry out is qubit 2 nbits + 1.
 """
 
 from __future__ import annotations
@@ -35,6 +43,7 @@ import numpy as np
 TWO_PI = 2.0 * math.pi
 _ONE_Q_ANGLES = {"rx": 1, "ry": 1, "rz": 1, "p": 1, "u3": 3}
 _TWO_Q = {"cx", "cz", "cp", "swap"}
+_THREE_Q = {"ccx", "cswap"}
 
 
 def _rng(seed: int) -> np.random.Generator:
@@ -42,6 +51,9 @@ def _rng(seed: int) -> np.random.Generator:
 
 
 def _draw_gate(rng, name: str, n: int, pair_pool=None):
+    if name in _THREE_Q:
+        a, b, c = rng.choice(n, size=3, replace=False)
+        return (name, int(a), int(b), (), int(c))
     if name in _TWO_Q:
         if pair_pool is None:
             a, b = rng.choice(n, size=2, replace=False)
@@ -167,3 +179,19 @@ def serving_stream(num_requests: int, rate_per_s: float, seed: int,
         dtype = "c64" if float(rng.uniform()) < p_c64 else "c128"
         out.append(Request(t, n, layers, dtype, int(seed) * 1_000_003 + i))
     return out
+
+
+def adder_circuit(nbits: int):
+    """Ripple-carry adder on 2 nbits + 2 qubits (layout in the module notes)."""
+    a = lambda i: 2 + 2 * i  # noqa: E731
+    b = lambda i: 1 + 2 * i  # noqa: E731
+    carry = lambda i: 0 if i == 0 else a(i - 1)  # noqa: E731
+    gates = []
+    for i in range(nbits):  # MAJ(carry_i, b_i, a_i)
+        gates += [("cx", a(i), b(i), ()), ("cx", a(i), carry(i), ()),
+                  ("ccx", carry(i), b(i), (), a(i))]
+    gates.append(("cx", a(nbits - 1), 2 * nbits + 1, ()))
+    for i in reversed(range(nbits)):  # UMA(carry_i, b_i, a_i)
+        gates += [("ccx", carry(i), b(i), (), a(i)), ("cx", a(i), carry(i), ()),
+                  ("cx", carry(i), b(i), ())]
+    return 2 * nbits + 2, gates

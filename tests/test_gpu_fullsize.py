@@ -157,3 +157,35 @@ def test_random34_round_trip(n, dtype):
     want = np.zeros(idx.size, dtype=np.complex128)
     want[idx == 0] = 1.0
     assert report(f"random{n} U^-1 U", np.abs(got - want), n) <= TOL[dtype]
+
+
+def test_adder16_superposition_34_qubits():
+    """A 16-bit ripple-carry adder (34 qubits, complex64, 545 gates after the
+    Toffoli decompositions) on |a = uniform superposition over 2^16, b>:
+    amplitude 2^-8 on |a, a + b> for every a; sampled exactly."""
+    nb, b = 16, 40503
+    n, adder = wl.adder_circuit(nb)
+    gates = [("h", 2 + 2 * i, -1, ()) for i in range(nb)] + adder
+
+    def index(a, bb, carry=0):
+        x = np.uint64(carry) << np.uint64(2 * nb + 1)
+        for i in range(nb):
+            x |= np.uint64((a >> i) & 1) << np.uint64(2 + 2 * i)
+            x |= np.uint64((bb >> i) & 1) << np.uint64(1 + 2 * i)
+        return x
+
+    st, buf = simulate(n, gates, "c64", 7, "dfs", init=int(index(0, b)))
+    rng = np.random.default_rng(12)
+    avals = rng.integers(0, 1 << nb, 2048)
+    idx = np.array([index(int(a), (int(a) + b) % (1 << nb), (int(a) + b) >> nb) for a in avals],
+                   dtype=np.uint64)
+    got = st.amplitudes_at(idx)
+    assert report("adder16 hits", np.abs(got - 2.0 ** -8), n) <= TOL["c64"]
+    # and nothing anywhere else: the hits already carry the whole norm
+    assert abs(st.norm() - 1) <= 1e-5
+    other = rng.integers(0, 1 << n, 4096, dtype=np.uint64)
+    hit = {int(index(a, (a + b) % (1 << nb), (a + b) >> nb)) for a in range(1 << nb)}
+    want = np.array([2.0 ** -8 if int(x) in hit else 0.0 for x in other])
+    assert report("adder16 elsewhere", np.abs(st.amplitudes_at(other) - want), n) <= TOL["c64"]
+    st.close()
+    del buf

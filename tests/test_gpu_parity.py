@@ -253,3 +253,38 @@ def test_split_relayout_parity(n, strategy, dtype, tile, lds_kib):
     finally:
         hisv.hs_tune("spec_lds_limit_kib", 64)
     check(got, sv.simulate(n, gates, init), dtype)
+
+
+# ---- three-qubit kinds (decomposed at load) ----------------------------------------
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("mode,k", [("part_lds", 5), ("part_spec", 7), ("part_fused", 5), ("auto_spec", 6)])
+def test_toffoli_fredkin_circuits(mode, k, dtype):
+    n = 14
+    gates = wl.random_circuit(n, 120, ("h", "u3", "rz", "cx", "cp", "ccx", "cswap"), seed=61)
+    init = 12345 % (1 << n)
+    got, _ = run_hip(n, gates, dtype, k, "dfs", mode, init=init)
+    check(got, sv.simulate(n, gates, init), dtype)
+
+
+def _adder_index(nb, a, b, carry=0):
+    x = carry << (2 * nb + 1)
+    for i in range(nb):
+        x |= ((a >> i) & 1) << (2 + 2 * i)
+        x |= ((b >> i) & 1) << (1 + 2 * i)
+    return x
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_adder_superposition(dtype):
+    """H on every a_i, then the adder: amplitude 2^(-nb/2) on |a, a + b> for
+    every a, zero elsewhere."""
+    nb, b = 6, 45
+    n, adder = wl.adder_circuit(nb)
+    gates = [("h", 2 + 2 * i, -1, ()) for i in range(nb)] + adder
+    got, _ = run_hip(n, gates, dtype, 7, "dfs", "part_spec", init=_adder_index(nb, 0, b))
+    want = np.zeros(1 << n, dtype=np.complex128)
+    for a in range(1 << nb):
+        s = a + b
+        want[_adder_index(nb, a, s % (1 << nb), s >> nb)] = 2 ** (-nb / 2)
+    check(got, want, dtype)

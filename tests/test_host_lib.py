@@ -412,3 +412,52 @@ def test_partition_quality_against_exact_optimum():
     mean = {s: sum(v) / len(v) for s, v in ratios.items()}
     assert mean["dfs"] <= 1.02 and mean["dagp"] <= 1.05
     assert mean["nat"] >= mean["dfs"]
+
+
+# ---- three-qubit kinds, decomposed at load ---------------------------------------------
+
+def test_three_qubit_kinds_decompose_exactly():
+    """CCX / CSWAP are replaced at load; the compiled plan, replayed on the
+    host, equals the oracle applying them whole."""
+    n = 10
+    gates = wl.random_circuit(n, 60, ("h", "rz", "cx", "ccx", "cswap", "u3"), seed=17)
+    c = hisv.Circuit(n, gates)
+    n3 = sum(g[0] == "ccx" for g in gates)
+    ns = sum(g[0] == "cswap" for g in gates)
+    assert n3 and ns
+    assert c.num_gates == len(gates) + 14 * n3 + 16 * ns
+    for strategy in ("nat", "dfs", "dagp"):
+        plan = hisv.Plan.partition(c, 5, strategy, seed=1, trials=8)
+        assert len(plan.part_of_gate()) == c.num_gates
+        plan.validate()
+        psi0 = _random_state(n, 4)
+        got, _ = replay_plan(plan, n, psi0, "c64", "part_spec")
+        np.testing.assert_allclose(got, sv.simulate(n, gates, psi0), atol=1e-12, rtol=0)
+
+
+def test_three_qubit_kind_errors():
+    for bad, code in ((("ccx", 1, 1, (), 2), "HS_E_QUBIT_RANGE"), (("ccx", 0, 1, (), 9), "HS_E_QUBIT_RANGE"),
+                      (("cswap", 0, 2, (), 2), "HS_E_QUBIT_RANGE")):
+        with pytest.raises(hisv.HisvError) as e:
+            hisv.Circuit(8, [bad])
+        assert e.value.code == code
+    with pytest.raises(hisv.HisvError) as e:
+        hisv.Circuit(8, [("cx", 0, 1, (), 3)])  # q2 set on a two-qubit kind
+    assert e.value.code == "HS_E_ARG"
+
+
+def test_assignment_and_part_ids_are_sized():
+    """part ids index the decomposed gate sequence; both calls check sizes."""
+    import ctypes
+    gates = [("h", 0, -1, ()), ("ccx", 0, 1, (), 2)]
+    c = hisv.Circuit(3, gates)
+    assert c.num_gates == 16
+    with pytest.raises(hisv.HisvError) as e:  # one id per gate as given: too short
+        hisv.Plan.from_assignment(c, 3, [0, 0])
+    assert e.value.code == "HS_E_ARG"
+    plan = hisv.Plan.from_assignment(c, 3, [0] * 16)
+    assert plan.part_of_gate().tolist() == [0] * 16
+    buf = (ctypes.c_int32 * 4)()
+    cnt = ctypes.c_size_t()
+    rc = hisv.lib().hs_plan_part_of_gate(plan.handle, buf, 4, ctypes.byref(cnt))
+    assert rc == 1 and cnt.value == 16  # HS_E_ARG: buffer too small, count still reported

@@ -287,3 +287,61 @@ def test_state_bytes(golden_dir):
     for n, gib in d["table1_gib"].items():
         assert (2 ** int(n)) * d["bytes_per_amplitude_c128"] == gib * 2 ** 30
     assert sv.basis_state(4).itemsize == d["bytes_per_amplitude_c128"]
+
+
+# ---- three-qubit gates (applied whole by the oracle) -------------------------------
+
+def _rand_state(n, seed):
+    rng = np.random.default_rng(seed)
+    v = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    return v / np.linalg.norm(v)
+
+
+@pytest.mark.parametrize("a,b,t", [(0, 1, 2), (3, 0, 1), (2, 3, 0)])
+def test_ccx_is_h_ccz_h(a, b, t):
+    """Toffoli = H on the target, a phase of -1 where all three bits are 1
+    (a diagonal built from the index bits), H on the target."""
+    n = 4
+    psi = _rand_state(n, 11 + a)
+    want = psi.copy()
+    sv.apply_gate(want, ("h", t, -1, ()))
+    idx = np.arange(1 << n)
+    ccz = np.where(((idx >> a) & (idx >> b) & (idx >> t) & 1) == 1, -1.0, 1.0)
+    want *= ccz
+    sv.apply_gate(want, ("h", t, -1, ()))
+    got = psi.copy()
+    sv.apply_gate(got, ("ccx", a, b, (), t))
+    np.testing.assert_allclose(got, want, atol=1e-14)
+
+
+@pytest.mark.parametrize("c,x,y", [(0, 1, 2), (2, 3, 0), (1, 0, 3)])
+def test_cswap_is_cx_ccx_cx(c, x, y):
+    n = 4
+    psi = _rand_state(n, 21 + c)
+    want = psi.copy()
+    for g in (("cx", y, x, ()), ("ccx", c, x, (), y), ("cx", y, x, ())):
+        sv.apply_gate(want, g)
+    got = psi.copy()
+    sv.apply_gate(got, ("cswap", c, x, (), y))
+    np.testing.assert_allclose(got, want, atol=1e-14)
+    sv.apply_gate(got, ("cswap", c, x, (), y))  # self-inverse
+    np.testing.assert_allclose(got, psi, atol=1e-14)
+
+
+def _adder_index(nb, a, b, carry=0):
+    x = carry << (2 * nb + 1)
+    for i in range(nb):
+        x |= ((a >> i) & 1) << (2 + 2 * i)
+        x |= ((b >> i) & 1) << (1 + 2 * i)
+    return x
+
+
+def test_adder_closed_form():
+    """The ripple-carry adder maps |a, b> to |a, a + b> (carry in its qubit)."""
+    nb = 3
+    n, gates = wl.adder_circuit(nb)
+    for a in range(1 << nb):
+        for b in range(1 << nb):
+            psi = sv.simulate(n, gates, _adder_index(nb, a, b))
+            s = a + b
+            assert abs(psi[_adder_index(nb, a, s % (1 << nb), s >> nb)] - 1) < 1e-12
