@@ -25,6 +25,9 @@ Prints ONE JSON line on stdout:
   multilevel the same circuits with the multi-level partition (first level
              bounded by the padded LDS tile, 13 qubits complex64 / 12
              complex128; second level = register stages)
+  layered28  28 qubits, 40 layers (U3 on every qubit + CX matching), DFS
+             k = 6, complex64 and complex128: interpreter (PART_LDS) vs
+             specialized kernels vs AUTO vs one sweep per gate
   qft32      a 32-qubit QFT on a random basis state, k = 7 dagP partition:
              gate-by-gate (specialized) vs fused-unitary (matrix cores) vs
              AUTO, with the fused kernel's matrix-core roofline
@@ -110,16 +113,16 @@ def cpu_baseline(n_target: int, seed: int, budget_s: float = 12.0, n_cpu: int = 
     }
 
 
-def timed_plan(st, plan, stream, steps=1):
+def timed_plan(st, plan, stream, steps=1, mode="part_spec"):
     """Seconds of `steps` whole-plan runs (one warm run first), HIP events on the state's stream."""
     import torch
-    st.simulate(plan, "part_spec")
+    st.simulate(plan, mode)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(stream)
     for _ in range(steps):
-        st.simulate(plan, "part_spec")
+        st.simulate(plan, mode)
     e1.record(stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / 1e3 / steps
@@ -191,6 +194,53 @@ def run_multilevel(args, buf, stream, log):
         log(f"[bench] multilevel {row}")
         if not abs(norm - 1.0) < 1e-3:
             raise RuntimeError(f"norm drift in multi-level case {row}")
+        rows.append(row)
+    return rows
+
+
+def run_layered(args, buf, stream, log):
+    """28-qubit layered circuit (40 layers of U3 on every qubit + CX on a
+    random perfect matching, 1,680 gates), DFS k = 6, complex64 and
+    complex128: the gate-by-gate interpreter (PART_LDS), the specialized
+    kernels (PART_SPEC), AUTO, and one sweep per gate."""
+    import torch
+    from paper_2205_06973_amd import hisv
+    from paper_2205_06973_amd import workloads as wl
+    n, gates = wl.layered28(args.seed)
+    k = 6
+    plan = hisv.Plan.partition(hisv.Circuit(n, gates), k, "dfs", seed=args.seed, trials=args.trials)
+    P, G = plan.num_parts, len(gates)
+    rows = []
+    for dt in ("c64", "c128"):
+        nbytes = (1 << n) * (8 if dt == "c64" else 16)
+        view = buf.view(torch.uint8)[:nbytes].view(torch.complex64 if dt == "c64" else torch.complex128)
+        st = hisv.State.wrap_tensor(view, stream)
+        plan.specialize(dt)
+        row = {"workload": "layered28", "n": n, "dtype": dt, "k": k, "strategy": "dfs",
+               "parts": P, "gates": G, "passes_saved": G / P}
+        for mode in ("part_lds", "part_spec", "auto"):
+            st.set_basis(0)
+            sec = timed_plan(st, plan, stream, steps=3, mode=mode)
+            gbs = part_pass_bytes(n, dt) * P / sec / 1e9
+            row[mode] = {"gates_per_s": G / sec, "ms_per_circuit": sec * 1e3,
+                         "pass_GBps": gbs, "frac": gbs / HBM_PEAK_GBS, "norm_after": st.norm()}
+            if not abs(row[mode]["norm_after"] - 1.0) < 1e-3:
+                raise RuntimeError(f"norm drift in layered case {dt} {mode}")
+        circ = hisv.Circuit(n, gates)
+        st.simulate_gate_per_pass(circ)  # warm
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        st.simulate_gate_per_pass(circ)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        gpp = G / (e0.elapsed_time(e1) / 1e3)
+        row["gate_per_pass_gates_per_s"] = gpp
+        row["speedup_part_lds"] = row["part_lds"]["gates_per_s"] / gpp
+        row["speedup_part_spec"] = row["part_spec"]["gates_per_s"] / gpp
+        st.close()
+        log(f"[bench] layered28 {row}")
         rows.append(row)
     return rows
 
@@ -274,6 +324,7 @@ def main() -> int:
     ap.add_argument("--no-sweep", action="store_true", help="skip the n / k / dtype sweep")
     ap.add_argument("--no-qft", action="store_true", help="skip the 32-qubit QFT comparison")
     ap.add_argument("--no-multilevel", action="store_true", help="skip the multi-level partition runs")
+    ap.add_argument("--no-layered", action="store_true", help="skip the 28-qubit layered circuit runs")
     ap.add_argument("--qft-only", action="store_true",
                     help="run only the 32-qubit QFT comparison (for kernel profiles)")
     args = ap.parse_args()
@@ -425,7 +476,7 @@ def main() -> int:
 
     st.close()
 
-    if not (args.no_sweep and args.no_multilevel and args.no_qft):
+    if not (args.no_sweep and args.no_multilevel and args.no_qft and args.no_layered):
         # the extra sections share one buffer: 256 GiB (a 35-qubit complex64 or
         # 34-qubit complex128 state) when the device has room, else the
         # headline's
@@ -440,6 +491,8 @@ def main() -> int:
             out["sweep"] = run_sweep(args, buf, stream, log)
         if not args.no_multilevel:
             out["multilevel"] = run_multilevel(args, buf, stream, log)
+        if not args.no_layered:
+            out["layered28"] = run_layered(args, buf, stream, log)
         if not args.no_qft:
             out["qft32"] = run_qft(buf, stream, log)
     del buf

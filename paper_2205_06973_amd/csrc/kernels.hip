@@ -215,42 +215,44 @@ __device__ __forceinline__ void apply_op(RegV<T, RB>& a, const OpDesc<T>* __rest
 template <typename T>
 constexpr int lds_sw() { return sizeof(T) == 4 ? 4 : 3; }
 
-// Global index bits contributed by coordinate bits [c0, c1) of a layout.
-__device__ __forceinline__ uint64_t coord_global(const StageDesc& e, const int8_t* tq, int c0, int c1,
-                                                 uint32_t v) {
-  uint64_t g = 0;
-  for (int c = c0; c < c1; ++c) g |= uint64_t((v >> (c - c0)) & 1u) << tq[e.pos[c]];
-  return g;
-}
-
-__device__ __forceinline__ uint32_t thread_tile(const StageDesc& e, int nthr_bits, uint32_t thr) {
-  uint32_t t = 0;
-  for (int c = 0; c < nthr_bits; ++c) t |= ((thr >> c) & 1u) << e.pos[c];
-  return t;
-}
-
-// Move the tile between HBM and registers in layout `e`.  The address of
-// register j is (uniform part: tile base + wave bits + register bits) plus
-// the lane's offset.  The lane offset is 64-bit: a gather/scatter layout's
-// lanes start with the lowest qubits but may also carry high ones.
-template <typename T, int RB, bool STORE>
-__device__ __forceinline__ void tile_io(cplx<T>* __restrict__ st, RegV<T, RB>& a, const StageDesc& e,
-                                        const int8_t* tq, int lb, int wb, uint64_t tbase,
-                                        uint32_t lane, uint32_t wave, bool active) {
-  const uint64_t uni = tbase + coord_global(e, tq, lb, lb + wb, wave);
-  const uint64_t lane_bytes = coord_global(e, tq, 0, lb, lane) * sizeof(cplx<T>);
-  uint64_t ro[RB > 0 ? RB : 1];
+// Sum of the per-bit offsets selected by the bits of v (global offsets);
+// masks rather than branches, since v is per lane.
+template <int N>
+__device__ __forceinline__ uint64_t bit_sum(const uint64_t* w, uint32_t v) {
+  uint64_t s = 0;
 #pragma unroll
-  for (int r = 0; r < RB; ++r) ro[r] = uint64_t(1) << tq[e.pos[lb + wb + r]];
-  if (!active) return;
+  for (int c = 0; c < N; ++c) s += w[c] & (uint64_t(0) - uint64_t(v >> c & 1u));
+  return s;
+}
+
+// XOR of the per-bit LDS offsets selected by the bits of v.
+template <int N>
+__device__ __forceinline__ uint32_t bit_xor(const uint32_t* w, uint32_t v) {
+  uint32_t s = 0;
+#pragma unroll
+  for (int c = 0; c < N; ++c) s ^= w[c] & (0u - (v >> c & 1u));
+  return s;
+}
+
+// Base index of a tile: the outer setting `tile` with a zero bit inserted at
+// every tile qubit (Alg. 1: the amplitudes of one outer setting).
+__device__ __forceinline__ uint64_t tile_base32(uint64_t tile, const int32_t* tq, int m) {
+  uint64_t b = tile;
+  for (int i = 0; i < m; ++i) {
+    const int q = tq[i];
+    const uint64_t low = b & ((uint64_t(1) << q) - 1);
+    b = ((b >> q) << (q + 1)) | low;
+  }
+  return b;
+}
+
+// Move the tile between HBM and registers.  `p` is the lane's address of
+// register 0; register j adds the (uniform) offsets of its register bits.
+template <typename T, int RB, bool STORE>
+__device__ __forceinline__ void tile_io(cplx<T>* p, RegV<T, RB>& a, const uint64_t* reg) {
 #pragma unroll
   for (int j = 0; j < (1 << RB); ++j) {
-    uint64_t o = uni;
-#pragma unroll
-    for (int r = 0; r < RB; ++r)
-      if (j >> r & 1) o += ro[r];
-    char* pj = reinterpret_cast<char*>(st + o);
-    cplx<T>* q = reinterpret_cast<cplx<T>*>(pj + lane_bytes);
+    cplx<T>* q = p + bit_sum<RB>(reg, (uint32_t)j);
     if constexpr (STORE) {
       cplx<T> v;
       v.x = a[2 * j];
@@ -265,24 +267,31 @@ __device__ __forceinline__ void tile_io(cplx<T>* __restrict__ st, RegV<T, RB>& a
 }
 
 // ---------------------------------------------------------------------------
-// part-pass kernel (Alg. 1 for one part)
+// part-pass kernel (Alg. 1 for one part), interpreting the part's ops
 // ---------------------------------------------------------------------------
 template <typename T, int RB>
 __global__ void __launch_bounds__(1024)
-part_pass_kernel(cplx<T>* __restrict__ st, const PartDesc* __restrict__ pd,
-                 const StageDesc* __restrict__ sd, const OpDesc<T>* __restrict__ ops, uint32_t xcd) {
+part_pass_kernel(cplx<T>* __restrict__ st, const IPart* __restrict__ pd,
+                 const IStage* __restrict__ sd, const OpDesc<T>* __restrict__ ops, uint32_t xcd) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
   constexpr int NR = 1 << RB;
-  constexpr int SW = lds_sw<T>();
-  const int m = pd->m, lb = pd->lb, wb = pd->wb;
+  const int m = pd->m;
   const int ne = pd->n_stages;
   const uint64_t tiles = pd->tiles;
-  const int tb_bits = lb + wb;
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const uint32_t thr = lane | (wave << lb);
-  const bool active = lane < (1 << lb);
+  const bool active = lane < (1u << pd->lb);
+
+  // Tile-independent parts of the addresses.  Bits a layout lacks have zero
+  // offsets, so lanes beyond the tile's lane bits stay in bounds.
+  uint64_t ld_lane = bit_sum<kLaneBits>(pd->load.lane, lane) +
+                           bit_sum<kMaxWaveBits>(pd->load.wave, wave);
+  uint64_t sv_lane = bit_sum<kLaneBits>(pd->store.lane, lane) +
+                           bit_sum<kMaxWaveBits>(pd->store.wave, wave);
+  const uint32_t slot0 = bit_xor<kLaneBits>(sd[0].lane, lane) ^ bit_xor<kMaxWaveBits>(sd[0].wave, wave);
+  // opaque: each stays one register value (otherwise the compiler keeps the
+  // per-bit terms live across the tile loop and re-adds them per tile)
+  asm volatile("" : "+v"(ld_lane), "+v"(sv_lane));
 
   // Tiles of this workgroup: with xcd set (grid and tile count multiples of
   // 8), XCD x = blockIdx % 8 sweeps the contiguous run [x T/8, (x+1) T/8).
@@ -298,42 +307,34 @@ part_pass_kernel(cplx<T>* __restrict__ st, const PartDesc* __restrict__ pd,
   // has 128 VGPRs, and a second tile's registers would spill)
   RegV<T, RB> a;
   for (; tile < end; tile += step) {
-    const uint64_t tbase = tile_base(tile, pd->tq, m);
-    tile_io<T, RB, false>(st, a, sd[0], pd->tq, lb, wb, tbase, lane, wave, active);
+    cplx<T>* const base = st + tile_base32(tile, pd->tq, m);
+    if (active) tile_io<T, RB, false>(base + ld_lane, a, pd->load.reg);
     // ---- execute: stages, re-laid out through LDS where the layout changes
+    uint32_t slot = slot0;  // this lane's LDS offset in the current layout
+    // an opaque copy of the lane index: keeps the per-bit lane masks of the
+    // re-layouts from being hoisted out of the tile loop into live registers
+    uint32_t ln = lane;
+    asm volatile("" : "+v"(ln));
     for (int s = 1; s < ne; ++s) {
-      const StageDesc& e = sd[s];
+      const IStage& e = sd[s];
       if (e.transition) {
-        const StageDesc& f = sd[s - 1];
-        uint32_t rs[RB > 0 ? RB : 1];
-        const uint32_t wbase = lds_slot(thread_tile(f, tb_bits, thr), SW);
-#pragma unroll
-        for (int r = 0; r < RB; ++r) rs[r] = lds_slot(1u << f.pos[tb_bits + r], SW);
+        const IStage& f = sd[s - 1];
         __syncthreads();
         if (active) {
 #pragma unroll
           for (int j = 0; j < NR; ++j) {
-            uint32_t o = wbase;
-#pragma unroll
-            for (int r = 0; r < RB; ++r)
-              if (j >> r & 1) o ^= rs[r];
             cplx<T> v;
             v.x = a[2 * j];
             v.y = a[2 * j + 1];
-            lds[o] = v;
+            *reinterpret_cast<cplx<T>*>(smem_raw + (slot ^ bit_xor<RB>(f.reg, (uint32_t)j))) = v;
           }
         }
         __syncthreads();
-        const uint32_t rbase = lds_slot(thread_tile(e, tb_bits, thr), SW);
-#pragma unroll
-        for (int r = 0; r < RB; ++r) rs[r] = lds_slot(1u << e.pos[tb_bits + r], SW);
+        slot = bit_xor<kLaneBits>(e.lane, ln) ^ bit_xor<kMaxWaveBits>(e.wave, wave);
 #pragma unroll
         for (int j = 0; j < NR; ++j) {
-          uint32_t o = rbase;
-#pragma unroll
-          for (int r = 0; r < RB; ++r)
-            if (j >> r & 1) o ^= rs[r];
-          const cplx<T> v = lds[o];
+          const cplx<T> v =
+              *reinterpret_cast<const cplx<T>*>(smem_raw + (slot ^ bit_xor<RB>(e.reg, (uint32_t)j)));
           a[2 * j] = v.x;
           a[2 * j + 1] = v.y;
         }
@@ -342,7 +343,7 @@ part_pass_kernel(cplx<T>* __restrict__ st, const PartDesc* __restrict__ pd,
       for (int o = e.op_begin; o < o1; ++o) apply_op<T, RB>(a, ops + o);
     }
     // ---- scatter (last entry is the store layout)
-    tile_io<T, RB, true>(st, a, sd[ne - 1], pd->tq, lb, wb, tbase, lane, wave, active);
+    if (active) tile_io<T, RB, true>(base + sv_lane, a, pd->store.reg);
   }
 }
 
@@ -783,8 +784,8 @@ hs_status dev_gate_pass(State* s, const Gate& g) {
 // ---- uploaded plan ----------------------------------------------------------
 struct DevicePlan {
   int device = 0;
-  PartDesc* parts = nullptr;
-  StageDesc* stages = nullptr;
+  IPart* parts = nullptr;
+  IStage* stages = nullptr;
   void* ops = nullptr;
   std::vector<PartDesc> h_parts;     // host copy (absolute offsets)
   std::vector<int> rb;               // register bits of the kernel per part
@@ -849,10 +850,35 @@ static void part_grid(const LaunchShape& ls, uint64_t tiles, int block, int per_
   *grid = (unsigned)g;
 }
 
+// Interpreter tables of one layout (host side of IStage / IoOffsets).
+template <typename T>
+static IStage interp_stage(const StageDesc& e, const PartDesc& d) {
+  IStage o{};
+  const int sw = lds_sw<T>();
+  auto slot = [&](int c) { return lds_slot(1u << e.pos[c], sw) * (uint32_t)sizeof(cplx<T>); };
+  for (int c = 0; c < d.lb; ++c) o.lane[c] = slot(c);
+  for (int c = 0; c < d.wb; ++c) o.wave[c] = slot(d.lb + c);
+  for (int r = 0; r < d.rb; ++r) o.reg[r] = slot(d.lb + d.wb + r);
+  o.op_begin = e.op_begin;
+  o.op_end = e.op_end;
+  o.transition = e.transition;
+  return o;
+}
+
+static IoOffsets interp_io(const StageDesc& e, const PartDesc& d) {
+  IoOffsets o{};
+  auto off = [&](int c) { return uint64_t(1) << d.tq[e.pos[c]]; };
+  for (int c = 0; c < d.lb; ++c) o.lane[c] = off(c);
+  for (int c = 0; c < d.wb; ++c) o.wave[c] = off(d.lb + c);
+  for (int r = 0; r < d.rb; ++r) o.reg[r] = off(d.lb + d.wb + r);
+  return o;
+}
+
 template <typename T>
 static hs_status upload_plan(Plan* p, int dtype, int dev, DevicePlan** out) {
-  std::vector<PartDesc> parts;
-  std::vector<StageDesc> stages;
+  std::vector<PartDesc> hparts;
+  std::vector<IPart> parts;
+  std::vector<IStage> stages;
   std::vector<OpDesc<T>> ops;
   auto dp = std::make_unique<DevicePlan>();
   dp->device = dev;
@@ -860,14 +886,25 @@ static hs_status upload_plan(Plan* p, int dtype, int dev, DevicePlan** out) {
   if (hs_status rc = device_info(dev, &dinfo)) return rc;
   for (const CompiledPart& cp : p->comp[dtype]) {
     PartDesc d = cp.desc;
+    if (d.rb > kMaxRegBits || d.wb > kMaxWaveBits || d.lb > kLaneBits || cp.stages.size() < 2)
+      return fail(HS_E_UNSUPPORTED, "part layout outside the interpreter's limits");
     d.stage_off = (int)stages.size();
     d.lds_bytes = cp.lds_round_trips ? (int)((size_t(1) << d.m) * sizeof(cplx<T>)) : 0;
     const int op0 = (int)ops.size();
-    for (StageDesc e : cp.stages) {
-      e.op_begin += op0;
-      e.op_end += op0;
-      stages.push_back(e);
+    for (const StageDesc& e : cp.stages) {
+      IStage is = interp_stage<T>(e, d);
+      is.op_begin += op0;
+      is.op_end += op0;
+      stages.push_back(is);
     }
+    IPart ip{};
+    ip.load = interp_io(cp.stages.front(), d);
+    ip.store = interp_io(cp.stages.back(), d);
+    ip.tiles = d.tiles;
+    ip.m = d.m;
+    ip.lb = d.lb;
+    ip.n_stages = d.n_stages;
+    for (int i = 0; i < kMaxTile; ++i) ip.tq[i] = d.tq[i];
     for (const HostOp& h : cp.ops) {
       OpDesc<T> o{};
       o.kind = h.kind;
@@ -876,7 +913,8 @@ static hs_status upload_plan(Plan* p, int dtype, int dev, DevicePlan** out) {
       for (int i = 0; i < 8; ++i) o.c[i] = (T)h.c[i];
       ops.push_back(o);
     }
-    parts.push_back(d);
+    hparts.push_back(d);
+    parts.push_back(ip);
     dp->rb.push_back(cp.rb_kernel);
     const int block = 64 << d.wb;
     int per_cu = 0;
@@ -888,13 +926,13 @@ static hs_status upload_plan(Plan* p, int dtype, int dev, DevicePlan** out) {
     dp->xcd.push_back(x);
   }
   if (ops.empty()) ops.push_back(OpDesc<T>{});
-  HIP_TRY(hipMalloc(&dp->parts, parts.size() * sizeof(PartDesc)));
-  HIP_TRY(hipMalloc(&dp->stages, stages.size() * sizeof(StageDesc)));
+  HIP_TRY(hipMalloc(&dp->parts, parts.size() * sizeof(IPart)));
+  HIP_TRY(hipMalloc(&dp->stages, stages.size() * sizeof(IStage)));
   HIP_TRY(hipMalloc(&dp->ops, ops.size() * sizeof(OpDesc<T>)));
-  HIP_TRY(hipMemcpy(dp->parts, parts.data(), parts.size() * sizeof(PartDesc), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(dp->stages, stages.data(), stages.size() * sizeof(StageDesc), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(dp->parts, parts.data(), parts.size() * sizeof(IPart), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(dp->stages, stages.data(), stages.size() * sizeof(IStage), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(dp->ops, ops.data(), ops.size() * sizeof(OpDesc<T>), hipMemcpyHostToDevice));
-  dp->h_parts = parts;
+  dp->h_parts = hparts;
   *out = dp.release();
   return HS_OK;
 }
@@ -906,8 +944,8 @@ static hs_status launch_part(State* s, DevicePlan* dp, int part) {
   const unsigned grid = dp->grid[part];
   const size_t lds = (size_t)d.lds_bytes;
   cplx<T>* st = (cplx<T>*)s->ptr;
-  const PartDesc* pd = dp->parts + part;
-  const StageDesc* sd = dp->stages + d.stage_off;
+  const IPart* pd = dp->parts + part;
+  const IStage* sd = dp->stages + d.stage_off;
   const OpDesc<T>* ops = (const OpDesc<T>*)dp->ops;
   hipStream_t str = stream_of(s);
   const uint32_t xcd = dp->xcd[part];

@@ -65,6 +65,42 @@ struct alignas(16) OpDesc {
   T c[8];
 };
 
+// Descriptors of the interpreter kernel (part_pass_kernel), built from the
+// compiled part at upload, per dtype.  Every per-bit quantity is a 32- or
+// 64-bit word, so the kernel reads them with scalar loads and a lane builds
+// its own offsets from them with a few ALU operations per bit.  Entries for
+// bits a layout does not have are zero.
+constexpr int kMaxWaveBits = 4;  // 1024-thread workgroups
+constexpr int kMaxRegBits = 4;   // widest interpreter register stage
+
+// Global offsets (in amplitudes) of the coordinate bits of a load or store
+// layout: an amplitude's index is the tile base plus the offsets of its
+// lane, wave and register bits.
+struct alignas(16) IoOffsets {
+  uint64_t lane[kLaneBits];
+  uint64_t wave[kMaxWaveBits];
+  uint64_t reg[kMaxRegBits];
+};
+
+// One entry of the stage table: swizzled LDS byte offsets of the layout's
+// coordinate bits (XOR-combined: lds_slot is linear over XOR) and the ops
+// that run in it.
+struct alignas(16) IStage {
+  uint32_t lane[kLaneBits];
+  uint32_t wave[kMaxWaveBits];
+  uint32_t reg[kMaxRegBits];
+  int32_t op_begin, op_end;
+  int32_t transition;  // 1: re-lay the tile out through LDS before the ops
+  int32_t pad;
+};
+
+struct alignas(16) IPart {
+  IoOffsets load, store;
+  uint64_t tiles;       // 2^(n-m)
+  int32_t m, lb, n_stages, pad;
+  int32_t tq[kMaxTile];  // tile bit -> global qubit, ascending
+};
+
 // A fused part on the device: U (2^w x 2^w, real block then imaginary
 // block, row-major, in the state's precision) starts at element u_off of the
 // plan's matrix buffer.

@@ -69,7 +69,7 @@ namespace {
 size_t plan_bytes(const Plan& p, hs_dtype dt) {
   size_t b = 0;
   for (const CompiledPart& cp : p.comp[dt])
-    b += sizeof(PartDesc) + cp.stages.size() * sizeof(StageDesc) +
+    b += sizeof(IPart) + cp.stages.size() * sizeof(IStage) +
          cp.ops.size() * (dt == HS_C64 ? sizeof(OpDesc<float>) : sizeof(OpDesc<double>));
   return b;
 }
