@@ -141,7 +141,10 @@ hs_status hs_device_count(int* out);
  * re-laying out through LDS (0..6; 6 = only fully contiguous 64-amplitude
  * runs); "min_tile" (0..16) = pad every tile with the lowest free qubits up
  * to this many qubits, for longer contiguous runs (0 = lanes + registers;
- * capped at the kernel's widest tile).  Launch shape of the part kernels: "xcd" (0/1) = each of the 8
+ * capped at the kernel's widest tile); "fuse2" (0/1; default 1 for the
+ * interpreter, 0 for the specialized kernels) = merge a two-qubit gate and
+ * the dense one-qubit gates around it into one 4 x 4 op where that saves
+ * instructions.  Launch shape of the part kernels: "xcd" (0/1) = each of the 8
  * XCDs sweeps one contiguous eighth of the tiles; "grid" = 0 for one
  * workgroup per tile, g in 1..64 for a persistent grid of g x the resident
  * workgroups per CU; "spec_prefetch" (0/1) = a persistent grid of the
@@ -260,9 +263,10 @@ hs_status hs_plan_part_layout(hs_plan p, int part, hs_dtype dtype, hs_exec exec,
  * entry pos[16] (coordinate bit -> tile bit; lane bits, then wave bits, then
  * register bits), op_begin, op_end (relative to the part), transition, 0;
  * entry 0 is the load layout and the last entry the store layout.
- * ops[11 * ops] (filled if ops_cap >= ops): kind, b0, b1, c[8] with kinds
+ * ops[35 * ops] (filled if ops_cap >= ops): kind, b0, b1, c[32] with kinds
  * 0 dense 2x2, 1 real 2x2, 2 diagonal, 3 diag(1, d), 4 X, 5 CX, 6 CZ,
- * 7 controlled phase, 8 SWAP. */
+ * 7 controlled phase, 8 SWAP (coefficients in c[0..7]), 9 dense 4x4 on
+ * b0 < b1 (index bit b0 + 2 bit b1; 16 complex entries, row-major). */
 hs_status hs_plan_part_descriptors(hs_plan p, int part, hs_dtype dtype, hs_exec exec, int32_t* header,
                                    int32_t* entries, int entries_cap, double* ops, int ops_cap);
 

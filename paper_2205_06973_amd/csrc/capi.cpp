@@ -42,6 +42,9 @@ static int g_min_run[2][2] = {{4, 4}, {3, 3}};  // [specialized][dtype]
 // [specialized]: both paths default to one workgroup per tile, XCD-contiguous
 static LaunchShape g_launch[2];
 static int g_min_tile[2] = {0, 0};             // [specialized]
+// Dense 4 x 4 ops: they save the interpreter's per-op dispatch and register
+// moves; the specialized kernels have neither, so they keep gate-sized ops.
+static bool g_fuse2[2] = {true, false};        // [specialized]
 
 CompileOptions default_options(hs_dtype dtype, bool spec) {
   CompileOptions o;
@@ -51,6 +54,7 @@ CompileOptions default_options(hs_dtype dtype, bool spec) {
   o.min_run = g_min_run[spec][dtype];
   o.launch = g_launch[spec];
   o.min_tile = g_min_tile[spec];
+  o.fuse2 = g_fuse2[spec];
   if (dtype == HS_C64) {
     o.swizzle = 4;
     o.max_m = 14;  // 2^14 x 8 B = 128 KiB of LDS
@@ -172,6 +176,9 @@ hs_status hs_tune(const char* key, int value) {
   } else if (k == "xcd" || (k == "prefetch" && spec)) {
     CHECK_ARG(value == 0 || value == 1, "%s must be 0 or 1", k.c_str());
     (k == "xcd" ? g_launch[spec].xcd : g_launch[spec].prefetch) = value != 0;
+  } else if (k == "fuse2") {
+    CHECK_ARG(value == 0 || value == 1, "fuse2 must be 0 or 1");
+    g_fuse2[spec] = value != 0;
   } else if (k == "min_tile") {
     CHECK_ARG(value >= 0 && value <= 16, "min_tile must be 0..16");
     g_min_tile[spec] = value;
@@ -475,11 +482,11 @@ hs_status hs_plan_part_descriptors(hs_plan p, int part, hs_dtype dtype, hs_exec 
   }
   if (ops && ops_cap >= (int)cp.ops.size()) {
     for (size_t i = 0; i < cp.ops.size(); ++i) {
-      double* o = ops + 11 * i;
+      double* o = ops + 35 * i;
       o[0] = cp.ops[i].kind;
       o[1] = cp.ops[i].b0;
       o[2] = cp.ops[i].b1;
-      for (int j = 0; j < 8; ++j) o[3 + j] = cp.ops[i].c[j];
+      for (int j = 0; j < 32; ++j) o[3 + j] = cp.ops[i].c[j];
     }
   }
   return HS_OK;

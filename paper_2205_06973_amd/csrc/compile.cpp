@@ -136,6 +136,105 @@ void emit_1q(int b, const cd u[4], std::vector<HostOp>* ops) {
   ops->push_back(op);
 }
 
+// Kind emit_1q gives u (-1: identity, no op).
+int kind_1q(const cd u[4]) {
+  if (is_exact(u[1], 0, 0) && is_exact(u[2], 0, 0)) {
+    if (is_exact(u[0], 1, 0) && is_exact(u[3], 1, 0)) return -1;
+    return is_exact(u[0], 1, 0) ? OP_D1 : OP_D;
+  }
+  if (is_exact(u[0], 0, 0) && is_exact(u[3], 0, 0) && is_exact(u[1], 1, 0) && is_exact(u[2], 1, 0))
+    return OP_X;
+  if (u[0].imag() == 0 && u[1].imag() == 0 && u[2].imag() == 0 && u[3].imag() == 0) return OP_R;
+  return OP_U;
+}
+
+// Estimated VALU instructions per wavefront for one op on A = 2^rb
+// amplitudes a lane: its arithmetic or register moves, plus what every op
+// costs the interpreter (moving the sub-state back into the loop's
+// registers, and the dispatch).
+int op_cost(int kind, int A) {
+  int c = 0;
+  switch (kind) {
+    case -1: return 0;
+    case OP_U: c = 8 * A; break;
+    case OP_R: case OP_D: c = 4 * A; break;
+    case OP_D1: case OP_X: c = 2 * A; break;
+    case OP_CX: case OP_CP: case OP_SWAP: c = A; break;
+    case OP_CZ: c = A / 2; break;
+    case OP_U2: c = 16 * A; break;
+    default: c = 8 * A;
+  }
+  return c + A + 10;
+}
+
+// 4 x 4 matrices, basis index i = bit(b0) + 2 bit(b1), row-major.
+void matmul4(const cd a[16], const cd b[16], cd out[16]) {  // out = a * b
+  cd r[16];
+  for (int i = 0; i < 4; ++i)
+    for (int k = 0; k < 4; ++k) {
+      cd z = 0;
+      for (int j = 0; j < 4; ++j) z += a[4 * i + j] * b[4 * j + k];
+      r[4 * i + k] = z;
+    }
+  for (int i = 0; i < 16; ++i) out[i] = r[i];
+}
+
+// The same operator with the roles of the two bits exchanged.
+void swap_bits4(const cd a[16], cd out[16]) {
+  auto sg = [](int i) { return (i >> 1) | ((i & 1) << 1); };
+  cd r[16];
+  for (int i = 0; i < 4; ++i)
+    for (int k = 0; k < 4; ++k) r[4 * sg(i) + sg(k)] = a[4 * i + k];
+  for (int i = 0; i < 16; ++i) out[i] = r[i];
+}
+
+// u0 on bit 0 and u1 on bit 1 of the 4 x 4 index (u1 (x) u0).
+void kron2(const cd u0[4], const cd u1[4], cd out[16]) {
+  for (int i = 0; i < 4; ++i)
+    for (int k = 0; k < 4; ++k) out[4 * i + k] = u0[2 * (i & 1) + (k & 1)] * u1[2 * (i >> 1) + (k >> 1)];
+}
+
+// A two-qubit gate on (q0 -> bit 0, q1 -> bit 1); CX: q0 controls.
+hs_status gate4(const Gate& g, cd out[16]) {
+  for (int i = 0; i < 16; ++i) out[i] = 0;
+  switch (g.kind) {
+    case HS_CX: out[0] = out[4 * 2 + 2] = out[4 * 1 + 3] = out[4 * 3 + 1] = 1; break;
+    case HS_CZ: out[0] = out[5] = out[10] = 1; out[15] = -1; break;
+    case HS_CP: out[0] = out[5] = out[10] = 1; out[15] = cd(cos(g.p[0]), sin(g.p[0])); break;
+    case HS_SWAP: out[0] = out[4 * 1 + 2] = out[4 * 2 + 1] = out[15] = 1; break;
+    default: return fail(HS_E_ARG, "unknown two-qubit kind %d", g.kind);
+  }
+  return HS_OK;
+}
+
+void set_u2(HostOp* op, const cd m[16]) {
+  for (int i = 0; i < 16; ++i) {
+    op->c[2 * i] = m[i].real();
+    op->c[2 * i + 1] = m[i].imag();
+  }
+}
+
+void get_u2(const HostOp& op, cd m[16]) {
+  for (int i = 0; i < 16; ++i) m[i] = cd(op.c[2 * i], op.c[2 * i + 1]);
+}
+
+// Left-multiply the U2 op by `m`, given on (r0 -> bit 0, r1 -> bit 1).
+void u2_apply_after(HostOp* op, int r0, const cd m[16]) {
+  cd mm[16], cur[16];
+  if (r0 == op->b0) {
+    for (int i = 0; i < 16; ++i) mm[i] = m[i];
+  } else {
+    swap_bits4(m, mm);
+  }
+  get_u2(*op, cur);
+  matmul4(mm, cur, cur);
+  set_u2(op, cur);
+}
+
+// Register-stage cut: seeded DFS orders tried per part.
+constexpr uint64_t kStageSeed = 0x5eed;
+constexpr int kStageTrials = 32;
+
 }  // namespace
 
 hs_status compile_part(int n, const std::vector<Gate>& pg, const CompileOptions& opt,
@@ -169,20 +268,26 @@ hs_status compile_part(int n, const std::vector<Gate>& pg, const CompileOptions&
     }
   }
 
-  // second-level cutoff: stages of at most rb tile bits, circuit order
+  // Second level of the multi-level partition (Sec. IV): the part's gates
+  // are cut into register stages of at most rb qubits by the DFS
+  // partitioner (Sec. IV.B.2; its first trial is the circuit order), which
+  // keeps fewest stages, hence fewest LDS re-layouts.  Stages run in
+  // creation order, a topological order of the stage graph; a stage's gates
+  // keep circuit order.
   struct Stage {
-    uint32_t bits;
-    int g0, g1;
+    uint32_t bits = 0;
+    std::vector<int> gates;
   };
-  std::vector<Stage> st;
+  for (const Gate& g : pg)
+    if (g.arity() > rb) return fail(HS_E_UNSUPPORTED, "gate wider than the register stage");
+  std::vector<int32_t> stage_of;
+  const int nst = partition_dfs(pg, build_dag(pg), rb, kStageSeed, kStageTrials, &stage_of);
+  std::vector<Stage> st(nst);
   for (int i = 0; i < (int)pg.size(); ++i) {
-    uint32_t gb = 1u << bit_of[pg[i].q0];
-    if (pg[i].q1 >= 0) gb |= 1u << bit_of[pg[i].q1];
-    if (__builtin_popcount(gb) > rb)
-      return fail(HS_E_UNSUPPORTED, "gate wider than the register stage");
-    if (st.empty() || __builtin_popcount(st.back().bits | gb) > rb) st.push_back({0u, i, i});
-    st.back().bits |= gb;
-    st.back().g1 = i + 1;
+    Stage& S = st[stage_of[i]];
+    S.bits |= 1u << bit_of[pg[i].q0];
+    if (pg[i].q1 >= 0) S.bits |= 1u << bit_of[pg[i].q1];
+    S.gates.push_back(i);
   }
 
   out->desc = PartDesc{};
@@ -231,11 +336,30 @@ hs_status compile_part(int n, const std::vector<Gate>& pg, const CompileOptions&
     for (int r = 0; r < rb; ++r) reg_of[lay[s].pos[lb + wb + r]] = r;
     cd pend[kMaxTile][4];
     bool has[kMaxTile] = {false};
+    // latest op on each register bit in this stage (-1: none): a dense
+    // 4 x 4 op that is still the latest on a bit absorbs later gates there
+    int last[kMaxTile];
+    for (int r = 0; r < kMaxTile; ++r) last[r] = -1;
+    const int A = 1 << rb;
+    auto open_u2 = [&](int r) { return opt.fuse2 && last[r] >= 0 && out->ops[last[r]].kind == OP_U2; };
+    const cd I2[4] = {1, 0, 0, 1};
     auto flush = [&](int r) {
-      if (has[r]) emit_1q(r, pend[r], &out->ops);
+      if (!has[r]) return;
       has[r] = false;
+      if (open_u2(r)) {
+        HostOp& o = out->ops[last[r]];
+        cd m[16];
+        kron2(r == o.b0 ? pend[r] : I2, r == o.b0 ? I2 : pend[r], m);
+        u2_apply_after(&o, o.b0, m);
+        return;
+      }
+      const size_t before = out->ops.size();
+      emit_1q(r, pend[r], &out->ops);
+      if (out->ops.size() > before) last[r] = (int)before;
     };
-    for (int i = st[s].g0; i < st[s].g1; ++i) {
+    // cost of applying r's pending one-qubit gates on their own
+    auto pend_cost = [&](int r) { return (!has[r] || open_u2(r)) ? 0 : op_cost(kind_1q(pend[r]), A); };
+    for (int i : st[s].gates) {
       const Gate& g = pg[i];
       const int r0 = reg_of[bit_of[g.q0]];
       if (g.arity() == 1) {
@@ -250,8 +374,38 @@ hs_status compile_part(int n, const std::vector<Gate>& pg, const CompileOptions&
         continue;
       }
       const int r1 = reg_of[bit_of[g.q1]];
+      if (opt.fuse2) {
+        cd m[16], pm[16];
+        if (hs_status rc = gate4(g, m)) return rc;
+        kron2(has[r0] ? pend[r0] : I2, has[r1] ? pend[r1] : I2, pm);
+        matmul4(m, pm, m);  // the pending one-qubit gates come first
+        const int gk = g.kind == HS_CX ? OP_CX : g.kind == HS_CZ ? OP_CZ : g.kind == HS_CP ? OP_CP : OP_SWAP;
+        if (open_u2(r0) && last[r0] == last[r1]) {  // same pair: absorb
+          u2_apply_after(&out->ops[last[r0]], r0, m);
+          has[r0] = has[r1] = false;
+          continue;
+        }
+        if (op_cost(OP_U2, A) < pend_cost(r0) + pend_cost(r1) + op_cost(gk, A)) {
+          HostOp op{};
+          op.kind = OP_U2;
+          op.b0 = std::min(r0, r1);
+          op.b1 = std::max(r0, r1);
+          cd mm[16];
+          if (r0 < r1) {
+            for (int j = 0; j < 16; ++j) mm[j] = m[j];
+          } else {
+            swap_bits4(m, mm);
+          }
+          set_u2(&op, mm);
+          has[r0] = has[r1] = false;
+          last[r0] = last[r1] = (int)out->ops.size();
+          out->ops.push_back(op);
+          continue;
+        }
+      }
       flush(r0);
       flush(r1);
+      last[r0] = last[r1] = (int)out->ops.size();
       HostOp op{};
       op.b0 = r0;
       op.b1 = r1;

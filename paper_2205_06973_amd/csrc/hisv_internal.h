@@ -71,7 +71,7 @@ std::string check_partition(const std::vector<Gate>& gates, const Dag& dag,
 // ---- part compilation (kernel descriptors) --------------------------------------
 struct HostOp {
   int kind, b0, b1;
-  double c[8];
+  double c[32];  // OP_U2: 4 x 4 complex; the others use the first 8
 };
 
 // How a part-pass grid walks the tiles of a part.  Workgroup b of a launch
@@ -121,6 +121,8 @@ struct CompileOptions {
                      // at least qubits 0..min_run-1 (runs of 2^min_run amplitudes)
   int min_tile = 0;  // pad tiles with the lowest free qubits up to this many
                      // (longer contiguous runs per tile); 0 = lanes + registers
+  bool fuse2 = false;  // merge two-qubit gates with their one-qubit neighbours
+                       // into dense 4 x 4 ops where that saves instructions
   LaunchShape launch;
 };
 

@@ -175,6 +175,36 @@ __device__ __forceinline__ void r_cp(RegV<T, RB>& a, const T* __restrict__ c) {
     if ((j & (1 << B0)) && (j & (1 << B1))) cmul_at<T, RB>(a, j, cr, ci);
 }
 
+// Dense 4 x 4 on bits B0 < B1: y = M x over every quad of amplitudes that
+// differ only in those bits (index within the quad = bit B0 + 2 bit B1).
+template <typename T, int RB, int B0, int B1>
+__device__ __forceinline__ void r_u2(RegV<T, RB>& a, const T* __restrict__ c) {
+#pragma unroll
+  for (int j = 0; j < (1 << RB); ++j) {
+    if ((j >> B0 & 1) || (j >> B1 & 1)) continue;
+    const int ix[4] = {j, j | (1 << B0), j | (1 << B1), j | (1 << B0) | (1 << B1)};
+    T xr[4], xi[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      xr[q] = a[2 * ix[q]];
+      xi[q] = a[2 * ix[q] + 1];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const T* m = c + 8 * i;
+      T yr = m[0] * xr[0] - m[1] * xi[0];
+      T yi = m[0] * xi[0] + m[1] * xr[0];
+#pragma unroll
+      for (int k = 1; k < 4; ++k) {
+        yr += m[2 * k] * xr[k] - m[2 * k + 1] * xi[k];
+        yi += m[2 * k] * xi[k] + m[2 * k + 1] * xr[k];
+      }
+      a[2 * ix[i]] = yr;
+      a[2 * ix[i] + 1] = yi;
+    }
+  }
+}
+
 template <typename T, int RB>
 __device__ __forceinline__ void apply_op(RegV<T, RB>& a, const OpDesc<T>* __restrict__ op) {
   const int kind = __builtin_amdgcn_readfirstlane(op->kind);
@@ -207,6 +237,18 @@ __device__ __forceinline__ void apply_op(RegV<T, RB>& a, const OpDesc<T>* __rest
         r_swap<T, RB, decltype(B0)::value, decltype(B1)::value>(a);
       });
       break;
+    case OP_U2:
+      if constexpr (RB >= 2) {
+        for_pair<RB>(b0, b1, [&](auto B0, auto B1) __attribute__((always_inline)) {
+          if constexpr (decltype(B0)::value < decltype(B1)::value)
+            r_u2<T, RB, decltype(B0)::value, decltype(B1)::value>(a, c);
+          else
+            __builtin_unreachable();
+        });
+        break;
+      } else {
+        __builtin_unreachable();
+      }
     default: __builtin_unreachable();
   }
 }
@@ -910,7 +952,7 @@ static hs_status upload_plan(Plan* p, int dtype, int dev, DevicePlan** out) {
       o.kind = h.kind;
       o.b0 = h.b0;
       o.b1 = h.b1;
-      for (int i = 0; i < 8; ++i) o.c[i] = (T)h.c[i];
+      for (int i = 0; i < 32; ++i) o.c[i] = (T)h.c[i];
       ops.push_back(o);
     }
     hparts.push_back(d);

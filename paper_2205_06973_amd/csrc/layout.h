@@ -56,13 +56,15 @@ enum OpKind : int32_t {
   OP_CZ = 6,    // negate where b0 = b1 = 1
   OP_CP = 7,    // multiply by c[0..1] where b0 = b1 = 1
   OP_SWAP = 8,  // exchange bits b0 and b1
-  OP_NUM = 9
+  OP_U2 = 9,    // dense 4x4 on b0 < b1, row/column index = bit b0 + 2 bit b1:
+                // c = 16 complex entries, row-major (32 reals)
+  OP_NUM = 10
 };
 
 template <typename T>
 struct alignas(16) OpDesc {
   int32_t kind, b0, b1, pad;
-  T c[8];
+  T c[32];
 };
 
 // Descriptors of the interpreter kernel (part_pass_kernel), built from the

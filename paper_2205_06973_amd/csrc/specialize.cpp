@@ -152,6 +152,30 @@ void emit_op(Emit& E, const HostOp& op) {
       }
       break;
     }
+    case OP_U2: {
+      const double* c = op.c;
+      for (int j = 0; j < N; ++j) {
+        if ((j >> op.b0 & 1) || (j >> op.b1 & 1)) continue;
+        const int ix[4] = {j, j | (1 << op.b0), j | (1 << op.b1), j | (1 << op.b0) | (1 << op.b1)};
+        o << "  { const " << E.T();
+        for (int q = 0; q < 4; ++q)
+          o << (q ? ", " : " ") << "x" << q << "r = ar" << ix[q] << ", x" << q << "i = ai" << ix[q];
+        o << ";\n";
+        for (int i = 0; i < 4; ++i) {
+          o << "    ar" << ix[i] << " =";
+          for (int k = 0; k < 4; ++k)
+            o << (k ? " + " : " ") << L(c[8 * i + 2 * k]) << "*x" << k << "r - " << L(c[8 * i + 2 * k + 1])
+              << "*x" << k << "i";
+          o << ";\n    ai" << ix[i] << " =";
+          for (int k = 0; k < 4; ++k)
+            o << (k ? " + " : " ") << L(c[8 * i + 2 * k]) << "*x" << k << "i + " << L(c[8 * i + 2 * k + 1])
+              << "*x" << k << "r";
+          o << ";\n";
+        }
+        o << "  }\n";
+      }
+      break;
+    }
     default: break;
   }
 }

@@ -265,13 +265,13 @@ class Plan:
         return m.value, s.value, t.value
 
     def part_descriptors(self, part: int, dtype: str = "c64", mode: str = "part_lds"):
-        """(header[24], entries[E, 20], ops[O, 11]) of a compiled part."""
+        """(header[24], entries[E, 20], ops[O, 35]) of a compiled part."""
         hdr = np.zeros(24, dtype=np.int32)
         _call("hs_plan_part_descriptors", self.handle, int(part), DTYPES[dtype], EXEC[mode],
               hdr.ctypes.data_as(_i32p), None, 0, None, 0)
         ne, no = int(hdr[4]), int(hdr[6])
         ent = np.zeros((ne, 20), dtype=np.int32)
-        ops = np.zeros((max(no, 1), 11), dtype=np.float64)
+        ops = np.zeros((max(no, 1), 35), dtype=np.float64)
         _call("hs_plan_part_descriptors", self.handle, int(part), DTYPES[dtype], EXEC[mode],
               hdr.ctypes.data_as(_i32p), ent.ctypes.data_as(_i32p), ne,
               ops.ctypes.data_as(_dp), max(no, 1))

@@ -64,6 +64,13 @@ def _apply_ops(R: np.ndarray, ops: np.ndarray, rb: int, nthr: int) -> None:
             src = J[((J >> b0) & 1 == 1) & ((J >> b1) & 1 == 0)]
             dst = src ^ (1 << b0) ^ (1 << b1)
             V[src], V[dst] = V[dst].copy(), V[src].copy()
+        elif kind == 9:  # dense 4x4, quad index = bit b0 + 2 bit b1
+            M = (c[0:32:2] + 1j * c[1:32:2]).reshape(4, 4)
+            base = J[((J >> b0) & 1 == 0) & ((J >> b1) & 1 == 0)]
+            rows = [base, base | (1 << b0), base | (1 << b1), base | (1 << b0) | (1 << b1)]
+            X = [V[r].copy() for r in rows]
+            for i in range(4):
+                V[rows[i]] = sum(M[i, k] * X[k] for k in range(4))
         else:
             raise ValueError(f"unknown op kind {kind}")
 

@@ -133,3 +133,25 @@ def test_spec_kernels_four_round_relayouts(tmp_path):
     finally:
         hisv.hs_tune("spec_lds_limit_kib", 64)
     np.testing.assert_allclose(got, sv.simulate(n, gates, psi0), atol=TOL["c64"], rtol=0)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_spec_kernels_with_dense_two_qubit_ops(dtype, tmp_path):
+    """Two-qubit gates merged with the dense one-qubit gates around them into
+    4 x 4 ops (off by default for these kernels, on here): the merge in the
+    part compiler and the emitted 4 x 4 code, on layered U3 + CX circuits
+    and on every two-qubit kind."""
+    n = 14
+    gates = wl.layered_circuit(n, 6, seed=45) + wl.random_circuit(
+        n, 60, ("u3", "cx", "cz", "cp", "swap", "h", "rz"), seed=46)
+    hisv.hs_tune("spec_fuse2", 1)
+    try:
+        plan = hisv.Plan.partition(hisv.Circuit(n, gates), 6, "dfs", seed=4, trials=8)
+        kinds = {int(k) for i in range(plan.num_parts)
+                 for k in plan.part_descriptors(i, dtype, "part_spec")[2][:, 0]}
+        assert 9 in kinds  # some 4 x 4 ops were formed
+        psi0 = random_state(n, 8)
+        got = run_on_host(plan, n, dtype, psi0, tmp_path)
+    finally:
+        hisv.hs_tune("spec_fuse2", 0)
+    np.testing.assert_allclose(got, sv.simulate(n, gates, psi0), atol=TOL[dtype], rtol=0)
