@@ -113,6 +113,24 @@ def layered_product_block_circuit(n: int, layers: int, seed: int):
     return gates
 
 
+def dressed_pairs_circuit(n: int, blocks: int, seed: int, span: int = 6):
+    """Blocks of U3 on two qubits, a two-qubit gate (CX, CZ, CP or SWAP)
+    on them, and U3 on both again; pairs drawn from a sliding window of
+    `span` qubits, so a part holds several dressed pairs."""
+    rng = _rng(seed)
+    out = []
+    two = ["cx", "cz", "cp", "swap"]
+    for b in range(blocks):
+        lo = (b // 8) % max(1, n - span + 1)
+        a, c = (int(x) + lo for x in rng.choice(span, size=2, replace=False))
+        dress = lambda: [("u3", q, -1, _draw_gate(rng, "u3", n)[3]) for q in (a, c)]  # noqa: E731
+        out += dress()
+        g = two[int(rng.integers(len(two)))]
+        out.append((g, a, c, _draw_gate(rng, g, n)[3]))
+        out += dress()
+    return out
+
+
 def qft_circuit(n: int):
     gates = []
     for j in range(n - 1, -1, -1):

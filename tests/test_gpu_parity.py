@@ -288,3 +288,21 @@ def test_adder_superposition(dtype):
         s = a + b
         want[_adder_index(nb, a, s % (1 << nb), s >> nb)] = 2 ** (-nb / 2)
     check(got, want, dtype)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("fuse", [1, 0])
+def test_dense_two_qubit_ops(dtype, fuse):
+    """Dressed two-qubit gates: the interpreter's 4 x 4 ops (on by default)
+    against the oracle, and the same plan compiled without them."""
+    n = 15
+    gates = wl.dressed_pairs_circuit(n, 80, seed=7)
+    hisv.hs_tune("fuse2", fuse)
+    try:
+        got, plan = run_hip(n, gates, dtype, 6, "dfs", "part_lds", init=4321)
+        kinds = {int(k) for i in range(plan.num_parts)
+                 for k in plan.part_descriptors(i, dtype, "part_lds")[2][:, 0]}
+    finally:
+        hisv.hs_tune("fuse2", 1)
+    assert (9 in kinds) == bool(fuse)
+    check(got, sv.simulate(n, gates, 4321), dtype)

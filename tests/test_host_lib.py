@@ -461,3 +461,27 @@ def test_assignment_and_part_ids_are_sized():
     cnt = ctypes.c_size_t()
     rc = hisv.lib().hs_plan_part_of_gate(plan.handle, buf, 4, ctypes.byref(cnt))
     assert rc == 1 and cnt.value == 16  # HS_E_ARG: buffer too small, count still reported
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_dense_two_qubit_ops_replay(dtype):
+    """Two-qubit gates dressed with U3 on both sides become 4 x 4 ops in the
+    interpreter's descriptors; their replay matches the oracle, and so does
+    the plan compiled without them."""
+    n = 12
+    gates = wl.dressed_pairs_circuit(n, 50, seed=5)
+    rng = np.random.default_rng(9)
+    psi0 = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    psi0 /= np.linalg.norm(psi0)
+    want = sv.simulate(n, gates, psi0)
+    for fuse in (1, 0):
+        hisv.hs_tune("fuse2", fuse)
+        try:
+            plan = hisv.Plan.partition(hisv.Circuit(n, gates), 6, "dfs", seed=2, trials=8)
+            kinds = {int(k) for i in range(plan.num_parts)
+                     for k in plan.part_descriptors(i, dtype, "part_lds")[2][:, 0]}
+            assert (9 in kinds) == bool(fuse)
+            got, _ = replay_plan(plan, n, psi0, dtype)
+        finally:
+            hisv.hs_tune("fuse2", 1)
+        np.testing.assert_allclose(got, want, atol=1e-12, rtol=0)
