@@ -31,6 +31,8 @@ Prints ONE JSON line on stdout:
   qft32      a 32-qubit QFT on a random basis state, k = 7 dagP partition:
              gate-by-gate (specialized) vs fused-unitary (matrix cores) vs
              AUTO, with the fused kernel's matrix-core roofline
+  accuracy   U^-1 U |0> against |0> on sampled amplitudes of the headline
+             state (untimed)
   cpu_baseline  the oracle (numpy complex128) on a bounded sample
 """
 
@@ -51,6 +53,23 @@ METRIC = "gates/s + HBM GB/s per part-pass at n=30..34; p50/p99 latency in servi
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6}  # dense FP32 / FP64 matrix cores
 PROFILE_DIR = os.path.join(ROOT, "profiles")
+
+
+def inverse_gates(gates):
+    """The circuit's inverse: gates in reverse order, each inverted (the
+    headline's kinds and the other parametrised ones)."""
+    out = []
+    for g in reversed(gates):
+        name, p = g[0], tuple(g[3])
+        if name in ("h", "x", "y", "z", "cx", "cz", "swap"):
+            out.append(g)
+        elif name in ("rx", "ry", "rz", "p", "cp"):
+            out.append((name, g[1], g[2], (-p[0],)))
+        elif name == "u3":
+            out.append((name, g[1], g[2], (-p[0], -p[2], -p[1])))
+        else:
+            raise ValueError(f"no inverse for {name}")
+    return out
 
 
 def part_pass_bytes(n: int, dtype: str) -> int:
@@ -447,6 +466,27 @@ def main() -> int:
         },
         "norm_after": norm,
     }
+
+    # accuracy at full size, untimed: U then U^-1 from |0> must give |0> again
+    # (the inverse runs on the interpreter: no second kernel build)
+    import numpy as np
+    st.set_basis(0)
+    st.simulate(plan, args.mode)
+    inv = hisv.Plan.partition(hisv.Circuit(n, inverse_gates(gates)), args.k, args.strategy,
+                              seed=args.seed, trials=64)
+    st.simulate(inv, "part_lds")
+    rng = np.random.default_rng(7)
+    idx = np.unique(np.concatenate([np.arange(4096, dtype=np.uint64),
+                                    rng.integers(0, 1 << n, 1 << 14, dtype=np.uint64),
+                                    np.arange((1 << n) - 4096, 1 << n, dtype=np.uint64)]))
+    amp = st.amplitudes_at(idx)
+    err = float(np.max(np.abs(amp - (idx == 0))))
+    out["accuracy"] = {
+        "check": f"U^-1 U |0> against |0> on {idx.size} amplitudes (first and last 4096, "
+                 f"2^14 random)",
+        "max_abs_err": err, "tolerance": 2e-5 if args.dtype == "c64" else 1e-12,
+    }
+    log(f"[bench] round trip max |d| = {err:.3e}")
 
     if args.gpp_gates > 0:
         e0 = torch.cuda.Event(enable_timing=True)
