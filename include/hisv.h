@@ -348,14 +348,10 @@ hs_status hs_server_create(size_t budget_bytes, int num_streams, hs_server* out)
 
 /* Queue a circuit (copied) to be partitioned with limit k (Nat when
  * strategy = NAT, DFS otherwise), simulated from |init_basis> in `dtype`,
- * and kept resident until released.  pad_qubits = 0: every part has at most
- * k qubits; pad_qubits > 0: a part's qubits together with qubits
- * 0..pad_qubits-1 number at most k (the multi-level rule of
- * hs_partition_multilevel, k = the tile).  Returns a ticket.
- * HS_E_ARITY_GT_K if a gate does not fit; HS_E_ADMISSION if the state can
- * never fit the budget.  Non-blocking. */
+ * and kept resident until released.  Returns a ticket.  HS_E_ADMISSION if
+ * the state can never fit the budget.  Non-blocking. */
 hs_status hs_server_submit(hs_server sv, int n, const hs_gate* gates, size_t count,
-                           hs_dtype dtype, uint64_t init_basis, int k, int pad_qubits,
+                           hs_dtype dtype, uint64_t init_basis, int k,
                            hs_strategy strategy, uint64_t* ticket);
 
 /* Block until the ticket's result is ready (timeout_ms < 0: no limit).

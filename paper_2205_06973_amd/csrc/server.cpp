@@ -189,16 +189,12 @@ hs_status hs_server_create(size_t budget_bytes, int num_streams, hs_server* out)
 }
 
 hs_status hs_server_submit(hs_server sv, int n, const hs_gate* gates, size_t count, hs_dtype dtype,
-                           uint64_t init_basis, int k, int pad_qubits, hs_strategy strategy,
-                           uint64_t* ticket) {
+                           uint64_t init_basis, int k, hs_strategy strategy, uint64_t* ticket) {
   if (!sv || !ticket || (!gates && count)) return fail(HS_E_ARG, "null argument");
   if (n < 1 || n > 40) return fail(HS_E_ARG, "n = %d outside [1, 40]", n);
   if (dtype != HS_C64 && dtype != HS_C128) return fail(HS_E_ARG, "bad dtype");
   if (init_basis >= (uint64_t(1) << n)) return fail(HS_E_ARG, "basis index outside the state");
   if (k < 1) return fail(HS_E_ARG, "k = %d < 1", k);
-  if (pad_qubits < 0 || pad_qubits > 64) return fail(HS_E_ARG, "pad_qubits = %d outside [0, 64]", pad_qubits);
-  const int np = std::min(pad_qubits, n);
-  const uint64_t pad = (uint64_t(1) << np) - 1;  // n <= 40
   auto r = std::make_unique<Request>();
   r->n = n;
   r->dtype = dtype;
@@ -208,14 +204,13 @@ hs_status hs_server_submit(hs_server sv, int n, const hs_gate* gates, size_t cou
   for (size_t i = 0; i < count; ++i)
     if (hs_status rc = expand_gate(n, gates[i], &gs)) return rc;
   for (const Gate& g : gs)
-    if (__builtin_popcountll(g.mask() | pad) > k)
-      return fail(HS_E_ARITY_GT_K, "a gate (with %d padding qubits) is wider than k = %d", np, k);
+    if (g.arity() > k) return fail(HS_E_ARITY_GT_K, "gate wider than k = %d", k);
   std::vector<int32_t> part;
   const Dag dag = build_dag(gs);
-  if (strategy == HS_PART_NAT) partition_nat(gs, k, &part, pad);
-  else partition_dfs(gs, dag, k, 0x5eed + count, 16, &part, pad);
+  if (strategy == HS_PART_NAT) partition_nat(gs, k, &part);
+  else partition_dfs(gs, dag, k, 0x5eed + count, 16, &part);
   r->plan = std::make_unique<Plan>();
-  if (hs_status rc = plan_build(n, gs, k, part, r->plan.get(), pad)) return rc;
+  if (hs_status rc = plan_build(n, gs, k, part, r->plan.get())) return rc;
   if (hs_status rc = plan_compile(r->plan.get(), dtype)) return rc;
   r->bytes = (size_t(1) << n) * amp_bytes(dtype) + plan_bytes(*r->plan, dtype);
   r->work = (double)r->plan->parts.size() * (double)((size_t(1) << n) * amp_bytes(dtype));

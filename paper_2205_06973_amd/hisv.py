@@ -84,7 +84,7 @@ _SIGS = {
     "hs_copy_probe": [_vp, _vp, C.c_size_t, _vp],
     "hs_server_create": [C.c_size_t, C.c_int, C.POINTER(_vp)],
     "hs_server_submit": [_vp, C.c_int, C.POINTER(hs_gate), C.c_size_t, C.c_int, _u64, C.c_int,
-                         C.c_int, C.c_int, C.POINTER(_u64)],
+                         C.c_int, C.POINTER(_u64)],
     "hs_server_wait": [_vp, _u64, C.c_int64],
     "hs_server_poll": [_vp, _u64, C.POINTER(C.c_int)],
     "hs_server_read": [_vp, _u64, _u64, _u64, _dp],
@@ -417,11 +417,11 @@ class Server:
         self.handle = h
 
     def submit(self, n: int, gates, dtype: str = "c64", init_basis: int = 0, k: int = 6,
-               strategy: str = "dfs", pad_qubits: int = 0) -> int:
+               strategy: str = "dfs") -> int:
         arr = gates_to_array(gates)
         t = _u64()
         _call("hs_server_submit", self.handle, int(n), arr, len(gates), DTYPES[dtype],
-              int(init_basis), int(k), int(pad_qubits), STRATEGIES[strategy], C.byref(t))
+              int(init_basis), int(k), STRATEGIES[strategy], C.byref(t))
         return t.value
 
     def wait(self, ticket: int, timeout_ms: int = -1) -> None:

@@ -18,16 +18,10 @@ from . import hisv
 from . import workloads as wl
 
 
-PAD_QUBITS = 6  # qubits 0..5: every tile holds them for coalescing
-
-
-def part_limit(n: int, dtype: str):
-    """(k, pad_qubits): the whole state in one tile when it fits, else parts
-    that fill the kernel's widest tile together with qubits 0..5 (the
-    multi-level rule, Sec. IV), which needs fewer passes than bounding the
-    parts' own qubits by the tile less the padding."""
-    tile = hisv.hs_max_part_qubits(dtype) + PAD_QUBITS
-    return (n, 0) if n <= tile else (tile, PAD_QUBITS)
+def part_limit(n: int, dtype: str) -> int:
+    """Whole state in one tile when it fits, else the widest part the kernel takes."""
+    whole = 14 if dtype == "c64" else 13
+    return n if n <= whole else hisv.hs_max_part_qubits(dtype)
 
 
 def run_stream(requests, budget_bytes: int = 0, num_streams: int = 4, read_check: int = 0,
@@ -48,8 +42,7 @@ def run_stream(requests, budget_bytes: int = 0, num_streams: int = 4, read_check
                 break
             time.sleep(min(0.001, target - now))
         n, gates = wl.layered28(r.seed, n=r.n, layers=r.layers)
-        k, pad = part_limit(n, r.dtype)
-        tickets.append(srv.submit(n, gates, r.dtype, 0, k, "dfs", pad))
+        tickets.append(srv.submit(n, gates, r.dtype, 0, part_limit(n, r.dtype), "dfs"))
     lat, amps = [], []
     for t in tickets:
         srv.wait(t)
