@@ -91,8 +91,12 @@ typedef struct {
 
 /* Sec. IV.B: natural topological-order cutoff (Nat), the same cutoff over
  * seeded random DFS topological orders keeping the fewest parts (DFS), and an
- * acyclic recursive-bisection partitioner with a final merge phase (DAGP). */
-typedef enum { HS_PART_NAT = 0, HS_PART_DFS = 1, HS_PART_DAGP = 2 } hs_strategy;
+ * acyclic recursive-bisection partitioner with a final merge phase (DAGP).
+ * GREEDY (not in the paper): each part grows by the ready gate that fits and
+ * adds the fewest new qubits, closing when none fits; trial 0 breaks ties by
+ * gate index, the other trials by seeded random keys; fewest parts win.
+ * Its parts are contiguous pieces of a topological order, hence acyclic. */
+typedef enum { HS_PART_NAT = 0, HS_PART_DFS = 1, HS_PART_DAGP = 2, HS_PART_GREEDY = 3 } hs_strategy;
 
 /* How hs_simulate applies a plan:
  *   GATE_PER_PASS -- ignore the partition; one sweep of the state per gate
@@ -205,7 +209,8 @@ hs_status hs_circuit_destroy(hs_circuit c);
 /* Partition the circuit's gate DAG into acyclic parts of at most k qubits
  * (Sec. IV.A conditions i-ii), minimising the part count heuristically
  * (condition iii).  `seed` and `trials` drive DFS (trial 0 is the natural
- * order, so DFS never returns more parts than Nat) and are ignored by Nat.
+ * order, so DFS never returns more parts than Nat) and GREEDY, and are
+ * ignored by Nat.
  * Parts are numbered in a topological order of the part-graph.
  * HS_E_ARITY_GT_K if a gate is wider than k; HS_E_ARG if k < 1. */
 hs_status hs_partition(hs_circuit c, int k, hs_strategy strategy, uint64_t seed,

@@ -122,6 +122,63 @@ int partition_dfs(const std::vector<Gate>& gates, const Dag& dag, int k, uint64_
   return best;
 }
 
+// Greedy growth over the ready set.  A part takes, one at a time, a ready
+// gate (all its predecessors placed) that still fits, preferring the one
+// that adds the fewest new qubits; when no ready gate fits, the part is
+// closed.  The placed gates form a topological order and every part is a
+// contiguous piece of it, so the part-graph is acyclic (as for the cutoff
+// of Sec. IV.B.1-2).  Ties go to the lowest gate index in trial 0 and to a
+// seeded random key in the other trials; the fewest parts win.
+int partition_greedy(const std::vector<Gate>& gates, const Dag& dag, int k, uint64_t seed,
+                     int trials, std::vector<int32_t>* part, uint64_t pad) {
+  const int G = (int)gates.size();
+  int best = -1;
+  std::vector<int32_t> cand(G);
+  std::vector<int> indeg(G), ready;
+  std::vector<uint64_t> key(G);
+  for (int t = 0; t < std::max(1, trials); ++t) {
+    Rng rng(seed * 0x100000001B3ull + 0x9e37ull + (uint64_t)t);
+    for (int i = 0; i < G; ++i) key[i] = t == 0 ? (uint64_t)i : rng.next();
+    ready.clear();
+    for (int i = 0; i < G; ++i) {
+      indeg[i] = (int)dag.pred[i].size();
+      if (!indeg[i]) ready.push_back(i);
+    }
+    int np = 0, placed = 0;
+    while (placed < G) {
+      uint64_t cur = pad;
+      ++np;
+      for (;;) {
+        int pick = -1, pick_new = 65;
+        for (int r = 0; r < (int)ready.size(); ++r) {
+          const int i = ready[r];
+          const uint64_t m = gates[i].mask();
+          if (__builtin_popcountll(cur | m) > k) continue;
+          const int nw = __builtin_popcountll(m & ~cur);
+          if (nw < pick_new || (nw == pick_new && key[i] < key[ready[pick]])) {
+            pick = r;
+            pick_new = nw;
+          }
+        }
+        if (pick < 0) break;
+        const int i = ready[pick];
+        ready[pick] = ready.back();
+        ready.pop_back();
+        cur |= gates[i].mask();
+        cand[i] = np - 1;
+        ++placed;
+        for (int s : dag.succ[i])
+          if (--indeg[s] == 0) ready.push_back(s);
+      }
+    }
+    if (best < 0 || np < best) {
+      best = np;
+      *part = cand;
+    }
+  }
+  return best;
+}
+
 std::string check_partition(const std::vector<Gate>& gates, const Dag& dag,
                             const std::vector<int32_t>& part, int k, uint64_t pad) {
   const int G = (int)gates.size();
