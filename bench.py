@@ -2,12 +2,13 @@
 """Benchmark of the partitioned state-vector hot path on one MI355X.
 
 A step is one pass of the whole path over one circuit: the gate list is
-loaded, partitioned (DFS, Sec. IV.B.2) and compiled (the specialized part
+loaded, partitioned (greedy ready-set partitioner; --strategy picks Nat,
+DFS or dagP of Sec. IV.B instead) and compiled (the specialized part
 kernels come from the kernel cache after the warmup), every part is applied
 as one in-place Gather-Execute-Scatter sweep of a state resident in HBM
 (Alg. 1), and the FP64 norm is read back.  Default workload: a 34-qubit random
 circuit of 1,000 gates drawn uniformly from {H, RZ, RX, CX, CZ}, complex64
-state (128 GiB), DFS partition (Sec. IV.B.2) with at most k qubits per part.
+state (128 GiB), acyclic partition with at most k qubits per part.
 
 Prints ONE JSON line on stdout:
   value      gates/s over the timed steps (wall clock, synchronized; host
@@ -23,12 +24,12 @@ Prints ONE JSON line on stdout:
              that fit (35-qubit complex64, 34-qubit complex128; 256 GiB):
              one timed step each
   multilevel the same circuits with the multi-level partition (first level
-             bounded by the padded LDS tile, 13 qubits complex64 / 12
+             bounded by the padded LDS tile, 14 qubits complex64 / 13
              complex128; second level = register stages)
-  layered28  28 qubits, 40 layers (U3 on every qubit + CX matching), DFS
+  layered28  28 qubits, 40 layers (U3 on every qubit + CX matching),
              k = 6, complex64 and complex128: interpreter (PART_LDS) vs
              specialized kernels vs AUTO vs one sweep per gate
-  qft32      a 32-qubit QFT on a random basis state, k = 7 dagP partition:
+  qft32      a 32-qubit QFT on a random basis state, k = 7:
              gate-by-gate (specialized) vs fused-unitary (matrix cores) vs
              AUTO, with the fused kernel's matrix-core roofline
   accuracy   U^-1 U |0> against |0> on sampled amplitudes of the headline
@@ -165,7 +166,8 @@ def run_sweep(args, buf, stream, log):
         st = hisv.State.wrap_tensor(view, stream)
         st.set_basis(0)
         _, gates = wl.random34(args.seed, n=n, num_gates=args.gates)
-        plan = hisv.Plan.partition(hisv.Circuit(n, gates), k, "dfs", seed=args.seed, trials=args.trials)
+        plan = hisv.Plan.partition(hisv.Circuit(n, gates), k, args.strategy, seed=args.seed,
+                                   trials=args.trials)
         plan.specialize(dt)
         sec = timed_plan(st, plan, stream)
         norm = st.norm()
@@ -188,7 +190,8 @@ def run_multilevel(args, buf, stream, log):
     from paper_2205_06973_amd import hisv
     from paper_2205_06973_amd import workloads as wl
     rows = []
-    cases = [("random34", 34, "c64", "dfs"), ("random33", 33, "c128", "dfs"), ("qft32", 32, "c64", "dagp")]
+    s = args.strategy
+    cases = [("random34", 34, "c64", s), ("random33", 33, "c128", s), ("qft32", 32, "c64", s)]
     for name, n, dt, strat in cases:
         amp = 8 if dt == "c64" else 16
         if (1 << n) * amp > buf.numel() * buf.element_size():
@@ -227,7 +230,8 @@ def run_layered(args, buf, stream, log):
     from paper_2205_06973_amd import workloads as wl
     n, gates = wl.layered28(args.seed)
     k = 6
-    plan = hisv.Plan.partition(hisv.Circuit(n, gates), k, "dfs", seed=args.seed, trials=args.trials)
+    plan = hisv.Plan.partition(hisv.Circuit(n, gates), k, args.strategy, seed=args.seed,
+                               trials=args.trials)
     P, G = plan.num_parts, len(gates)
     rows = []
     for dt in ("c64", "c128"):
@@ -235,7 +239,7 @@ def run_layered(args, buf, stream, log):
         view = buf.view(torch.uint8)[:nbytes].view(torch.complex64 if dt == "c64" else torch.complex128)
         st = hisv.State.wrap_tensor(view, stream)
         plan.specialize(dt)
-        row = {"workload": "layered28", "n": n, "dtype": dt, "k": k, "strategy": "dfs",
+        row = {"workload": "layered28", "n": n, "dtype": dt, "k": k, "strategy": args.strategy,
                "parts": P, "gates": G, "passes_saved": G / P}
         for mode in ("part_lds", "part_spec", "auto"):
             st.set_basis(0)
@@ -264,7 +268,7 @@ def run_layered(args, buf, stream, log):
     return rows
 
 
-def run_qft(buf, stream, log):
+def run_qft(buf, stream, log, strategy="greedy", trials=256):
     """32-qubit QFT (H + controlled-phase ladder + swaps) on a random basis
     state, dagP k = 7: gate-by-gate specialized kernels (a) vs the fused dense
     unitary on matrix cores (b) vs AUTO; sampled amplitudes against the closed
@@ -280,13 +284,13 @@ def run_qft(buf, stream, log):
     st = hisv.State.wrap_tensor(view, stream)
     gates = wl.qft_circuit(n)
     x = wl.random_basis_index(n, 3)
-    plan = hisv.Plan.partition(hisv.Circuit(n, gates), 7, "dagp", seed=0)
+    plan = hisv.Plan.partition(hisv.Circuit(n, gates), 7, strategy, seed=0, trials=trials)
     plan.specialize(dt)
     P = plan.num_parts
     idx = np.unique(np.random.default_rng(1).integers(0, 1 << n, 4096, dtype=np.uint64))
     want = np.exp(2j * np.pi * ((int(x) * idx.astype(object)) % (1 << n)).astype(np.float64)
                   / (1 << n)) / 2 ** (n / 2)
-    out = {"n": n, "dtype": dt, "k": 7, "strategy": "dagp", "parts": P, "gates": len(gates)}
+    out = {"n": n, "dtype": dt, "k": 7, "strategy": strategy, "parts": P, "gates": len(gates)}
     for mode in ("part_spec", "part_fused", "auto"):
         st.set_basis(int(x))
         torch.cuda.synchronize()
@@ -327,8 +331,9 @@ def main() -> int:
     ap.add_argument("--gates", type=int, default=1000)
     ap.add_argument("--k", type=int, default=7)
     ap.add_argument("--dtype", default="c64", choices=["c64", "c128"])
-    ap.add_argument("--strategy", default="dfs", choices=["nat", "dfs", "dagp"])
-    ap.add_argument("--trials", type=int, default=512, help="DFS orders tried per partition")
+    ap.add_argument("--strategy", default="greedy", choices=["nat", "dfs", "dagp", "greedy"])
+    ap.add_argument("--trials", type=int, default=256,
+                    help="orders (DFS) or tie-break draws (greedy) tried per partition")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--mode", default="part_spec", choices=["part_lds", "part_spec", "auto"])
     ap.add_argument("--gpp-gates", type=int, default=48,
@@ -370,7 +375,7 @@ def main() -> int:
         stream = torch.cuda.Stream()
         with torch.cuda.stream(stream):
             qbuf = torch.empty(1 << 32, dtype=torch.complex64, device="cuda")
-        print(json.dumps({"qft32": run_qft(qbuf, stream, log)}), flush=True)
+        print(json.dumps({"qft32": run_qft(qbuf, stream, log, args.strategy, args.trials)}), flush=True)
         return 0
     n, G = args.n, args.gates
     _, gates = wl.random34(args.seed, n=n, num_gates=G)
@@ -534,7 +539,7 @@ def main() -> int:
         if not args.no_layered:
             out["layered28"] = run_layered(args, buf, stream, log)
         if not args.no_qft:
-            out["qft32"] = run_qft(buf, stream, log)
+            out["qft32"] = run_qft(buf, stream, log, args.strategy, args.trials)
     del buf
     torch.cuda.empty_cache()
 

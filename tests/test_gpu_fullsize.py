@@ -107,7 +107,7 @@ def test_layered28_round_trip(dtype):
     assert report("layered28 U^-1 U", np.abs(got - want), n) <= TOL[dtype]
 
 
-@pytest.mark.parametrize("strategy", ["dagp", "ml-dagp"])
+@pytest.mark.parametrize("strategy", ["dagp", "ml-dagp", "greedy", "ml-greedy"])
 def test_qft32_closed_form(strategy):
     n, gates, x = wl.qft32(0)
     st, buf = simulate(n, gates, "c64", 7, strategy, init=x)
@@ -120,7 +120,8 @@ def test_qft32_closed_form(strategy):
 
 
 @pytest.mark.parametrize("n,dtype,strategy", [(34, "c64", "dfs"), (33, "c128", "dfs"),
-                                              (34, "c64", "ml-dfs"), (33, "c128", "ml-dfs")])
+                                              (34, "c64", "ml-dfs"), (33, "c128", "ml-dfs"),
+                                              (34, "c64", "greedy"), (33, "c128", "ml-greedy")])
 def test_random34_product_block(n, dtype, strategy):
     gates = wl.product_block_circuit(n, 1000, wl.RANDOM34_KINDS, seed=5)
     st, buf = simulate(n, gates, dtype, 7, strategy)
@@ -151,7 +152,8 @@ def test_largest_state_round_trip(n, dtype):
 @pytest.mark.parametrize("n,dtype", [(34, "c64"), (33, "c128")])
 def test_random34_round_trip(n, dtype):
     _, gates = wl.random34(0, n=n)
-    st, buf = simulate(n, gates, dtype, 7, "dfs", extra=sv.inverse_circuit(gates))
+    # the headline configuration: greedy partition, k = 7, specialized kernels
+    st, buf = simulate(n, gates, dtype, 7, "greedy", extra=sv.inverse_circuit(gates))
     idx = sample_indices(n, 1 << 14, 7)
     got = st.amplitudes_at(idx)
     want = np.zeros(idx.size, dtype=np.complex128)
