@@ -77,15 +77,17 @@ def _counter_per_kernel(path: str, counter: str) -> dict[str, list[float]]:
 
 
 def traffic(fetch_csv: str, write_csv: str, key: str, command: str, copy_bytes: int,
-            khash: str, txt_out: str | None = None) -> dict:
+            khash: str, txt_out: str | None = None, kernel: str = "part_pass_spec") -> dict:
     fetch = _counter_per_kernel(fetch_csv, "FETCH_SIZE")
     write = _counter_per_kernel(write_csv, "WRITE_SIZE")
     cf = [v for k, v in fetch.items() if k.startswith("copy_probe_kernel")][0]
     cw = [v for k, v in write.items() if k.startswith("copy_probe_kernel")][0]
     f_scale = copy_bytes / (sum(cf) / len(cf) * 1024.0)
     w_scale = copy_bytes / (sum(cw) / len(cw) * 1024.0)
-    pf = [v for k, vs in fetch.items() if k.startswith("part_pass") for v in vs]
-    pw = [v for k, vs in write.items() if k.startswith("part_pass") for v in vs]
+    # only the profiled kernel (other part kernels in the same run, such as
+    # the interpreter, are not part of the record)
+    pf = [v for k, vs in fetch.items() if k == kernel for v in vs]
+    pw = [v for k, vs in write.items() if k == kernel for v in vs]
     fb = sum(pf) / len(pf) * 1024.0 * f_scale
     wb = sum(pw) / len(pw) * 1024.0 * w_scale
     rec = {"bytes_per_launch": fb + wb, "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
@@ -94,13 +96,13 @@ def traffic(fetch_csv: str, write_csv: str, key: str, command: str, copy_bytes: 
     n, dt = key.split("_")[0][1:], key.split("_")[1]
     algo = 2 * (1 << int(n)) * (8 if dt == "c64" else 16)
     kib_f, kib_w = sum(pf) / len(pf), sum(pw) / len(pw)
-    txt = [f"# HBM traffic per launch of the part-pass kernel, workload {key}",
+    txt = [f"# HBM traffic per launch of {kernel}, workload {key}",
            f"# commands (run from /tmp with TMPDIR=/tmp, one counter per run): {command}",
            f"# kernel hash (generated part kernels): {khash}", "",
            f"calibration (copy_probe_kernel, {copy_bytes} B read + {copy_bytes} B written):",
            f"  FETCH_SIZE {sum(cf) / len(cf):14.1f} KiB -> scale {f_scale:.4f}",
            f"  WRITE_SIZE {sum(cw) / len(cw):14.1f} KiB -> scale {w_scale:.4f}", "",
-           f"part-pass kernel, mean over {len(pf)} launches:",
+           f"{kernel}, mean over {len(pf)} launches:",
            f"  FETCH_SIZE {kib_f:14.1f} KiB x {f_scale:.4f} = {fb / 1e9:.3f} GB",
            f"  WRITE_SIZE {kib_w:14.1f} KiB x {w_scale:.4f} = {wb / 1e9:.3f} GB",
            f"  total {(fb + wb) / 1e9:.3f} GB per launch; algorithmic 2 * 2^{n} * "
