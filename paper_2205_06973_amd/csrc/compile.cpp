@@ -548,17 +548,19 @@ double spec_part_cost(const CompiledPart& cp) {
 // The fused kernel does 8 * 2^w flops per amplitude on matrix cores against
 // 2 * s bytes of HBM traffic (s = 8 or 16 bytes per amplitude).  At the
 // FP32 / FP64 matrix peaks (157.3 / 78.6 TFLOP/s) against ~6 TB/s that is
-// about 0.02 * 2^w sweeps for either precision: w <= 5 stays HBM-bound (the
-// measured cost is 1.05 / 1.2 sweeps), w = 6 and 7 are matrix-core bound
-// (2.2 / 4.0 sweeps measured on a 32-qubit QFT).  When the part holds one of
-// qubits 0..3 the 16 columns of a wave are not one contiguous run and the
-// HBM-bound widths measured ~1.7 sweeps.
+// about 0.02 * 2^w sweeps for either precision: w = 6 and 7 are matrix-core
+// bound (2.2 / 4.0 sweeps measured on a 32-qubit QFT, 2.15 for w = 6 on a
+// 28-qubit state).  w <= 5 should stay HBM-bound, but measured 1.05 / 1.2
+// sweeps on 34-qubit states and 1.6 / 1.76 on 28-qubit ones; the larger
+// figures are used, so AUTO takes these widths only where the gate-by-gate
+// kernels are clearly slower.  When the part holds one of qubits 0..3 the
+// 16 columns of a wave are not one contiguous run: ~1.7-1.85 sweeps.
 double fused_part_cost(const FusedPart& f, hs_dtype dt) {
   (void)dt;
   const bool coalesced = f.pq[0] == 0 && f.pq[1] == 1 && f.pq[2] == 2 && f.pq[3] == 3;
   switch (f.w) {
-    case 4: return coalesced ? 1.05 : 1.7;
-    case 5: return coalesced ? 1.2 : 1.8;
+    case 4: return coalesced ? 1.6 : 1.75;
+    case 5: return coalesced ? 1.76 : 1.85;
     case 6: return 2.2;
     case 7: return 4.0;
     default: return 1e30;
