@@ -351,8 +351,8 @@ typedef struct hs_server_* hs_server;
  * requests; several requests are in flight on the device at once. */
 hs_status hs_server_create(size_t budget_bytes, int num_streams, hs_server* out);
 
-/* Queue a circuit (copied) to be partitioned with limit k (Nat when
- * strategy = NAT, DFS otherwise), simulated from |init_basis> in `dtype`,
+/* Queue a circuit (copied) to be partitioned with limit k by `strategy`
+ * (DFS and GREEDY with 16 trials), simulated from |init_basis> in `dtype`,
  * and kept resident until released.  Returns a ticket.  HS_E_ADMISSION if
  * the state can never fit the budget.  Non-blocking. */
 hs_status hs_server_submit(hs_server sv, int n, const hs_gate* gates, size_t count,

@@ -207,8 +207,13 @@ hs_status hs_server_submit(hs_server sv, int n, const hs_gate* gates, size_t cou
     if (g.arity() > k) return fail(HS_E_ARITY_GT_K, "gate wider than k = %d", k);
   std::vector<int32_t> part;
   const Dag dag = build_dag(gs);
-  if (strategy == HS_PART_NAT) partition_nat(gs, k, &part);
-  else partition_dfs(gs, dag, k, 0x5eed + count, 16, &part);
+  switch (strategy) {
+    case HS_PART_NAT: partition_nat(gs, k, &part); break;
+    case HS_PART_DFS: partition_dfs(gs, dag, k, 0x5eed + count, 16, &part); break;
+    case HS_PART_DAGP: partition_dagp(gs, dag, n, k, 0x5eed + count, &part); break;
+    case HS_PART_GREEDY: partition_greedy(gs, dag, k, 0x5eed + count, 16, &part); break;
+    default: return fail(HS_E_ARG, "unknown strategy %d", (int)strategy);
+  }
   r->plan = std::make_unique<Plan>();
   if (hs_status rc = plan_build(n, gs, k, part, r->plan.get())) return rc;
   if (hs_status rc = plan_compile(r->plan.get(), dtype)) return rc;

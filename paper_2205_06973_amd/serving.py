@@ -25,7 +25,7 @@ def part_limit(n: int, dtype: str) -> int:
 
 
 def run_stream(requests, budget_bytes: int = 0, num_streams: int = 4, read_check: int = 0,
-               time_scale: float = 1.0):
+               time_scale: float = 1.0, strategy: str = "greedy"):
     """Submit `requests` (workloads.Request) at their arrival times.
 
     Returns per-request latencies (s), total wall time, server stats and the
@@ -42,7 +42,7 @@ def run_stream(requests, budget_bytes: int = 0, num_streams: int = 4, read_check
                 break
             time.sleep(min(0.001, target - now))
         n, gates = wl.layered28(r.seed, n=r.n, layers=r.layers)
-        tickets.append(srv.submit(n, gates, r.dtype, 0, part_limit(n, r.dtype), "dfs"))
+        tickets.append(srv.submit(n, gates, r.dtype, 0, part_limit(n, r.dtype), strategy))
     lat, amps = [], []
     for t in tickets:
         srv.wait(t)
