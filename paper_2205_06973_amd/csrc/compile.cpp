@@ -270,18 +270,24 @@ hs_status compile_part(int n, const std::vector<Gate>& pg, const CompileOptions&
 
   // Second level of the multi-level partition (Sec. IV): the part's gates
   // are cut into register stages of at most rb qubits by the DFS
-  // partitioner (Sec. IV.B.2; its first trial is the circuit order), which
-  // keeps fewest stages, hence fewest LDS re-layouts.  Stages run in
-  // creation order, a topological order of the stage graph; a stage's gates
-  // keep circuit order.
+  // partitioner (Sec. IV.B.2; its first trial is the circuit order) and by
+  // the greedy one; the cut with fewer stages, hence fewer LDS re-layouts,
+  // is kept (DFS on ties).  Stages run in creation order, a topological
+  // order of the stage graph; a stage's gates keep circuit order.
   struct Stage {
     uint32_t bits = 0;
     std::vector<int> gates;
   };
   for (const Gate& g : pg)
     if (g.arity() > rb) return fail(HS_E_UNSUPPORTED, "gate wider than the register stage");
-  std::vector<int32_t> stage_of;
-  const int nst = partition_dfs(pg, build_dag(pg), rb, kStageSeed, kStageTrials, &stage_of);
+  std::vector<int32_t> stage_of, greedy_of;
+  const Dag pdag = build_dag(pg);
+  int nst = partition_dfs(pg, pdag, rb, kStageSeed, kStageTrials, &stage_of);
+  const int ngr = partition_greedy(pg, pdag, rb, kStageSeed, kStageTrials, &greedy_of);
+  if (ngr < nst) {
+    nst = ngr;
+    stage_of.swap(greedy_of);
+  }
   std::vector<Stage> st(nst);
   for (int i = 0; i < (int)pg.size(); ++i) {
     Stage& S = st[stage_of[i]];
