@@ -349,6 +349,8 @@ def main() -> int:
     ap.add_argument("--no-qft", action="store_true", help="skip the 32-qubit QFT comparison")
     ap.add_argument("--no-multilevel", action="store_true", help="skip the multi-level partition runs")
     ap.add_argument("--no-layered", action="store_true", help="skip the 28-qubit layered circuit runs")
+    ap.add_argument("--layered-only", action="store_true",
+                    help="run only the 28-qubit layered section (for profiling)")
     ap.add_argument("--qft-only", action="store_true",
                     help="run only the 32-qubit QFT comparison (for kernel profiles)")
     args = ap.parse_args()
@@ -371,6 +373,12 @@ def main() -> int:
     for kv in args.tune:
         key, val = kv.split("=")
         hisv.hs_tune(key, int(val))
+    if args.layered_only:
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            lbuf = torch.empty(1 << 28, dtype=torch.complex128, device="cuda")
+        print(json.dumps({"layered28": run_layered(args, lbuf, stream, log)}), flush=True)
+        return 0
     if args.qft_only:
         stream = torch.cuda.Stream()
         with torch.cuda.stream(stream):

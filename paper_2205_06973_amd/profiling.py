@@ -4,6 +4,7 @@
     python -m paper_2205_06973_amd.profiling traffic <fetch.csv> <write.csv> <key> "<command>" \
         --copy-bytes B --kernel-hash H [--txt out.txt]
     python -m paper_2205_06973_amd.profiling mfma <counters.csv> <stats.csv> <out.txt> "<command>"
+    python -m paper_2205_06973_amd.profiling valu <counters.csv> <stats.csv> <out.txt> "<command>"
 
 `stats` condenses a `--kernel-trace --stats` kernel_stats.csv.  `traffic`
 reads two `--pmc` counter_collection.csv files (FETCH_SIZE in one run,
@@ -152,12 +153,49 @@ def mfma(counters_csv: str, stats_csv: str, out_path: str, command: str) -> None
     print("\n".join(lines))
 
 
+VALU_COUNTERS = ("SQ_INSTS_VALU", "SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU_MUL_F32",
+                 "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_ACTIVE_INST_VALU",
+                 "SQ_WAVES", "GRBM_GUI_ACTIVE")
+
+
+def valu(counters_csv: str, stats_csv: str, out_path: str, command: str) -> None:
+    """Vector-ALU summary of the part kernels: instructions per wavefront,
+    the share that is the gates' own FMA/MUL arithmetic, and how busy the
+    VALUs were (SQ_ACTIVE_INST_VALU counts 4-cycle issue slots per SIMD;
+    GRBM_GUI_ACTIVE is summed over the 8 XCDs; 1024 SIMDs)."""
+    ctr: dict[str, dict[str, list[float]]] = {}
+    for r in csv.DictReader(open(counters_csv)):
+        ctr.setdefault(_short(r["Kernel_Name"]), {}).setdefault(r["Counter_Name"], []).append(
+            float(r["Counter_Value"]))
+    avg_ns = {_short(r["Name"]): float(r["AverageNs"]) for r in csv.DictReader(open(stats_csv))}
+    lines = ["# vector-ALU counters per dispatch (rocprofv3 --pmc) and kernel-trace durations",
+             f"# command: {command}", f"# kernel source hash: {kernel_source_hash()}",
+             "# arith = FMA + MUL instructions (F32 or F64) / all VALU instructions;",
+             "# busy = SQ_ACTIVE_INST_VALU * 4 / (GRBM_GUI_ACTIVE / 8 * 1024 SIMDs)", "",
+             f"{'kernel':36s} {'calls':>6s} {'avg_us':>10s} {'VALU/wave':>10s} {'arith':>6s} {'busy':>6s}"]
+    mean = lambda d, c: sum(d.get(c, [0.0])) / max(1, len(d.get(c, [0.0])))  # noqa: E731
+    for k, d in sorted(ctr.items()):
+        if not k.startswith("part_pass") or "SQ_INSTS_VALU" not in d:
+            continue
+        v = mean(d, "SQ_INSTS_VALU")
+        ar = sum(mean(d, c) for c in VALU_COUNTERS[1:5])
+        waves = mean(d, "SQ_WAVES")
+        busy = mean(d, "SQ_ACTIVE_INST_VALU") * 4 / (mean(d, "GRBM_GUI_ACTIVE") / 8 * 1024)
+        lines.append(f"{k:36s} {len(d['SQ_INSTS_VALU']):6d} {avg_ns.get(k, 0) / 1e3:10.1f} "
+                     f"{v / max(1.0, waves):10.0f} {ar / max(1.0, v):6.3f} {busy:6.3f}")
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main(argv):
     if argv[0] == "stats":
         stats(argv[1], argv[2], argv[3],
               argv[argv.index("--kernel-hash") + 1] if "--kernel-hash" in argv else None)
     elif argv[0] == "mfma":
         mfma(argv[1], argv[2], argv[3], argv[4])
+    elif argv[0] == "valu":
+        valu(argv[1], argv[2], argv[3], argv[4])
     elif argv[0] == "traffic":
         cb = int(argv[argv.index("--copy-bytes") + 1])
         txt = argv[argv.index("--txt") + 1] if "--txt" in argv else None
