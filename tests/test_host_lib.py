@@ -546,3 +546,21 @@ def test_dense_two_qubit_ops_replay(dtype):
         finally:
             hisv.hs_tune("fuse2", 1)
         np.testing.assert_allclose(got, want, atol=1e-12, rtol=0)
+
+
+def test_bench_inverse_gates_undo_the_circuit():
+    """bench.py's accuracy check runs U then its inverse: the inverse it
+    builds must undo U (checked with the oracle, every kind it handles)."""
+    import importlib.util
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "bench.py")
+    spec = importlib.util.spec_from_file_location("bench_under_test", path)
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    n = 7
+    kinds = ("h", "x", "y", "z", "rx", "ry", "rz", "p", "u3", "cx", "cz", "cp", "swap")
+    gates = wl.random_circuit(n, 150, kinds, seed=21)
+    psi0 = _random_state(n, 3)
+    got = sv.simulate(n, gates + bench.inverse_gates(gates), psi0)
+    np.testing.assert_allclose(got, psi0, atol=1e-12, rtol=0)
+    with pytest.raises(ValueError):
+        bench.inverse_gates([("s", 0, -1, ())])
