@@ -13,8 +13,9 @@ Modules
 -------
 statevector
     complex128 gate-at-a-time simulator (Sec. II.A-B, Sec. III.A) and a
-    literal Gather-Execute-Scatter executor (Alg. 1, Sec. III.C) used to pin
-    that the hierarchical method reaches the gate-at-a-time result.
+    part-by-part executor over a partition (Sec. III.C: each part acts on the
+    sub-vectors addressed by its qubits) used to pin that the hierarchical
+    method reaches the gate-at-a-time result.
 partition
     gate DAG (Sec. IV.A), working-set size, an exact validity check of an
     acyclic partition (Sec. IV.A conditions i-ii), the natural-order cutoff

@@ -20,12 +20,12 @@ What it follows
   the design notes (rotation RZ keeps its global phase:
   RZ(t) = diag(e^{-it/2}, e^{it/2})).
 * Sec. II.A: probabilities are |amplitude|^2 (the paper writes alpha^2).
-* Alg. 1 (Sec. III.C): ``simulate_alg1`` executes a given partition literally
-  -- for every setting of the qubits outside a part, gather the 2^w
-  amplitudes addressed by the part's qubits into a small inner vector, run
-  the part's gates on it, scatter back.  The inner slots take the part's
-  qubits in ascending global order, which matches the worked example of
-  Sec. III.C (S0 = {q1, q0} -> in_sv[q1, q0]).
+* Sec. III.C: ``simulate_alg1`` applies a given partition part by part: the
+  state is viewed as one sub-vector of 2^w amplitudes (the part's qubits)
+  per setting of the other qubits, the part's gates act on every sub-vector,
+  and the view is undone.  The inner slots take the part's qubits in
+  ascending global order, which matches the worked example of Sec. III.C
+  (S0 = {q1, q0} -> in_sv[q1, q0]).
 
 Two-qubit gates are written by what they do to amplitudes, so no 4x4
 basis-ordering convention is needed:
@@ -255,59 +255,71 @@ def inverse_circuit(gates):
 
 
 # ---------------------------------------------------------------------------
-# Alg. 1 executed literally (small n only: pure-Python loop over settings)
+# Hierarchical execution over a partition (Sec. III.C), by tensor views
 # ---------------------------------------------------------------------------
 
-def gather_addresses(n: int, part_qubits) -> np.ndarray:
-    """Alg. 1 gather map: row r = outer setting r, column j = inner slot j.
+def _part_perm(n: int, part_qubits) -> list[int]:
+    """Axis order that views a (2,)*n state tensor as (outer qubits, part qubits).
 
-    Entry [r, j] is the index in out_sv of the amplitude that lands in
-    in_sv[j] for the r-th setting of the qubits outside the part.  Bit b of r
-    is the value of the b-th smallest outer qubit; bit b of j is the value of
-    the b-th smallest part qubit (Sec. III.C: S0 = {q1, q0} -> in_sv[q1, q0]).
+    numpy's row-major reshape of the 2^n vector puts qubit q on axis n-1-q
+    (the last axis is the least significant bit).  After this permutation
+    the leading axes are the qubits outside the part, highest first, and the
+    trailing axes the part's qubits, highest first; flattening the two groups
+    gives (row r, column j) with bit b of r = the b-th smallest outer qubit
+    and bit b of j = the b-th smallest part qubit -- the inner-slot order of
+    the worked example of Sec. III.C (S0 = {q1, q0} -> in_sv[q1, q0]).
     """
-    qubits = sorted(int(q) for q in part_qubits)
-    outer = [q for q in range(n) if q not in qubits]
-    w = len(qubits)
-    addr = np.zeros((1 << len(outer), 1 << w), dtype=np.int64)
-    for r in range(1 << len(outer)):
-        base = 0
-        for bit, q in enumerate(outer):
-            if (r >> bit) & 1:
-                base |= 1 << q
-        for j in range(1 << w):
-            a = base
-            for bit, q in enumerate(qubits):
-                if (j >> bit) & 1:
-                    a |= 1 << q
-            addr[r, j] = a
-    return addr
+    part = sorted(int(q) for q in part_qubits)
+    outer = [q for q in range(n) if q not in part]
+    return [n - 1 - q for q in reversed(outer)] + [n - 1 - q for q in reversed(part)]
+
+
+def split_by_part(psi: np.ndarray, n: int, part_qubits) -> np.ndarray:
+    """The state as a (2^(n-w), 2^w) matrix: row r holds the 2^w amplitudes of
+    outer setting r (Sec. III.C: the sub-vectors addressed by the part's
+    qubits, one per setting of the others; disjoint and exhaustive)."""
+    w = len(set(int(q) for q in part_qubits))
+    t = np.asarray(psi).reshape((2,) * n).transpose(_part_perm(n, part_qubits))
+    return np.ascontiguousarray(t).reshape(1 << (n - w), 1 << w)
+
+
+def merge_by_part(mat: np.ndarray, n: int, part_qubits) -> np.ndarray:
+    """Inverse of split_by_part: the matrix of sub-vectors back to the 2^n state."""
+    perm = _part_perm(n, part_qubits)
+    t = np.asarray(mat).reshape((2,) * n).transpose(np.argsort(perm))
+    return np.ascontiguousarray(t).reshape(1 << n)
+
+
+def gather_addresses(n: int, part_qubits) -> np.ndarray:
+    """Index map of the split: entry [r, j] is the state index whose amplitude
+    lands in inner slot j for outer setting r."""
+    return split_by_part(np.arange(1 << n, dtype=np.int64), n, part_qubits)
 
 
 def simulate_alg1(n: int, gates, part_of_gate, init=0) -> np.ndarray:
-    """Gather-Execute-Scatter over a given partition (Alg. 1, Sec. III.C).
+    """Hierarchical simulation over a given partition (Sec. III.C).
 
-    Parts run in increasing part id (the ids must already be a topological
-    order of the part-graph); within a part the gates keep circuit order
-    (Sec. IV.A, last paragraph of the model).  For every setting of the
-    t = n - w qubits outside the part, the 2^w amplitudes addressed by the
-    part's qubits are gathered into ``in_sv`` (inner slot j <- the j-th
-    smallest part qubit), the part's gates -- renamed to inner slots -- run on
-    it gate by gate, and the result is scattered back.
+    Parts are applied one after another in increasing part id (the ids must
+    already be a topological order of the part-graph).  A part with qubit set
+    S (w qubits) acts only on the sub-vectors addressed by S: the state is
+    split into its 2^(n-w) sub-vectors of 2^w amplitudes, the part's gates --
+    in circuit order (Sec. IV.A) and renamed to inner slots -- are applied to
+    every sub-vector, and the sub-vectors are merged back.  Applying a gate on
+    slot b to the flattened (row, slot) matrix acts on bit b of every row at
+    once, so all outer settings are handled in one call per gate.
     """
     psi = simulate(n, [], init)
     parts = {}
     for gi, p in enumerate(part_of_gate):
         parts.setdefault(int(p), []).append(gi)
     for p in sorted(parts):
-        gate_list = [gates[i] for i in parts[p]]
-        qubits = sorted({q for g in gate_list for q in (g[1], g[2]) + tuple(g[4:5]) if q >= 0})
+        part_gates = [gates[i] for i in parts[p]]
+        qubits = sorted({q for g in part_gates for q in (g[1], g[2]) + tuple(g[4:5]) if q >= 0})
         slot = {q: j for j, q in enumerate(qubits)}
-        inner_gates = [(g[0], slot[g[1]], slot[g[2]] if g[2] >= 0 else -1, g[3])
-                       + ((slot[g[4]],) if len(g) > 4 else ()) for g in gate_list]
-        for addr in gather_addresses(n, qubits):
-            in_sv = psi[addr].copy()            # Gather
-            for g in inner_gates:               # Execute
-                apply_gate(in_sv, g)
-            psi[addr] = in_sv                   # Scatter
+        renamed = [(g[0], slot[g[1]], slot[g[2]] if g[2] >= 0 else -1, g[3])
+                   + ((slot[g[4]],) if len(g) > 4 else ()) for g in part_gates]
+        rows = split_by_part(psi, n, qubits).reshape(-1)
+        for g in renamed:
+            apply_gate(rows, g)
+        psi = merge_by_part(rows, n, qubits)
     return psi

@@ -283,7 +283,9 @@ void emit_transition(Emit& E, const StageDesc& from, const StageDesc& to, const 
   o << "    {\n";
   thread_slot(from, "wb_");
   thread_slot(to, "rb_");
-  const std::string dst = sb.empty() ? "a" : "n";
+  // split rounds read into their own temporaries (s*), never into the
+  // prefetch registers (n*) that hold the next tile's amplitudes
+  const std::string dst = sb.empty() ? "a" : "s";
   for (int h = 0; h < (1 << sb.size()); ++h) {
     o << "    __syncthreads();\n";
     std::string wc = thread_cond(from, h);
@@ -304,7 +306,7 @@ void emit_transition(Emit& E, const StageDesc& from, const StageDesc& to, const 
     o << "    }\n";
   }
   if (!sb.empty())
-    for (int j = 0; j < N; ++j) o << "    ar" << j << " = nr" << j << "; ai" << j << " = ni" << j << ";\n";
+    for (int j = 0; j < N; ++j) o << "    ar" << j << " = sr" << j << "; ai" << j << " = si" << j << ";\n";
   o << "    }\n";
 }
 
@@ -346,9 +348,13 @@ std::string specialize_part_source(const CompiledPart& cp, hs_dtype dt, const st
     << "  (void)thr; (void)active;\n";
   o << "  " << T << " ";
   for (int j = 0; j < N; ++j) o << "ar" << j << ", ai" << j << (j + 1 < N ? ", " : ";\n");
-  if (pf || nsplit) {
+  if (pf) {  // the next tile's amplitudes (persistent grid with prefetch)
     o << "  " << T << " ";
     for (int j = 0; j < N; ++j) o << "nr" << j << ", ni" << j << (j + 1 < N ? ", " : ";\n");
+  }
+  if (nsplit) {  // destinations of split re-layout rounds
+    o << "  " << T << " ";
+    for (int j = 0; j < N; ++j) o << "sr" << j << ", si" << j << (j + 1 < N ? ", " : ";\n");
   }
   // tile base: insert a zero bit at every tile qubit (ascending)
   o << "  auto base_of = [&](unsigned long long t) -> unsigned long long {\n    unsigned long long b = t;\n";
@@ -417,7 +423,9 @@ struct SpecKernel {
 
 namespace {
 std::mutex g_spec_mu;
-std::map<std::pair<int, size_t>, std::shared_ptr<SpecKernel>> g_spec;  // (device, source hash)
+// keyed by (device, full generated source): a hash alone could map two
+// different parts onto one kernel
+std::map<std::pair<int, std::string>, std::shared_ptr<SpecKernel>> g_spec;
 
 hs_status rtc_compile(const std::string& src, const std::string& name, std::vector<char>* code) {
   hiprtcProgram prog;
@@ -450,27 +458,22 @@ hs_status specialize_plan(const std::vector<CompiledPart>& parts, hs_dtype dt, i
                           std::vector<std::shared_ptr<SpecKernel>>* out) {
   const int P = (int)parts.size();
   std::vector<std::string> src(P);
-  std::vector<size_t> hash(P);
   out->assign(P, nullptr);
   std::vector<int> todo;
+  for (int i = 0; i < P; ++i) src[i] = specialize_part_source(parts[i], dt, "part_pass_spec");
   {
     std::lock_guard<std::mutex> lk(g_spec_mu);
     for (int i = 0; i < P; ++i) {
-      src[i] = specialize_part_source(parts[i], dt, "part_pass_spec");
-      hash[i] = std::hash<std::string>()(src[i]);
-      auto it = g_spec.find({device, hash[i]});
+      auto it = g_spec.find({device, src[i]});
       if (it != g_spec.end()) (*out)[i] = it->second;
       else todo.push_back(i);
     }
   }
   // dedupe identical sources among the parts still to build
-  std::map<size_t, int> first;
+  std::map<std::string, int> first;
   std::vector<int> build;
   for (int i : todo)
-    if (!first.count(hash[i])) {
-      first[hash[i]] = i;
-      build.push_back(i);
-    }
+    if (first.emplace(src[i], i).second) build.push_back(i);
   std::vector<std::vector<char>> code(P);
   std::vector<hs_status> rc(P, HS_OK);
   std::vector<std::string> err(P);
@@ -505,9 +508,9 @@ hs_status specialize_plan(const std::vector<CompiledPart>& parts, hs_dtype dt, i
       return fail(HS_E_HIP, "occupancy query failed for a specialized part");
     k->per_cu = per_cu;
     k->cus = cus;
-    g_spec[{device, hash[i]}] = k;
+    g_spec[{device, src[i]}] = k;
   }
-  for (int i : todo) (*out)[i] = g_spec[{device, hash[i]}];
+  for (int i : todo) (*out)[i] = g_spec[{device, src[i]}];
   return HS_OK;
 }
 

@@ -112,6 +112,25 @@ def test_gather_map_worked_example(golden_dir):
     assert sorted(addr.ravel().tolist()) == list(range(2 ** d["n"]))
 
 
+@pytest.mark.parametrize("n,part", [(4, [0, 1]), (5, [4, 1]), (6, [0, 2, 5]), (3, [0, 1, 2]),
+                                    (7, [6])])
+def test_split_by_part_explicit_indices(n, part):
+    """The sub-vector view against explicit bit arithmetic: row r, slot j
+    holds the amplitude whose index has bit b of r on the b-th smallest outer
+    qubit and bit b of j on the b-th smallest part qubit; merging undoes it."""
+    rng = np.random.default_rng(n)
+    psi = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    mat = sv.split_by_part(psi, n, part)
+    qs = sorted(part)
+    outer = [q for q in range(n) if q not in qs]
+    for r in range(1 << len(outer)):
+        for j in range(1 << len(qs)):
+            i = sum(((r >> b) & 1) << q for b, q in enumerate(outer))
+            i |= sum(((j >> b) & 1) << q for b, q in enumerate(qs))
+            assert mat[r, j] == psi[i]
+    np.testing.assert_array_equal(sv.merge_by_part(mat, n, part), psi)
+
+
 # --- brute force ------------------------------------------------------------
 
 def _embed(n, qubits, small):

@@ -155,3 +155,26 @@ def test_spec_kernels_with_dense_two_qubit_ops(dtype, tmp_path):
     finally:
         hisv.hs_tune("spec_fuse2", 0)
     np.testing.assert_allclose(got, sv.simulate(n, gates, psi0), atol=TOL[dtype], rtol=0)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_spec_kernels_prefetch_with_split_relayouts(dtype, tmp_path):
+    """Persistent grid with next-tile prefetch on the widest tiles, whose LDS
+    re-layouts run in two rounds: the rounds must not land in the registers
+    that hold the prefetched tile."""
+    n = 17
+    gates = wl.random_circuit(n, 120, sv.ONE_QUBIT + sv.TWO_QUBIT, seed=43)
+    hisv.hs_tune("spec_grid", 1)
+    hisv.hs_tune("spec_prefetch", 1)
+    try:
+        plan = hisv.Plan.partition_multilevel(hisv.Circuit(n, gates), strategy="dfs", dtype=dtype,
+                                              seed=2, trials=8)
+        srcs = [plan.part_source(i, dtype) for i in range(plan.num_parts)]
+        # prefetch registers and split-round registers both present
+        assert any(" nr0" in s and " sr0" in s for s in srcs)
+        psi0 = random_state(n, 6)
+        got = run_on_host(plan, n, dtype, psi0, tmp_path, persistent=True)
+    finally:
+        hisv.hs_tune("spec_grid", 0)
+        hisv.hs_tune("spec_prefetch", 0)
+    np.testing.assert_allclose(got, sv.simulate(n, gates, psi0), atol=TOL[dtype], rtol=0)
