@@ -344,36 +344,56 @@ hs_status hs_copy_probe(const void* src, void* dst, size_t bytes, void* hip_stre
 
 typedef struct hs_server_* hs_server;
 
-/* A server owns a pool of `num_streams` HIP streams on the current device
- * and admits requests while the device bytes of resident states (plus their
- * plans) stay within `budget_bytes` (0 = free device memory at creation
- * minus a 4 GiB reserve).  A worker thread admits, launches and retires
- * requests; several requests are in flight on the device at once. */
+/* A server owns a pool of `num_streams` HIP streams on the current device,
+ * four host threads that prepare requests (partition, compile, upload the
+ * kernel descriptors) and a worker thread that admits, launches and retires
+ * them.  Requests are admitted while the device bytes of resident states
+ * (plus their descriptors) stay within `budget_bytes` (0 = free device
+ * memory at creation minus a 4 GiB reserve); several requests are in flight
+ * on the device at once.  A prepared request's descriptors (a few KiB per
+ * part) are on the device before it is admitted. */
 hs_status hs_server_create(size_t budget_bytes, int num_streams, hs_server* out);
 
-/* Queue a circuit (copied) to be partitioned with limit k by `strategy`
- * (DFS and GREEDY with 16 trials), simulated from |init_basis> in `dtype`,
- * and kept resident until released.  Returns a ticket.  HS_E_ADMISSION if
- * the state can never fit the budget.  Non-blocking. */
+/* The server clock (seconds, monotonic) against which arrival times and
+ * latencies are measured. */
+hs_status hs_server_clock(hs_server sv, double* seconds);
+
+/* Queue a circuit (copied and validated here) to be partitioned with limit
+ * k by `strategy` (DFS and GREEDY with 16 trials), simulated from
+ * |init_basis> in `dtype`, and kept resident until released.  `arrival_s`
+ * is the request's arrival time on the server clock, where its latency
+ * starts (negative: the time of this call; HS_E_ARG if it lies after the
+ * call).  Returns a ticket.  HS_E_ADMISSION if the state alone can never fit
+ * the budget (a request whose state and descriptors together exceed it fails
+ * later with the same code, reported by hs_server_wait).  Does not wait for
+ * partitioning, compilation or the device. */
 hs_status hs_server_submit(hs_server sv, int n, const hs_gate* gates, size_t count,
                            hs_dtype dtype, uint64_t init_basis, int k,
-                           hs_strategy strategy, uint64_t* ticket);
+                           hs_strategy strategy, double arrival_s, uint64_t* ticket);
 
 /* Block until the ticket's result is ready (timeout_ms < 0: no limit).
- * HS_E_STATE on timeout. */
+ * HS_E_STATE on timeout; the request's own error if it failed. */
 hs_status hs_server_wait(hs_server sv, uint64_t ticket, int64_t timeout_ms);
 
-/* Non-blocking: *done = 1 if the ticket's result is ready. */
+/* Non-blocking: *done = 1 if the ticket's result is ready (or it failed). */
 hs_status hs_server_poll(hs_server sv, uint64_t ticket, int* done);
 
-/* Read amplitudes of a finished request (as hs_read_amplitudes). */
+/* Read amplitudes of a finished request (as hs_read_amplitudes), staged
+ * through a buffer the server allocated at creation. */
 hs_status hs_server_read(hs_server sv, uint64_t ticket, uint64_t first, uint64_t count,
                          double* out);
 
-/* Latency (submit to completion, seconds) of a finished request. */
+/* Latency of a finished request: arrival to observed completion, seconds. */
 hs_status hs_server_latency(hs_server sv, uint64_t ticket, double* seconds);
 
-/* Free a finished request's device memory (its bytes return to the budget). */
+/* Where a finished request's latency went, seconds, summing to it:
+ * out4[0] arrival -> preparation start (host queue), out4[1] preparation
+ * (partition, compile, descriptor upload), out4[2] prepared -> launched
+ * (waiting for admission), out4[3] launched -> completion observed (device). */
+hs_status hs_server_timing(hs_server sv, uint64_t ticket, double* out4);
+
+/* Free a finished request's device memory (its bytes return to the budget).
+ * Stream-ordered frees: no device-wide wait. */
 hs_status hs_server_release(hs_server sv, uint64_t ticket);
 
 /* Counters: requests completed, peak admitted bytes, current admitted bytes,
@@ -381,7 +401,9 @@ hs_status hs_server_release(hs_server sv, uint64_t ticket);
 hs_status hs_server_stats(hs_server sv, uint64_t* completed, uint64_t* peak_bytes,
                           uint64_t* cur_bytes, int* peak_inflight);
 
-/* Wait for all submitted requests, stop the worker, free everything. */
+/* Wait for all submitted requests, stop the threads, free everything.
+ * Requests still waiting for bytes that no running request will free fail
+ * with HS_E_ADMISSION. */
 hs_status hs_server_destroy(hs_server sv);
 
 #ifdef __cplusplus

@@ -186,6 +186,10 @@ inline size_t amp_bytes(hs_dtype d) { return d == HS_C64 ? 8 : 16; }
 hs_status dev_set_basis(State* s, uint64_t x);
 hs_status dev_gate_pass(State* s, const Gate& g);
 hs_status dev_run_part(State* s, Plan* p, int part);
+// Upload the plan's interpreter descriptors for `dtype` on `device` with the
+// stream-ordered allocator on `stream` (waits for the copies); the plan later
+// frees them with hipFreeAsync on that stream, never with a device-wide wait.
+hs_status dev_plan_upload_async(Plan* p, hs_dtype dtype, int device, void* stream);
 hs_status dev_run_fused(State* s, Plan* p, int part);
 hs_status plan_compile_fused(Plan* p);
 // relative cost (one HBM sweep = 1) of a part on each path, for AUTO

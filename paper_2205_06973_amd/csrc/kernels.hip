@@ -826,6 +826,10 @@ hs_status dev_gate_pass(State* s, const Gate& g) {
 // ---- uploaded plan ----------------------------------------------------------
 struct DevicePlan {
   int device = 0;
+  // descriptors from the stream-ordered allocator (serving): freed with
+  // hipFreeAsync on free_stream, so a teardown never waits for the device
+  bool async_alloc = false;
+  void* free_stream = nullptr;
   IPart* parts = nullptr;
   IStage* stages = nullptr;
   void* ops = nullptr;
@@ -846,9 +850,11 @@ struct DevicePlan {
 void device_plan_free(DevicePlan* d) {
   if (!d) return;
   (void)hipSetDevice(d->device);
-  if (d->parts) (void)hipFree(d->parts);
-  if (d->stages) (void)hipFree(d->stages);
-  if (d->ops) (void)hipFree(d->ops);
+  for (void* ptr : {(void*)d->parts, (void*)d->stages, d->ops}) {
+    if (!ptr) continue;
+    if (d->async_alloc) (void)hipFreeAsync(ptr, (hipStream_t)d->free_stream);
+    else (void)hipFree(ptr);
+  }
   if (d->fparts) (void)hipFree(d->fparts);
   if (d->fmat) (void)hipFree(d->fmat);
   delete d;
@@ -916,8 +922,11 @@ static IoOffsets interp_io(const StageDesc& e, const PartDesc& d) {
   return o;
 }
 
+// Upload a plan's interpreter descriptors.  stream = NULL: hipMalloc and
+// blocking copies; otherwise the stream-ordered allocator and asynchronous
+// copies on `stream`, waited for before returning.
 template <typename T>
-static hs_status upload_plan(Plan* p, int dtype, int dev, DevicePlan** out) {
+static hs_status upload_plan(Plan* p, int dtype, int dev, DevicePlan** out, hipStream_t stream) {
   std::vector<PartDesc> hparts;
   std::vector<IPart> parts;
   std::vector<IStage> stages;
@@ -968,12 +977,29 @@ static hs_status upload_plan(Plan* p, int dtype, int dev, DevicePlan** out) {
     dp->xcd.push_back(x);
   }
   if (ops.empty()) ops.push_back(OpDesc<T>{});
-  HIP_TRY(hipMalloc(&dp->parts, parts.size() * sizeof(IPart)));
-  HIP_TRY(hipMalloc(&dp->stages, stages.size() * sizeof(IStage)));
-  HIP_TRY(hipMalloc(&dp->ops, ops.size() * sizeof(OpDesc<T>)));
-  HIP_TRY(hipMemcpy(dp->parts, parts.data(), parts.size() * sizeof(IPart), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(dp->stages, stages.data(), stages.size() * sizeof(IStage), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(dp->ops, ops.data(), ops.size() * sizeof(OpDesc<T>), hipMemcpyHostToDevice));
+  if (parts.empty()) parts.push_back(IPart{});
+  if (stages.empty()) stages.push_back(IStage{});
+  if (stream) {
+    dp->async_alloc = true;
+    dp->free_stream = stream;
+    HIP_TRY(hipMallocAsync((void**)&dp->parts, parts.size() * sizeof(IPart), stream));
+    HIP_TRY(hipMallocAsync((void**)&dp->stages, stages.size() * sizeof(IStage), stream));
+    HIP_TRY(hipMallocAsync(&dp->ops, ops.size() * sizeof(OpDesc<T>), stream));
+    HIP_TRY(hipMemcpyAsync(dp->parts, parts.data(), parts.size() * sizeof(IPart), hipMemcpyHostToDevice,
+                           stream));
+    HIP_TRY(hipMemcpyAsync(dp->stages, stages.data(), stages.size() * sizeof(IStage),
+                           hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(dp->ops, ops.data(), ops.size() * sizeof(OpDesc<T>), hipMemcpyHostToDevice,
+                           stream));
+    HIP_TRY(hipStreamSynchronize(stream));  // the host vectors die on return
+  } else {
+    HIP_TRY(hipMalloc(&dp->parts, parts.size() * sizeof(IPart)));
+    HIP_TRY(hipMalloc(&dp->stages, stages.size() * sizeof(IStage)));
+    HIP_TRY(hipMalloc(&dp->ops, ops.size() * sizeof(OpDesc<T>)));
+    HIP_TRY(hipMemcpy(dp->parts, parts.data(), parts.size() * sizeof(IPart), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(dp->stages, stages.data(), stages.size() * sizeof(IStage), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(dp->ops, ops.data(), ops.size() * sizeof(OpDesc<T>), hipMemcpyHostToDevice));
+  }
   dp->h_parts = hparts;
   *out = dp.release();
   return HS_OK;
@@ -1015,11 +1041,27 @@ static hs_status device_plan(State* s, Plan* p, DevicePlan** out) {
     return HS_OK;
   }
   DevicePlan* dp = nullptr;
-  hs_status rc = dt == HS_C64 ? upload_plan<float>(p, dt, s->device, &dp)
-                              : upload_plan<double>(p, dt, s->device, &dp);
+  hs_status rc = dt == HS_C64 ? upload_plan<float>(p, dt, s->device, &dp, nullptr)
+                              : upload_plan<double>(p, dt, s->device, &dp, nullptr);
   if (rc) return rc;
   p->dev[dt][s->device] = dp;
   *out = dp;
+  return HS_OK;
+}
+
+hs_status dev_plan_upload_async(Plan* p, hs_dtype dtype, int device, void* stream) {
+  HIP_TRY(hipSetDevice(device));
+  std::lock_guard<std::mutex> lk(p->mu);
+  const int dt = (int)dtype;
+  if (p->dev[dt].count(device)) return HS_OK;
+  DevicePlan* dp = nullptr;
+  hs_status rc = dt == HS_C64 ? upload_plan<float>(p, dt, device, &dp, (hipStream_t)stream)
+                              : upload_plan<double>(p, dt, device, &dp, (hipStream_t)stream);
+  if (rc) {
+    device_plan_free(dp);
+    return rc;
+  }
+  p->dev[dt][device] = dp;
   return HS_OK;
 }
 

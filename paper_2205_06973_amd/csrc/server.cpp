@@ -1,16 +1,29 @@
 // server.cpp -- continuous batching of many circuits on one GPU.
 //
-// Requests are partitioned and compiled on the submitting thread.  A worker
-// thread then admits them in arrival order while the bytes of resident
-// states (plus their plans) stay within the budget, allocates each state
-// with the stream-ordered allocator on the least loaded stream of a pool,
-// enqueues the set-basis kernel and one part-pass per part, and records an
-// event.  It keeps polling those events: a finished request frees its slot
-// on the stream, keeps its state resident until released, and has its
-// latency (submit to observed completion) recorded.  Requests admitted while
-// others are running overlap with them on the device.
+// A request's life:
+//   submit    the caller's thread copies and validates the gate list, checks
+//             that the state could ever fit the byte budget, and queues the
+//             request; nothing else happens on that thread, so an arrival
+//             loop keeps its schedule.  The latency clock starts at the
+//             request's arrival time (given by the caller on the server
+//             clock, or the time of the call).
+//   prepare   one of a pool of host threads partitions the circuit, compiles
+//             the interpreter descriptors and uploads them with the
+//             stream-ordered allocator on its own stream -- all without the
+//             server lock.
+//   admit     the worker thread admits prepared requests in ticket order
+//             while the bytes of resident states (plus their descriptors) stay
+//             within the budget, allocates the state on the stream of a pool
+//             with the least outstanding work, enqueues set-basis and one
+//             part-pass per part, and records an event.  Requests admitted
+//             while others run overlap with them on the device.
+//   retire    the worker polls the events; a finished request keeps its state
+//             resident until it is read and released.
+//   release   state and descriptors go back with hipFreeAsync (no device-wide
+//             wait), outside the server lock.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -24,24 +37,32 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
-enum ReqStatus { RQ_QUEUED, RQ_RUNNING, RQ_DONE, RQ_FAILED, RQ_RELEASED };
+double now_s() { return std::chrono::duration<double>(Clock::now().time_since_epoch()).count(); }
+
+enum ReqStatus { RQ_QUEUED, RQ_PREPARING, RQ_READY, RQ_RUNNING, RQ_DONE, RQ_FAILED, RQ_RELEASED };
 
 struct Request {
   uint64_t ticket = 0;
-  int n = 0;
+  int n = 0, k = 0;
   hs_dtype dtype = HS_C64;
+  hs_strategy strategy = HS_PART_GREEDY;
   uint64_t init = 0;
+  std::vector<Gate> gates;
   std::unique_ptr<Plan> plan;
   size_t bytes = 0;  // state + plan descriptors
   State st;
   int stream = -1;
-  double work = 0;  // estimated device work: part-passes x state bytes
+  double work = 0;   // estimated device work: part-passes x state bytes
   hipEvent_t done = nullptr;
-  Clock::time_point t_submit, t_done;
+  // server clock (seconds): arrival, preparation start and end, launch, done
+  double t_arrival = 0, t_prep0 = 0, t_prep1 = 0, t_launch = 0, t_done = 0;
   ReqStatus status = RQ_QUEUED;
   hs_status err = HS_OK;
   std::string err_msg;
 };
+
+constexpr int kPrepThreads = 4;
+constexpr size_t kReadScratch = size_t(64) << 20;  // covers dev_read's largest chunk
 
 }  // namespace
 
@@ -54,14 +75,19 @@ struct hs_server_ {
   uint64_t next_ticket = 1;
   std::vector<hipStream_t> streams;
   std::vector<double> load;  // estimated outstanding work per stream
+  std::vector<hipStream_t> prep_streams;
   hipStream_t read_stream = nullptr;
+  void* read_scratch = nullptr;  // persistent staging of hs_server_read
+  std::mutex read_mu;
   std::mutex mu;
   std::condition_variable cv;
-  std::deque<Request*> queue;
+  std::deque<Request*> prep_queue;
+  std::map<uint64_t, Request*> ready;  // prepared, waiting for admission (ticket order)
   std::vector<Request*> running;
   std::map<uint64_t, Request*> reqs;
   bool stop = false;
   std::thread worker;
+  std::vector<std::thread> preppers;
 };
 
 namespace {
@@ -74,9 +100,66 @@ size_t plan_bytes(const Plan& p, hs_dtype dt) {
   return b;
 }
 
-// Launch everything for an admitted request (called with the lock held) on
-// the stream with the least outstanding work, so that small requests do not
-// queue behind large ones when another stream is nearly idle.
+// Partition, compile and upload one request (no server lock held).
+hs_status prepare(hs_server_* sv, Request* r, hipStream_t stream) {
+  const std::vector<Gate>& gs = r->gates;
+  std::vector<int32_t> part;
+  const Dag dag = build_dag(gs);
+  const uint64_t seed = 0x5eed + gs.size();
+  switch (r->strategy) {
+    case HS_PART_NAT: partition_nat(gs, r->k, &part); break;
+    case HS_PART_DFS: partition_dfs(gs, dag, r->k, seed, 16, &part); break;
+    case HS_PART_DAGP: partition_dagp(gs, dag, r->n, r->k, seed, &part); break;
+    case HS_PART_GREEDY: partition_greedy(gs, dag, r->k, seed, 16, &part); break;
+    default: return fail(HS_E_ARG, "unknown strategy %d", (int)r->strategy);
+  }
+  auto plan = std::make_unique<Plan>();
+  if (hs_status rc = plan_build(r->n, gs, r->k, part, plan.get())) return rc;
+  if (hs_status rc = plan_compile(plan.get(), r->dtype)) return rc;
+  r->bytes = (size_t(1) << r->n) * amp_bytes(r->dtype) + plan_bytes(*plan, r->dtype);
+  if (r->bytes > sv->budget)
+    return fail(HS_E_ADMISSION, "request needs %zu bytes, budget is %zu", r->bytes, sv->budget);
+  if (hs_status rc = dev_plan_upload_async(plan.get(), r->dtype, sv->device, stream)) return rc;
+  r->work = (double)plan->parts.size() * (double)((size_t(1) << r->n) * amp_bytes(r->dtype));
+  r->plan = std::move(plan);
+  r->gates.clear();
+  r->gates.shrink_to_fit();
+  return HS_OK;
+}
+
+void prep_main(hs_server_* sv, int idx) {
+  (void)hipSetDevice(sv->device);
+  hipStream_t stream = sv->prep_streams[idx];
+  std::unique_lock<std::mutex> lk(sv->mu);
+  for (;;) {
+    sv->cv.wait(lk, [&] { return sv->stop || !sv->prep_queue.empty(); });
+    if (sv->prep_queue.empty()) break;  // stopping and nothing left
+    Request* r = sv->prep_queue.front();
+    sv->prep_queue.pop_front();
+    r->status = RQ_PREPARING;
+    lk.unlock();
+    r->t_prep0 = now_s();
+    const hs_status rc = prepare(sv, r, stream);
+    const std::string msg = rc ? hs_last_error() : "";
+    r->t_prep1 = now_s();
+    lk.lock();
+    if (rc) {
+      r->status = RQ_FAILED;
+      r->err = rc;
+      r->err_msg = msg;
+      r->t_done = r->t_prep1;
+    } else {
+      r->status = RQ_READY;
+      sv->ready.emplace(r->ticket, r);
+    }
+    sv->cv.notify_all();
+  }
+}
+
+// Launch everything for an admitted request (called with the lock held;
+// nothing here waits on the device) on the stream with the least
+// outstanding work, so that small requests do not queue behind large ones
+// when another stream is nearly idle.
 hs_status launch(hs_server_* sv, Request* r) {
   int best = 0;
   for (int i = 1; i < (int)sv->streams.size(); ++i)
@@ -92,6 +175,7 @@ hs_status launch(hs_server_* sv, Request* r) {
   hipError_t e = hipMallocAsync(&r->st.ptr, r->st.bytes, s);
   if (e != hipSuccess) {
     (void)hipGetLastError();
+    r->st.ptr = nullptr;
     return fail(HS_E_NOMEM, "hipMallocAsync(%zu): %s", r->st.bytes, hipGetErrorString(e));
   }
   if (hs_status rc = dev_set_basis(&r->st, r->init)) return rc;
@@ -113,7 +197,7 @@ void worker_main(hs_server_* sv) {
     for (size_t i = 0; i < sv->running.size();) {
       Request* r = sv->running[i];
       if (hipEventQuery(r->done) == hipSuccess) {
-        r->t_done = Clock::now();
+        r->t_done = now_s();
         r->status = RQ_DONE;
         sv->load[r->stream] -= r->work;
         sv->completed++;
@@ -124,13 +208,14 @@ void worker_main(hs_server_* sv) {
         ++i;
       }
     }
-    // admit in arrival order while the budget allows
-    while (!sv->queue.empty()) {
-      Request* r = sv->queue.front();
+    // admit prepared requests in ticket order while the budget allows
+    while (!sv->ready.empty()) {
+      Request* r = sv->ready.begin()->second;
       if (sv->cur_bytes + r->bytes > sv->budget) break;
-      sv->queue.pop_front();
+      sv->ready.erase(sv->ready.begin());
       sv->cur_bytes += r->bytes;
       sv->peak_bytes = std::max(sv->peak_bytes, sv->cur_bytes);
+      r->t_launch = now_s();
       hs_status rc = launch(sv, r);
       if (rc != HS_OK) {
         r->status = RQ_FAILED;
@@ -139,7 +224,7 @@ void worker_main(hs_server_* sv) {
         if (r->st.ptr) (void)hipFreeAsync(r->st.ptr, (hipStream_t)r->st.stream);
         r->st.ptr = nullptr;
         sv->cur_bytes -= r->bytes;
-        r->t_done = Clock::now();
+        r->t_done = now_s();
       } else {
         r->status = RQ_RUNNING;
         sv->running.push_back(r);
@@ -148,7 +233,23 @@ void worker_main(hs_server_* sv) {
       progress = true;
     }
     if (progress) sv->cv.notify_all();
-    if (sv->stop && sv->queue.empty() && sv->running.empty()) break;
+    if (sv->stop && sv->prep_queue.empty() && sv->running.empty()) {
+      bool preparing = false;
+      for (auto& kv : sv->reqs) preparing |= kv.second->status == RQ_PREPARING;
+      if (!preparing) {
+        // nothing runs and nothing more will be released: whatever is still
+        // waiting did not fit above and never will
+        for (auto& kv : sv->ready) {
+          Request* r = kv.second;
+          r->status = RQ_FAILED;
+          r->err = HS_E_ADMISSION;
+          r->err_msg = "server stopped before the request could be admitted";
+          r->t_done = now_s();
+        }
+        sv->ready.clear();
+        break;
+      }
+    }
     if (!progress)
       sv->cv.wait_for(lk, std::chrono::microseconds(sv->running.empty() ? 2000 : 20));
   }
@@ -158,6 +259,15 @@ void worker_main(hs_server_* sv) {
 Request* find(hs_server_* sv, uint64_t t) {
   auto it = sv->reqs.find(t);
   return it == sv->reqs.end() ? nullptr : it->second;
+}
+
+// Free a request's device memory and handles; no lock held.
+void drop_request_memory(hs_server_* sv, std::unique_ptr<Plan> plan, void* state,
+                         hipStream_t stream, hipEvent_t ev) {
+  (void)hipSetDevice(sv->device);
+  if (state) (void)hipFreeAsync(state, stream);
+  plan.reset();  // descriptors: hipFreeAsync on the preparing stream
+  if (ev) (void)hipEventDestroy(ev);
 }
 
 }  // namespace
@@ -173,60 +283,87 @@ hs_status hs_server_create(size_t budget_bytes, int num_streams, hs_server* out)
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return fail(HS_E_HIP, "hipMemGetInfo failed");
   const size_t reserve = size_t(4) << 30;
   sv->budget = budget_bytes ? budget_bytes : (free_b > reserve ? free_b - reserve : free_b / 2);
+  auto new_stream = [](hipStream_t* s) {
+    return hipStreamCreateWithFlags(s, hipStreamNonBlocking) == hipSuccess;
+  };
+  auto cleanup = [&]() {
+    for (hipStream_t s : sv->streams) (void)hipStreamDestroy(s);
+    for (hipStream_t s : sv->prep_streams) (void)hipStreamDestroy(s);
+    if (sv->read_stream) (void)hipStreamDestroy(sv->read_stream);
+    if (sv->read_scratch) (void)hipFree(sv->read_scratch);
+  };
   for (int i = 0; i < num_streams; ++i) {
     hipStream_t s;
-    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
+    if (!new_stream(&s)) {
+      cleanup();
       return fail(HS_E_HIP, "hipStreamCreate failed");
+    }
     sv->streams.push_back(s);
     sv->load.push_back(0);
   }
-  if (hipStreamCreateWithFlags(&sv->read_stream, hipStreamNonBlocking) != hipSuccess)
+  for (int i = 0; i < kPrepThreads; ++i) {
+    hipStream_t s;
+    if (!new_stream(&s)) {
+      cleanup();
+      return fail(HS_E_HIP, "hipStreamCreate failed");
+    }
+    sv->prep_streams.push_back(s);
+  }
+  if (!new_stream(&sv->read_stream)) {
+    cleanup();
     return fail(HS_E_HIP, "hipStreamCreate failed");
+  }
+  if (hipMalloc(&sv->read_scratch, kReadScratch) != hipSuccess) {
+    (void)hipGetLastError();
+    sv->read_scratch = nullptr;
+    cleanup();
+    return fail(HS_E_NOMEM, "read staging buffer of %zu bytes", kReadScratch);
+  }
   hs_server_* raw = sv.release();
   raw->worker = std::thread(worker_main, raw);
+  for (int i = 0; i < kPrepThreads; ++i) raw->preppers.emplace_back(prep_main, raw, i);
   *out = raw;
   return HS_OK;
 }
 
+hs_status hs_server_clock(hs_server sv, double* seconds) {
+  if (!sv || !seconds) return fail(HS_E_ARG, "null argument");
+  *seconds = now_s();
+  return HS_OK;
+}
+
 hs_status hs_server_submit(hs_server sv, int n, const hs_gate* gates, size_t count, hs_dtype dtype,
-                           uint64_t init_basis, int k, hs_strategy strategy, uint64_t* ticket) {
+                           uint64_t init_basis, int k, hs_strategy strategy, double arrival_s,
+                           uint64_t* ticket) {
+  const double t_call = now_s();
   if (!sv || !ticket || (!gates && count)) return fail(HS_E_ARG, "null argument");
   if (n < 1 || n > 40) return fail(HS_E_ARG, "n = %d outside [1, 40]", n);
   if (dtype != HS_C64 && dtype != HS_C128) return fail(HS_E_ARG, "bad dtype");
   if (init_basis >= (uint64_t(1) << n)) return fail(HS_E_ARG, "basis index outside the state");
   if (k < 1) return fail(HS_E_ARG, "k = %d < 1", k);
+  if (strategy < HS_PART_NAT || strategy > HS_PART_GREEDY)
+    return fail(HS_E_ARG, "unknown strategy %d", (int)strategy);
+  if (arrival_s > t_call) return fail(HS_E_ARG, "arrival time lies in the future");
   auto r = std::make_unique<Request>();
   r->n = n;
+  r->k = k;
   r->dtype = dtype;
+  r->strategy = strategy;
   r->init = init_basis;
-  std::vector<Gate> gs;
-  gs.reserve(count);
+  r->t_arrival = arrival_s >= 0 ? arrival_s : t_call;
+  r->gates.reserve(count);
   for (size_t i = 0; i < count; ++i)
-    if (hs_status rc = expand_gate(n, gates[i], &gs)) return rc;
-  for (const Gate& g : gs)
+    if (hs_status rc = expand_gate(n, gates[i], &r->gates)) return rc;
+  for (const Gate& g : r->gates)
     if (g.arity() > k) return fail(HS_E_ARITY_GT_K, "gate wider than k = %d", k);
-  std::vector<int32_t> part;
-  const Dag dag = build_dag(gs);
-  switch (strategy) {
-    case HS_PART_NAT: partition_nat(gs, k, &part); break;
-    case HS_PART_DFS: partition_dfs(gs, dag, k, 0x5eed + count, 16, &part); break;
-    case HS_PART_DAGP: partition_dagp(gs, dag, n, k, 0x5eed + count, &part); break;
-    case HS_PART_GREEDY: partition_greedy(gs, dag, k, 0x5eed + count, 16, &part); break;
-    default: return fail(HS_E_ARG, "unknown strategy %d", (int)strategy);
-  }
-  r->plan = std::make_unique<Plan>();
-  if (hs_status rc = plan_build(n, gs, k, part, r->plan.get())) return rc;
-  if (hs_status rc = plan_compile(r->plan.get(), dtype)) return rc;
-  r->bytes = (size_t(1) << n) * amp_bytes(dtype) + plan_bytes(*r->plan, dtype);
-  r->work = (double)r->plan->parts.size() * (double)((size_t(1) << n) * amp_bytes(dtype));
-  if (r->bytes > sv->budget)
-    return fail(HS_E_ADMISSION, "request needs %zu bytes, budget is %zu", r->bytes, sv->budget);
-  r->t_submit = Clock::now();
+  const size_t state_bytes = (size_t(1) << n) * amp_bytes(dtype);
+  if (state_bytes > sv->budget)
+    return fail(HS_E_ADMISSION, "state needs %zu bytes, budget is %zu", state_bytes, sv->budget);
   std::lock_guard<std::mutex> lk(sv->mu);
   r->ticket = sv->next_ticket++;
   *ticket = r->ticket;
   sv->reqs[r->ticket] = r.get();
-  sv->queue.push_back(r.release());
+  sv->prep_queue.push_back(r.release());
   sv->cv.notify_all();
   return HS_OK;
 }
@@ -265,14 +402,15 @@ hs_status hs_server_read(hs_server sv, uint64_t ticket, uint64_t first, uint64_t
     if (first > N || count > N - first) return fail(HS_E_ARG, "range outside the state");
     view = r->st;
   }
-  // read on a stream of its own, ordered after the request's kernels
+  if (!count) return HS_OK;
+  // read on a stream of its own (the request's kernels have finished),
+  // staged through the server's persistent buffer
+  std::lock_guard<std::mutex> rl(sv->read_mu);
   view.stream = sv->read_stream;
   view.owned = false;
-  view.scratch = nullptr;
-  view.scratch_bytes = 0;
-  hs_status rc = count ? dev_read(&view, first, count, out, false) : HS_OK;
-  if (view.scratch) (void)hipFree(view.scratch);
-  return rc;
+  view.scratch = sv->read_scratch;
+  view.scratch_bytes = kReadScratch;
+  return dev_read(&view, first, count, out, false);
 }
 
 hs_status hs_server_latency(hs_server sv, uint64_t ticket, double* seconds) {
@@ -281,29 +419,50 @@ hs_status hs_server_latency(hs_server sv, uint64_t ticket, double* seconds) {
   Request* r = find(sv, ticket);
   if (!r) return fail(HS_E_ARG, "unknown ticket");
   if (r->status != RQ_DONE && r->status != RQ_RELEASED) return fail(HS_E_STATE, "ticket is not finished");
-  *seconds = std::chrono::duration<double>(r->t_done - r->t_submit).count();
+  *seconds = r->t_done - r->t_arrival;
+  return HS_OK;
+}
+
+hs_status hs_server_timing(hs_server sv, uint64_t ticket, double* out4) {
+  if (!sv || !out4) return fail(HS_E_ARG, "null argument");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  Request* r = find(sv, ticket);
+  if (!r) return fail(HS_E_ARG, "unknown ticket");
+  if (r->status != RQ_DONE && r->status != RQ_RELEASED) return fail(HS_E_STATE, "ticket is not finished");
+  out4[0] = r->t_prep0 - r->t_arrival;
+  out4[1] = r->t_prep1 - r->t_prep0;
+  out4[2] = r->t_launch - r->t_prep1;
+  out4[3] = r->t_done - r->t_launch;
   return HS_OK;
 }
 
 hs_status hs_server_release(hs_server sv, uint64_t ticket) {
   if (!sv) return fail(HS_E_ARG, "null server");
-  std::lock_guard<std::mutex> lk(sv->mu);
-  Request* r = find(sv, ticket);
-  if (!r) return fail(HS_E_ARG, "unknown ticket");
-  if (r->status == RQ_RELEASED) return HS_OK;
-  if (r->status != RQ_DONE && r->status != RQ_FAILED) return fail(HS_E_STATE, "ticket is not finished");
-  if (r->status == RQ_DONE) {
-    // the read stream may still hold copies of this state
-    (void)hipStreamSynchronize(sv->read_stream);
-    (void)hipFreeAsync(r->st.ptr, (hipStream_t)r->st.stream);
-    r->st.ptr = nullptr;
-    sv->cur_bytes -= r->bytes;
+  std::unique_ptr<Plan> plan;
+  void* state = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    Request* r = find(sv, ticket);
+    if (!r) return fail(HS_E_ARG, "unknown ticket");
+    if (r->status == RQ_RELEASED) return HS_OK;
+    if (r->status != RQ_DONE && r->status != RQ_FAILED) return fail(HS_E_STATE, "ticket is not finished");
+    if (r->status == RQ_DONE) {
+      state = r->st.ptr;
+      stream = (hipStream_t)r->st.stream;
+      r->st.ptr = nullptr;
+      sv->cur_bytes -= r->bytes;
+    }
+    ev = r->done;
+    r->done = nullptr;
+    plan = std::move(r->plan);
+    r->status = RQ_RELEASED;
+    sv->cv.notify_all();
   }
-  if (r->done) (void)hipEventDestroy(r->done);
-  r->done = nullptr;
-  r->plan.reset();
-  r->status = RQ_RELEASED;
-  sv->cv.notify_all();
+  // a finished request's kernels are complete: the frees are stream-ordered
+  // and wait for nothing on the device
+  drop_request_memory(sv, std::move(plan), state, stream, ev);
   return HS_OK;
 }
 
@@ -325,20 +484,27 @@ hs_status hs_server_destroy(hs_server sv) {
     sv->stop = true;
     sv->cv.notify_all();
   }
+  for (auto& t : sv->preppers)
+    if (t.joinable()) t.join();
   if (sv->worker.joinable()) sv->worker.join();
   (void)hipSetDevice(sv->device);
   for (auto& kv : sv->reqs) {
     Request* r = kv.second;
     if (r->st.ptr) (void)hipFreeAsync(r->st.ptr, (hipStream_t)r->st.stream);
     if (r->done) (void)hipEventDestroy(r->done);
-    delete r;
+    delete r;  // plan descriptors: hipFreeAsync on the preparing stream
   }
   for (hipStream_t s : sv->streams) {
     (void)hipStreamSynchronize(s);
     (void)hipStreamDestroy(s);
   }
+  for (hipStream_t s : sv->prep_streams) {
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+  }
   (void)hipStreamSynchronize(sv->read_stream);
   (void)hipStreamDestroy(sv->read_stream);
+  if (sv->read_scratch) (void)hipFree(sv->read_scratch);
   delete sv;
   return HS_OK;
 }

@@ -83,12 +83,14 @@ _SIGS = {
     "hs_sync": [_vp],
     "hs_copy_probe": [_vp, _vp, C.c_size_t, _vp],
     "hs_server_create": [C.c_size_t, C.c_int, C.POINTER(_vp)],
+    "hs_server_clock": [_vp, _dp],
     "hs_server_submit": [_vp, C.c_int, C.POINTER(hs_gate), C.c_size_t, C.c_int, _u64, C.c_int,
-                         C.c_int, C.POINTER(_u64)],
+                         C.c_int, C.c_double, C.POINTER(_u64)],
     "hs_server_wait": [_vp, _u64, C.c_int64],
     "hs_server_poll": [_vp, _u64, C.POINTER(C.c_int)],
     "hs_server_read": [_vp, _u64, _u64, _u64, _dp],
     "hs_server_latency": [_vp, _u64, _dp],
+    "hs_server_timing": [_vp, _u64, _dp],
     "hs_server_release": [_vp, _u64],
     "hs_server_stats": [_vp, C.POINTER(_u64), C.POINTER(_u64), C.POINTER(_u64),
                         C.POINTER(C.c_int)],
@@ -416,12 +418,18 @@ class Server:
         _call("hs_server_create", int(budget_bytes), int(num_streams), C.byref(h))
         self.handle = h
 
+    def clock(self) -> float:
+        """The server clock (seconds) that arrival times are given on."""
+        v = C.c_double()
+        _call("hs_server_clock", self.handle, C.byref(v))
+        return v.value
+
     def submit(self, n: int, gates, dtype: str = "c64", init_basis: int = 0, k: int = 6,
-               strategy: str = "dfs") -> int:
+               strategy: str = "dfs", arrival_s: float = -1.0) -> int:
         arr = gates_to_array(gates)
         t = _u64()
         _call("hs_server_submit", self.handle, int(n), arr, len(gates), DTYPES[dtype],
-              int(init_basis), int(k), STRATEGIES[strategy], C.byref(t))
+              int(init_basis), int(k), STRATEGIES[strategy], float(arrival_s), C.byref(t))
         return t.value
 
     def wait(self, ticket: int, timeout_ms: int = -1) -> None:
@@ -442,6 +450,12 @@ class Server:
         v = C.c_double()
         _call("hs_server_latency", self.handle, int(ticket), C.byref(v))
         return v.value
+
+    def timing(self, ticket: int) -> tuple[float, float, float, float]:
+        """(host queue, preparation, admission wait, device) seconds of a finished request."""
+        out = np.zeros(4, dtype=np.float64)
+        _call("hs_server_timing", self.handle, int(ticket), out.ctypes.data_as(_dp))
+        return tuple(float(v) for v in out)
 
     def release(self, ticket: int) -> None:
         _call("hs_server_release", self.handle, int(ticket))

@@ -49,7 +49,11 @@ def simulate(n, gates, dtype, k, strategy, mode="part_spec", init=0, extra=None)
                                                   dtype=dtype, seed=0, trials=32)
         else:
             plan = hisv.Plan.partition(hisv.Circuit(n, gs), k, strategy, seed=0, trials=32)
-        st.simulate(plan, mode)
+        if mode == "auto_spec":  # AUTO over specialized gate-by-gate and fused kernels
+            plan.specialize(dtype)
+            st.simulate(plan, "auto")
+        else:
+            st.simulate(plan, mode)
     st.sync()
     return st, buf
 
@@ -107,10 +111,15 @@ def test_layered28_round_trip(dtype):
     assert report("layered28 U^-1 U", np.abs(got - want), n) <= TOL[dtype]
 
 
-@pytest.mark.parametrize("strategy", ["dagp", "ml-dagp", "greedy", "ml-greedy"])
-def test_qft32_closed_form(strategy):
+@pytest.mark.parametrize("strategy,mode", [("dagp", "part_spec"), ("ml-dagp", "part_spec"),
+                                           ("greedy", "part_spec"), ("ml-greedy", "part_spec"),
+                                           ("greedy", "part_fused"), ("greedy", "auto_spec")])
+def test_qft32_closed_form(strategy, mode):
+    """The 32-qubit QFT on a random basis state (32 GiB complex64), k = 7:
+    gate-by-gate specialized kernels, the fused dense-unitary kernels on
+    matrix cores, and AUTO over both."""
     n, gates, x = wl.qft32(0)
-    st, buf = simulate(n, gates, "c64", 7, strategy, init=x)
+    st, buf = simulate(n, gates, "c64", 7, strategy, mode=mode, init=x)
     idx = sample_indices(n, 1 << 18, 4)
     want = np.exp(2j * np.pi * ((np.uint64(x) * idx) % np.uint64(1 << n)).astype(np.float64)
                   / (1 << n)) / math.sqrt(1 << n)
@@ -130,6 +139,45 @@ def test_random34_product_block(n, dtype, strategy):
     d = np.abs(st.amplitudes_at(idx) - product_amp(idx, n, pe, po))
     assert report(f"random{n} product", d, n) <= TOL[dtype]
     assert abs(st.norm() - 1) <= (1e-5 if dtype == "c64" else 1e-12)
+
+
+@pytest.mark.parametrize("k,mode", [(5, "part_spec"), (6, "part_spec"), (7, "part_lds")])
+def test_random34_product_block_k_and_interpreter(k, mode):
+    """The 34-qubit complex64 workload's k sweep (5 and 6, specialized
+    kernels) and the interpreter kernel at k = 7, on the product-block
+    variant of its gate distribution."""
+    n, dtype = 34, "c64"
+    gates = wl.product_block_circuit(n, 1000, wl.RANDOM34_KINDS, seed=5)
+    st, buf = simulate(n, gates, dtype, k, "greedy", mode=mode)
+    pe, po = product_factors(n, gates)
+    idx = sample_indices(n, 1 << 16, 6 + k)
+    d = np.abs(st.amplitudes_at(idx) - product_amp(idx, n, pe, po))
+    assert report(f"random{n} product k={k} {mode}", d, n) <= TOL[dtype]
+    assert abs(st.norm() - 1) <= 1e-5
+
+
+@pytest.fixture(scope="module")
+def headline22():
+    """The headline gate distribution (1,000 gates over {H, RZ, RX, CX, CZ})
+    at 22 qubits, and the oracle's full state for it."""
+    n, gates = wl.random34(0, n=22)
+    print("[case] oracle, random22 (1,000 gates)", flush=True)
+    return n, gates, sv.simulate(n, gates)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_headline_configuration_full_vector(dtype, headline22):
+    """The headline launch configuration -- greedy partition, k = 7,
+    specialized kernels -- against the oracle on every amplitude at 22
+    qubits (max |d| and ||d||_2 bars)."""
+    n, gates, want = headline22
+    st, buf = simulate(n, gates, dtype, 7, "greedy")
+    got = st.amplitudes()
+    d = np.abs(got - want)
+    report(f"random{n} full vector {dtype}", d, n)
+    bar_max, bar_l2 = {"c64": (2e-5, 1e-4), "c128": (1e-12, 1e-11)}[dtype]
+    assert float(d.max()) <= bar_max
+    assert float(np.linalg.norm(got - want)) <= bar_l2
 
 
 @pytest.mark.parametrize("n,dtype", [(35, "c64"), (34, "c128")])

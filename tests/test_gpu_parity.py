@@ -167,8 +167,15 @@ def test_readout_norm_probabilities(dtype):
     check(amp, want, dtype)
     # slices, probabilities and the FP64 norm
     np.testing.assert_array_equal(st.amplitudes(1000, 77), amp[1000:1077])
-    p = st.probabilities(5, 300)
-    np.testing.assert_allclose(p, np.abs(amp[5:305]) ** 2, rtol=1e-12, atol=1e-300)
+    # probabilities of every amplitude against the oracle's |psi|^2: with
+    # |a - psi| <= e, | |a|^2 - |psi|^2 | <= 2 e |psi| + e^2
+    e = TOL[dtype][0]
+    p_want = sv.probabilities(want)
+    p = st.probabilities()
+    assert p.size == want.size
+    bar = 2 * e * np.abs(want) + e * e
+    assert np.all(np.abs(p - p_want) <= bar), float(np.max(np.abs(p - p_want) - bar))
+    np.testing.assert_array_equal(st.probabilities(5, 300), p[5:305])
     nrm = st.norm()
     assert abs(nrm - 1.0) < (1e-12 if dtype == "c128" else 1e-5)
     assert st.norm() == nrm  # fixed-order reduction: identical on every call

@@ -25,23 +25,31 @@ def _requests(count, seed, n_range=(8, 16), layer_range=(3, 12)):
 
 
 def test_mixed_equals_alone_and_oracle():
+    """Every amplitude of every request: the same in the mix as alone
+    (bitwise: same kernels, same plan), and within the dtype's bars of the
+    oracle (max |d| and ||d||_2)."""
     reqs = _requests(16, 3)
     print("[case] 16 requests submitted together", flush=True)
-    lat, wall, stats, mixed = serving.run_stream(reqs, read_check=1 << 8, num_streams=4)
+    res = serving.run_stream(reqs, read_states=True, num_streams=4)
+    stats = res["stats"]
     assert stats["completed"] == len(reqs)
     assert stats["peak_inflight"] >= 2, "requests must overlap on the device"
     print("[case] the same requests one at a time", flush=True)
     alone = []
     for r in reqs:
-        _, _, _, a = serving.run_stream([r], read_check=1 << 8, num_streams=1)
-        alone.append(a[0])
-    for r, m, a in zip(reqs, mixed, alone):
-        np.testing.assert_array_equal(m, a)  # same kernels, same plan: bitwise
+        alone.append(serving.run_stream([r], read_states=True, num_streams=1)["states"][0])
+    for r, m, a in zip(reqs, res["states"], alone):
+        assert m.size == 1 << r.n
+        np.testing.assert_array_equal(m, a)
         n, gates = wl.layered28(r.seed, n=r.n, layers=r.layers)
-        want = sv.simulate(n, gates)[: 1 << 8]
-        tol = 2e-5 if r.dtype == "c64" else 1e-12
-        assert np.max(np.abs(m - want)) <= tol
-    assert np.all(lat > 0)
+        want = sv.simulate(n, gates)
+        bar_max, bar_l2 = (2e-5, 1e-4) if r.dtype == "c64" else (1e-12, 1e-11)
+        assert np.max(np.abs(m - want)) <= bar_max
+        assert np.linalg.norm(m - want) <= bar_l2
+    assert np.all(res["latency"] > 0)
+    # the four parts of each latency add up to it
+    np.testing.assert_allclose(res["parts"].sum(axis=1), res["latency"], rtol=1e-9, atol=1e-9)
+    assert np.all(res["parts"] >= 0)
 
 
 def test_budget_is_respected():
@@ -49,7 +57,7 @@ def test_budget_is_respected():
     biggest = (1 << 16) * 16
     budget = 3 * biggest + (1 << 20)
     print("[case] budget of three 16-qubit states", flush=True)
-    lat, wall, stats, _ = serving.run_stream(reqs, budget_bytes=budget, num_streams=4)
+    stats = serving.run_stream(reqs, budget_bytes=budget, num_streams=4)["stats"]
     assert stats["completed"] == len(reqs)
     assert stats["peak_bytes"] <= budget
     assert stats["cur_bytes"] == 0
@@ -61,4 +69,31 @@ def test_request_larger_than_budget_is_rejected():
     with pytest.raises(hisv.HisvError) as e:
         srv.submit(n, gates, "c64", 0, 6)
     assert e.value.code == "HS_E_ADMISSION"
+    srv.close()
+
+
+def test_arrival_stamp_and_errors():
+    """Latency starts at the given arrival stamp; an arrival in the future is
+    refused; a request that fails during preparation reports its error."""
+    srv = hisv.Server(num_streams=2)
+    n, gates = wl.layered28(1, n=10, layers=3)
+    with pytest.raises(hisv.HisvError) as e:
+        srv.submit(n, gates, "c64", 0, 10, "greedy", arrival_s=srv.clock() + 60.0)
+    assert e.value.code == "HS_E_ARG"
+    t_arr = srv.clock() - 0.25  # arrived a quarter second ago
+    t = srv.submit(n, gates, "c64", 0, 10, "greedy", arrival_s=t_arr)
+    srv.wait(t)
+    assert srv.latency(t) >= 0.25
+    q, prep, adm, dev = srv.timing(t)
+    assert q >= 0.25 - 1e-3 and prep > 0 and dev > 0
+    srv.release(t)
+    srv.close()
+    # the state fits this budget but state + descriptors do not: the request
+    # is accepted, fails while being prepared, and wait reports why
+    srv = hisv.Server(budget_bytes=(1 << n) * 8 + 16, num_streams=1)
+    t = srv.submit(n, gates, "c64", 0, 10, "greedy")
+    with pytest.raises(hisv.HisvError) as e:
+        srv.wait(t)
+    assert e.value.code == "HS_E_ADMISSION"
+    srv.release(t)
     srv.close()
