@@ -4,11 +4,12 @@
 A step is one pass of the whole path over one circuit: the gate list is
 loaded, partitioned (greedy ready-set partitioner; --strategy picks Nat,
 DFS or dagP of Sec. IV.B instead) and compiled (the specialized part
-kernels come from the kernel cache after the warmup), every part is applied
-as one in-place Gather-Execute-Scatter sweep of a state resident in HBM
-(Alg. 1), and the FP64 norm is read back.  Default workload: a 34-qubit random
-circuit of 1,000 gates drawn uniformly from {H, RZ, RX, CX, CZ}, complex64
-state (128 GiB), acyclic partition with at most k qubits per part.
+kernels come from the kernel cache after the first pass), every part is
+applied as one in-place Gather-Execute-Scatter sweep of a state resident in
+HBM (Alg. 1), and the FP64 norm is read back.  Default workload: a 33-qubit
+random circuit of 1,000 gates drawn uniformly from {H, RZ, RX, CX, CZ},
+complex128 state (the paper's 16 bytes per amplitude, Sec. II.B; 128 GiB),
+acyclic partition with at most k = 7 qubits per part.
 
 Prints ONE JSON line on stdout:
   value      gates/s over the timed steps (wall clock, synchronized; host
@@ -17,24 +18,35 @@ Prints ONE JSON line on stdout:
              every amplitude once: 2 * 2^n * bytes/amplitude) / the average
              launch duration from HIP events on the kernel's stream, against
              the 8 TB/s HBM peak; `traffic` from committed rocprofv3 counters
-  gate_per_pass  the same GPU, one sweep per gate, on the circuit's first gates
-  serving    p50/p99 latency and circuits/s of a short Poisson request stream
-  sweep      the same circuit distribution at n = 30..33 (k = 7), n = 34 at
-             k = 5 and 6, a 33-qubit complex128 state, and the largest states
-             that fit (35-qubit complex64, 34-qubit complex128; 256 GiB):
-             one timed step each
+  first_run  the first pass of the circuit in the process: wall time with the
+             kernel build, the same circuit on the interpreter kernel (no
+             build), and the runs after which the build has paid for itself
+  gate_per_pass  the same GPU, one sweep per gate: one- and two-qubit gates
+             timed separately and projected onto the circuit's mix
+  random34_c64  the 34-qubit complex64 state (same bytes) under the same
+             protocol, with its own roofline
+  streaming  in-place streaming rate of a plain one-gate sweep, n = 30..34
+  sweep      the same circuit distribution at n = 30..32 (both dtypes), 33
+             (complex64), n = 34 at k = 5 and 6, and the largest states that
+             fit (35-qubit complex64, 34-qubit complex128; 256 GiB): one
+             timed run each
   multilevel the same circuits with the multi-level partition (first level
              bounded by the padded LDS tile, 14 qubits complex64 / 13
              complex128; second level = register stages)
   layered28  28 qubits, 40 layers (U3 on every qubit + CX matching),
              k = 6, complex64 and complex128: interpreter (PART_LDS) vs
              specialized kernels vs AUTO vs one sweep per gate
+  dressed30  deep dense five-qubit parts (dressed two-qubit blocks, ~80
+             gates per part), k = 5: gate-by-gate vs fused vs AUTO
   qft32      a 32-qubit QFT on a random basis state, k = 7:
              gate-by-gate (specialized) vs fused-unitary (matrix cores) vs
              AUTO, with the fused kernel's matrix-core roofline
+  serving    p50/p99 latency (from each request's scheduled arrival) and
+             circuits/s of a Poisson stream of 1,000 requests
   accuracy   U^-1 U |0> against |0> on sampled amplitudes of the headline
              state (untimed)
-  cpu_baseline  the oracle (numpy complex128) on a bounded sample
+  cpu_baseline  the oracle (numpy complex128, one thread) on a bounded
+             sample, extrapolated to the headline size
 """
 
 from __future__ import annotations
@@ -103,9 +115,12 @@ def committed_traffic(n: int, dtype: str, k: int, khash: str):
     return rec["bytes_per_launch"]
 
 
-def cpu_baseline(n_target: int, seed: int, budget_s: float = 12.0, n_cpu: int = 24) -> dict:
+def cpu_baseline(n_target: int, seed: int, dtype: str, budget_s: float = 20.0, n_cpu: int = 28) -> dict:
     """The oracle as it stands, one host thread, on the first gates of the same
-    circuit distribution at n_cpu qubits; per-gate time scaled by 2^(n_target-n_cpu)."""
+    circuit distribution at n_cpu qubits (complex128, the oracle's only
+    precision); per-gate time scaled by 2^(n_target-n_cpu).  The oracle cannot
+    hold the target state on the host in the time allowed (2^33 complex128
+    amplitudes are 128 GiB), so the figure is extrapolated and says so."""
     from threadpoolctl import threadpool_limits
 
     from oracle import statevector as sv  # test infrastructure: this leg only
@@ -125,10 +140,12 @@ def cpu_baseline(n_target: int, seed: int, budget_s: float = 12.0, n_cpu: int = 
     per_gate = dt / done
     scale = 2.0 ** (n_target - n_cpu)
     return {
-        "value": 1.0 / (per_gate * scale), "unit": "gates/s", "cores": 1, "kind": "oracle",
+        "value": 1.0 / (per_gate * scale), "unit": "gates/s", "cores": 1,
+        "kind": "oracle, extrapolated",
         "sample": (f"numpy complex128 oracle, 1 thread, first {done} gates of the same "
                    f"distribution at n={n_cpu} ({dt:.1f} s); per-gate time x2^{n_target - n_cpu} "
-                   f"to n={n_target}"),
+                   f"to n={n_target} (the GPU state is {dtype})"),
+        "extrapolated_from_n": n_cpu,
         "host_cpus": len(os.sched_getaffinity(0)),
     }
 
@@ -149,11 +166,14 @@ def timed_plan(st, plan, stream, steps=1, mode="part_spec"):
 
 
 def run_sweep(args, buf, stream, log):
-    """The headline circuit distribution over n = 30..34, k = 5..7 and both dtypes."""
+    """The headline circuit distribution over n = 30..35, k = 5..7 and both dtypes
+    (the 33-qubit complex128 and 34-qubit complex64 k = 7 cases are the
+    headline runs themselves)."""
     from paper_2205_06973_amd import hisv
     from paper_2205_06973_amd import workloads as wl
     cases = [(30, "c64", 7), (31, "c64", 7), (32, "c64", 7), (33, "c64", 7),
-             (34, "c64", 5), (34, "c64", 6), (33, "c128", 7),
+             (34, "c64", 5), (34, "c64", 6),
+             (30, "c128", 7), (31, "c128", 7), (32, "c128", 7),
              (35, "c64", 7), (34, "c128", 7)]  # the last two: 256 GiB states
     rows = []
     for n, dt, k in cases:
@@ -268,6 +288,44 @@ def run_layered(args, buf, stream, log):
     return rows
 
 
+def run_dressed(args, buf, stream, log):
+    """Deep, dense five-qubit parts: dressed two-qubit blocks (U3 on both
+    qubits, a CX / CZ / CP / SWAP, U3 again) drawn from a five-qubit window
+    that moves up one qubit every 16 blocks; 600 blocks = 3,000 gates on 30
+    qubits, k = 5 (about 80 gates per part).  Gate-by-gate (specialized) vs
+    the fused dense unitary (matrix cores) vs AUTO, both dtypes."""
+    import torch
+    from paper_2205_06973_amd import hisv
+    from paper_2205_06973_amd import workloads as wl
+    n, k = 30, 5
+    gates = wl.dressed_pairs_circuit(n, 600, seed=3, span=5, dwell=16)
+    plan = hisv.Plan.partition(hisv.Circuit(n, gates), k, args.strategy, seed=args.seed,
+                               trials=args.trials)
+    P, G = plan.num_parts, len(gates)
+    rows = []
+    for dt in ("c64", "c128"):
+        nbytes = (1 << n) * (8 if dt == "c64" else 16)
+        view = buf.view(torch.uint8)[:nbytes].view(torch.complex64 if dt == "c64" else torch.complex128)
+        st = hisv.State.wrap_tensor(view, stream)
+        plan.specialize(dt)
+        row = {"workload": "dressed30", "n": n, "dtype": dt, "k": k, "strategy": args.strategy,
+               "parts": P, "gates": G, "auto_fused_parts": int(plan.auto_choice(dt).sum())}
+        for mode in ("part_spec", "part_fused", "auto"):
+            st.set_basis(0)
+            sec = timed_plan(st, plan, stream, steps=2, mode=mode)
+            gbs = part_pass_bytes(n, dt) * P / sec / 1e9
+            row[mode] = {"gates_per_s": G / sec, "ms_per_circuit": sec * 1e3,
+                         "pass_GBps": gbs, "frac": gbs / HBM_PEAK_GBS, "norm_after": st.norm()}
+            if not abs(row[mode]["norm_after"] - 1.0) < 1e-3:
+                raise RuntimeError(f"norm drift in dressed case {dt} {mode}")
+        row["speedup_auto_over_part_spec"] = (row["part_spec"]["ms_per_circuit"]
+                                              / row["auto"]["ms_per_circuit"])
+        st.close()
+        log(f"[bench] dressed30 {row}")
+        rows.append(row)
+    return rows
+
+
 def run_qft(buf, stream, log, strategy="greedy", trials=256):
     """32-qubit QFT (H + controlled-phase ladder + swaps) on a random basis
     state, dagP k = 7: gate-by-gate specialized kernels (a) vs the fused dense
@@ -322,23 +380,197 @@ def run_qft(buf, stream, log, strategy="greedy", trials=256):
     return out
 
 
+def whole_path(args, n, dt, k, gates, view, stream, steps, warmup, log):
+    """Time `steps` passes of the whole path on one state (after `warmup`).
+
+    A pass ingests the gate list, partitions it, compiles it (specialized
+    kernels come from the kernel cache once built), applies every part and
+    reads the FP64 norm back.  The very first pass of a circuit also builds
+    its kernels: it is timed on its own (`first_run`) next to the same
+    circuit on the interpreter kernel, which needs no build."""
+    import torch
+    from paper_2205_06973_amd import hisv
+    G = len(gates)
+    st = hisv.State.wrap_tensor(view, stream)
+    st.set_basis(0)
+    mode = args.mode
+
+    def step(events=None, run_mode=mode):
+        circ = hisv.Circuit(n, gates)
+        plan = hisv.Plan.partition(circ, k, args.strategy, seed=args.seed, trials=args.trials)
+        if run_mode == "part_spec":
+            plan.specialize(dt)
+        if events is not None:
+            events[0].record(stream)
+        st.simulate(plan, run_mode)
+        if events is not None:
+            events[1].record(stream)
+        return plan, st.norm()
+
+    # one-shot cost: the first pass of this circuit in this process (kernel
+    # build included), then the same circuit on the interpreter kernel
+    first = {}
+    for label, m in (("wall_s", mode), ("interpreter_wall_s", "part_lds")):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        plan, norm = step(run_mode=m)
+        torch.cuda.synchronize()
+        first[label] = time.perf_counter() - t
+        if not abs(norm - 1.0) < 1e-3:
+            raise RuntimeError(f"norm {norm} after the first {m} pass")
+    P = plan.num_parts
+    log(f"[bench] n={n} {dt} G={G} k={k} {args.strategy}: {P} parts; first pass "
+        f"{first['wall_s']:.2f} s ({mode}, kernel build included), "
+        f"{first['interpreter_wall_s']:.2f} s (part_lds)")
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        plan, norm = step(ev[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = sum(a.elapsed_time(b) for a, b in ev)
+    log(f"[bench] timed {steps} steps: wall {wall:.3f} s, part kernels (events) {gpu_ms:.1f} ms")
+    if not abs(norm - 1.0) < 1e-3:
+        # a unitary circuit keeps the norm: anything else is a wrong result
+        raise RuntimeError(f"norm after the timed steps is {norm}, not 1")
+    launches = steps * P
+    avg_launch_s = gpu_ms / 1e3 / launches
+    bpl = part_pass_bytes(n, dt)
+    achieved = bpl / avg_launch_s / 1e9
+    khash = spec_kernel_hash(plan, dt) if mode == "part_spec" else None
+    traffic = committed_traffic(n, dt, k, khash) if khash else None
+    warm_s = wall / steps
+    first["gates_per_s"] = G / first["wall_s"]
+    first["interpreter_gates_per_s"] = G / first["interpreter_wall_s"]
+    # runs of the same circuit after which the kernel build has paid for itself
+    gain = first["interpreter_wall_s"] - warm_s
+    first["break_even_runs"] = ((first["wall_s"] - warm_s) / gain) if gain > 0 else None
+    res = {
+        "value": G * steps / wall, "ms_per_step": warm_s * 1e3, "plan": plan, "norm": norm,
+        "parts": P, "first_run": first, "gpu_ms": gpu_ms,
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": {"part_spec": "part_pass_spec", "part_lds": "part_pass_kernel",
+                       "auto": "part_pass_kernel+fused_pass_kernel"}[mode],
+            "bytes_per_launch": bpl,
+            "avg_launch_us": avg_launch_s * 1e6, "launches": launches, "kernel_hash": khash,
+        },
+        "state": st,
+    }
+    return res
+
+
+def round_trip_error(args, st, plan, n, k, gates):
+    """U then U^-1 from |0> must give |0> again (untimed; the inverse runs on
+    the interpreter: no second kernel build)."""
+    import numpy as np
+    from paper_2205_06973_amd import hisv
+    st.set_basis(0)
+    st.simulate(plan, args.mode)
+    inv = hisv.Plan.partition(hisv.Circuit(n, inverse_gates(gates)), k, args.strategy,
+                              seed=args.seed, trials=64)
+    st.simulate(inv, "part_lds")
+    rng = np.random.default_rng(7)
+    idx = np.unique(np.concatenate([np.arange(4096, dtype=np.uint64),
+                                    rng.integers(0, 1 << n, 1 << 14, dtype=np.uint64),
+                                    np.arange((1 << n) - 4096, 1 << n, dtype=np.uint64)]))
+    amp = st.amplitudes_at(idx)
+    return idx.size, float(np.max(np.abs(amp - (idx == 0))))
+
+
+def gate_per_pass(st, n, dt, gates, stream, count, part_kernel_s):
+    """One sweep per gate on the same state, timed separately for one- and
+    two-qubit gates (a two-qubit sweep leaves a quarter of the amplitudes
+    alone), then projected onto the whole circuit's mix of the two."""
+    import torch
+    from paper_2205_06973_amd import hisv
+    one = [g for g in gates if g[2] < 0][:count]
+    two = [g for g in gates if g[2] >= 0][:count]
+    per = {}
+    for name, sub in (("1q", one), ("2q", two)):
+        circ = hisv.Circuit(n, sub)
+        st.simulate_gate_per_pass(circ)  # warm
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        st.simulate_gate_per_pass(circ)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        per[name] = e0.elapsed_time(e1) / 1e3 / len(sub)
+    n1 = sum(1 for g in gates if g[2] < 0)
+    n2 = len(gates) - n1
+    circuit_s = n1 * per["1q"] + n2 * per["2q"]
+    bpl = part_pass_bytes(n, dt)
+    return {
+        "gates_timed": {"1q": len(one), "2q": len(two)},
+        "ms_per_gate": {"1q": per["1q"] * 1e3, "2q": per["2q"] * 1e3},
+        "pass_GBps_1q": bpl / per["1q"] / 1e9,
+        "circuit_gates": {"1q": n1, "2q": n2},
+        "gates_per_s": len(gates) / circuit_s,
+        # like for like: kernel time of the partitioned path (HIP events)
+        # against the projected kernel time of one sweep per gate
+        "speedup_partitioned_kernels": circuit_s / part_kernel_s,
+    }
+
+
+def streaming_ceiling(buf, stream, log, cases):
+    """In-place streaming rate of the plainest full-state sweep: one
+    single-qubit gate (H on the lowest qubit) per pass, per size."""
+    import torch
+    from paper_2205_06973_amd import hisv
+    rows = []
+    for n, dt in cases:
+        amp = 8 if dt == "c64" else 16
+        if (1 << n) * amp > buf.numel() * buf.element_size():
+            continue
+        view = buf.view(torch.uint8)[: (1 << n) * amp].view(
+            torch.complex64 if dt == "c64" else torch.complex128)
+        st = hisv.State.wrap_tensor(view, stream)
+        st.set_basis(0)
+        circ = hisv.Circuit(n, [("h", 0, -1, ())] * 8)
+        st.simulate_gate_per_pass(circ)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        st.simulate_gate_per_pass(circ)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) / 1e3 / 8
+        gbs = part_pass_bytes(n, dt) / sec / 1e9
+        rows.append({"n": n, "dtype": dt, "ms_per_pass": sec * 1e3, "pass_GBps": gbs,
+                     "frac": gbs / HBM_PEAK_GBS})
+        st.close()
+        log(f"[bench] streaming {rows[-1]}")
+    return rows
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=34)
+    ap.add_argument("--n", type=int, default=33)
     ap.add_argument("--gates", type=int, default=1000)
     ap.add_argument("--k", type=int, default=7)
-    ap.add_argument("--dtype", default="c64", choices=["c64", "c128"])
+    ap.add_argument("--dtype", default="c128", choices=["c64", "c128"])
     ap.add_argument("--strategy", default="greedy", choices=["nat", "dfs", "dagp", "greedy"])
     ap.add_argument("--trials", type=int, default=256,
                     help="orders (DFS) or tie-break draws (greedy) tried per partition")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--mode", default="part_spec", choices=["part_lds", "part_spec", "auto"])
-    ap.add_argument("--gpp-gates", type=int, default=48,
-                    help="gates timed on the gate-per-pass baseline (0 = skip)")
-    ap.add_argument("--serving", type=int, default=120, help="serving requests (0 = skip)")
+    ap.add_argument("--gpp-gates", type=int, default=24,
+                    help="one- and two-qubit gates each timed on the gate-per-pass baseline (0 = skip)")
+    ap.add_argument("--c64-steps", type=int, default=2,
+                    help="timed steps of the 34-qubit complex64 companion run (0 = skip)")
+    ap.add_argument("--serving", type=int, default=1000, help="serving requests (0 = skip)")
     ap.add_argument("--serving-rate", type=float, default=40.0, help="arrivals per second")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--tune", action="append", default=[], metavar="KEY=VALUE",
@@ -346,13 +578,17 @@ def main() -> int:
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="also run the plain copy kernel on this many GiB (counter calibration)")
     ap.add_argument("--no-sweep", action="store_true", help="skip the n / k / dtype sweep")
+    ap.add_argument("--no-streaming", action="store_true", help="skip the streaming-rate probe")
     ap.add_argument("--no-qft", action="store_true", help="skip the 32-qubit QFT comparison")
     ap.add_argument("--no-multilevel", action="store_true", help="skip the multi-level partition runs")
     ap.add_argument("--no-layered", action="store_true", help="skip the 28-qubit layered circuit runs")
+    ap.add_argument("--no-dressed", action="store_true", help="skip the dense five-qubit-part runs")
     ap.add_argument("--layered-only", action="store_true",
                     help="run only the 28-qubit layered section (for profiling)")
     ap.add_argument("--qft-only", action="store_true",
                     help="run only the 32-qubit QFT comparison (for kernel profiles)")
+    ap.add_argument("--streaming-only", action="store_true",
+                    help="run only the streaming-rate probe (for profiles)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -373,179 +609,109 @@ def main() -> int:
     for kv in args.tune:
         key, val = kv.split("=")
         hisv.hs_tune(key, int(val))
+    stream = torch.cuda.Stream()
+    stream_cases = [(30, "c64"), (31, "c64"), (32, "c64"), (33, "c64"), (34, "c64"),
+                    (30, "c128"), (31, "c128"), (32, "c128"), (33, "c128")]
     if args.layered_only:
-        stream = torch.cuda.Stream()
         with torch.cuda.stream(stream):
             lbuf = torch.empty(1 << 28, dtype=torch.complex128, device="cuda")
         print(json.dumps({"layered28": run_layered(args, lbuf, stream, log)}), flush=True)
         return 0
     if args.qft_only:
-        stream = torch.cuda.Stream()
         with torch.cuda.stream(stream):
             qbuf = torch.empty(1 << 32, dtype=torch.complex64, device="cuda")
         print(json.dumps({"qft32": run_qft(qbuf, stream, log, args.strategy, args.trials)}), flush=True)
         return 0
-    n, G = args.n, args.gates
+    if args.streaming_only:
+        with torch.cuda.stream(stream):
+            sbuf = torch.empty(1 << 34, dtype=torch.complex64, device="cuda")
+        print(json.dumps({"streaming": streaming_ceiling(sbuf, stream, log, stream_cases)}), flush=True)
+        return 0
+
+    n, G, dt = args.n, args.gates, args.dtype
     _, gates = wl.random34(args.seed, n=n, num_gates=G)
-    stream = torch.cuda.Stream()
-    tdt = torch.complex64 if args.dtype == "c64" else torch.complex128
+    tdt = torch.complex64 if dt == "c64" else torch.complex128
     with torch.cuda.stream(stream):
         buf = torch.empty(1 << n, dtype=tdt, device="cuda")
-    st = hisv.State.wrap_tensor(buf, stream)
-    st.set_basis(0)
-
-    def step(events=None):
-        """One pass of the whole path: ingest the gate list, partition, compile
-        (specialized kernels come from the kernel cache after the first step),
-        apply every part, read the FP64 norm back."""
-        circ = hisv.Circuit(n, gates)
-        plan = hisv.Plan.partition(circ, args.k, args.strategy, seed=args.seed, trials=args.trials)
-        if args.mode == "part_spec":
-            plan.specialize(args.dtype)
-        if events is not None:
-            events[0].record(stream)
-        st.simulate(plan, args.mode)
-        if events is not None:
-            events[1].record(stream)
-        return plan, st.norm()
-
-    t = time.perf_counter()
-    plan = hisv.Plan.partition(hisv.Circuit(n, gates), args.k, args.strategy, seed=args.seed,
-                               trials=args.trials)
-    part_ms = (time.perf_counter() - t) * 1e3
-    P = plan.num_parts
-    log(f"[bench] n={n} G={G} k={args.k} {args.strategy}: {P} parts ({part_ms:.1f} ms)")
-    spec_s = 0.0
-    if args.mode == "part_spec":
-        t = time.perf_counter()
-        plan.specialize(args.dtype)  # compiles and caches the part kernels
-        spec_s = time.perf_counter() - t
-        log(f"[bench] specialized {P} part kernels in {spec_s:.1f} s")
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    log(f"[bench] warmup done ({args.warmup} steps)")
-
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        plan, norm = step(ev[i])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = sum(a.elapsed_time(b) for a, b in ev)
-    log(f"[bench] timed {args.steps} steps: wall {wall:.3f} s, part kernels (events) {gpu_ms:.1f} ms")
-    if not abs(norm - 1.0) < 1e-3:
-        # a unitary circuit keeps the norm: anything else is a wrong result
-        log(f"[bench] ERROR: norm after the timed steps is {norm}, not 1")
-        return 3
-
-    launches = args.steps * P
-    avg_launch_s = gpu_ms / 1e3 / launches
-    bpl = part_pass_bytes(n, args.dtype)
-    achieved = bpl / avg_launch_s / 1e9
-    # the committed counters were taken on the specialized kernels
-    khash = spec_kernel_hash(plan, args.dtype) if args.mode == "part_spec" else None
-    traffic = committed_traffic(n, args.dtype, args.k, khash) if khash else None
+    head = whole_path(args, n, dt, args.k, gates, buf, stream, args.steps, args.warmup, log)
+    st, plan, P = head["state"], head["plan"], head["parts"]
+    bpl = part_pass_bytes(n, dt)
+    state_name = "complex64" if dt == "c64" else "complex128"
     out = {
         "metric": METRIC,
-        "value": G * args.steps / wall,
+        "value": head["value"],
         "unit": "gates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.dtype == "c64" else "f64",
+        "dtype": "f32" if dt == "c64" else "f64",
         "data": "synthetic",
         "config": {
             "workload": (f"random{n}: {n}-qubit random circuit, {G} gates uniform over "
-                         f"{{H,RZ,RX,CX,CZ}}, {'complex64' if args.dtype == 'c64' else 'complex128'} "
-                         f"state ({bpl // 2 / 2**30:.0f} GiB), {args.strategy.upper()} partition k={args.k}"),
+                         f"{{H,RZ,RX,CX,CZ}}, {state_name} state ({bpl // 2 / 2**30:.0f} GiB), "
+                         f"{args.strategy.upper()} partition k={args.k}"),
             "n": n, "gates": G, "k": args.k, "parts": P, "strategy": args.strategy,
-            "state": "complex64" if args.dtype == "c64" else "complex128", "mode": args.mode,
-            "passes_saved": G / P, "specialize_s": spec_s,
+            "state": state_name, "mode": args.mode, "passes_saved": G / P,
         },
-        "roofline": {
-            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": {"part_spec": "part_pass_spec", "part_lds": "part_pass_kernel",
-                       "auto": "part_pass_kernel+fused_pass_kernel"}[args.mode],
-            "bytes_per_launch": bpl,
-            "avg_launch_us": avg_launch_s * 1e6, "launches": launches, "kernel_hash": khash,
-        },
-        "norm_after": norm,
+        "roofline": head["roofline"],
+        "first_run": head["first_run"],
+        "norm_after": head["norm"],
     }
-
-    # accuracy at full size, untimed: U then U^-1 from |0> must give |0> again
-    # (the inverse runs on the interpreter: no second kernel build)
-    import numpy as np
-    st.set_basis(0)
-    st.simulate(plan, args.mode)
-    inv = hisv.Plan.partition(hisv.Circuit(n, inverse_gates(gates)), args.k, args.strategy,
-                              seed=args.seed, trials=64)
-    st.simulate(inv, "part_lds")
-    rng = np.random.default_rng(7)
-    idx = np.unique(np.concatenate([np.arange(4096, dtype=np.uint64),
-                                    rng.integers(0, 1 << n, 1 << 14, dtype=np.uint64),
-                                    np.arange((1 << n) - 4096, 1 << n, dtype=np.uint64)]))
-    amp = st.amplitudes_at(idx)
-    err = float(np.max(np.abs(amp - (idx == 0))))
+    cnt, err = round_trip_error(args, st, plan, n, args.k, gates)
     out["accuracy"] = {
-        "check": f"U^-1 U |0> against |0> on {idx.size} amplitudes (first and last 4096, "
-                 f"2^14 random)",
-        "max_abs_err": err, "tolerance": 2e-5 if args.dtype == "c64" else 1e-12,
+        "check": f"U^-1 U |0> against |0> on {cnt} amplitudes (first and last 4096, 2^14 random)",
+        "max_abs_err": err, "tolerance": 2e-5 if dt == "c64" else 1e-12,
     }
     log(f"[bench] round trip max |d| = {err:.3e}")
-
     if args.gpp_gates > 0:
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        sub = hisv.Circuit(n, gates[:args.gpp_gates])
-        st.simulate_gate_per_pass(sub)  # warm
-        torch.cuda.synchronize()
-        e0.record(stream)
-        st.simulate_gate_per_pass(sub)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        gpp_s = e0.elapsed_time(e1) / 1e3
-        gpp_rate = args.gpp_gates / gpp_s
-        out["gate_per_pass"] = {
-            "gates_timed": args.gpp_gates, "gates_per_s": gpp_rate,
-            "pass_GBps": bpl / (gpp_s / args.gpp_gates) / 1e9,
-            "speedup_partitioned": out["value"] / gpp_rate,
-            # like for like: both sides' kernel time from HIP events
-            "speedup_partitioned_kernels": (G * args.steps / (gpu_ms / 1e3)) / gpp_rate,
-            "passes_saved": G / P,
-            # a two-qubit sweep leaves the |00> amplitude of every quad alone
-            # (3/4 of the state moves), so in HBM bytes the saving is smaller
-            "traffic_passes_saved": (sum(1 for g in gates if g[2] < 0)
-                                     + 0.75 * sum(1 for g in gates if g[2] >= 0)) / P,
-        }
-        log(f"[bench] gate-per-pass: {gpp_rate:.1f} gates/s")
-
+        gpp = gate_per_pass(st, n, dt, gates, stream, args.gpp_gates,
+                            head["gpu_ms"] / 1e3 / args.steps)
+        gpp["passes_saved"] = G / P
+        gpp["speedup_partitioned"] = out["value"] / gpp["gates_per_s"]
+        out["gate_per_pass"] = gpp
+        log(f"[bench] gate-per-pass: {gpp}")
     st.close()
 
-    if not (args.no_sweep and args.no_multilevel and args.no_qft and args.no_layered):
+    if args.c64_steps > 0 and dt == "c128" and n == 33:
+        # the same bytes as a 34-qubit complex64 state: that workload on the
+        # same buffer, same protocol
+        view = buf.view(torch.complex64)
+        _, g34 = wl.random34(args.seed, n=34, num_gates=G)
+        r = whole_path(args, 34, "c64", args.k, g34, view, stream, args.c64_steps, 1, log)
+        r["state"].close()
+        out["random34_c64"] = {
+            "workload": (f"random34: 34-qubit random circuit, {G} gates, complex64 state (128 GiB), "
+                         f"{args.strategy.upper()} partition k={args.k}"),
+            "dtype": "f32", "gates_per_s": r["value"], "ms_per_step": r["ms_per_step"],
+            "steps": args.c64_steps, "parts": r["parts"], "roofline": r["roofline"],
+            "first_run": r["first_run"], "norm_after": r["norm"],
+        }
+        log(f"[bench] random34 c64: {r['value']:.1f} gates/s, frac {r['roofline']['frac']:.3f}")
+
+    if not (args.no_sweep and args.no_multilevel and args.no_qft and args.no_layered
+            and args.no_streaming and args.no_dressed):
         # the extra sections share one buffer: 256 GiB (a 35-qubit complex64 or
         # 34-qubit complex128 state) when the device has room, else the
         # headline's
-        big = None
         if torch.cuda.mem_get_info()[0] + buf.numel() * buf.element_size() >= (256 << 30) + (4 << 30):
             del buf
             torch.cuda.empty_cache()
             with torch.cuda.stream(stream):
-                big = torch.empty(1 << 35, dtype=torch.complex64, device="cuda")
-            buf = big
+                buf = torch.empty(1 << 35, dtype=torch.complex64, device="cuda")
+        if not args.no_streaming:
+            out["streaming"] = streaming_ceiling(buf, stream, log, stream_cases)
         if not args.no_sweep:
             out["sweep"] = run_sweep(args, buf, stream, log)
         if not args.no_multilevel:
             out["multilevel"] = run_multilevel(args, buf, stream, log)
         if not args.no_layered:
             out["layered28"] = run_layered(args, buf, stream, log)
+        if not args.no_dressed:
+            out["dressed30"] = run_dressed(args, buf, stream, log)
         if not args.no_qft:
             out["qft32"] = run_qft(buf, stream, log, args.strategy, args.trials)
     del buf
@@ -564,15 +730,15 @@ def main() -> int:
     if args.serving > 0:
         from paper_2205_06973_amd import serving
         reqs = wl.serving_stream(args.serving, args.serving_rate, seed=args.seed)
-        lat, swall, stats, _ = serving.run_stream(reqs)
-        out["serving"] = serving.summarize(lat, swall, len(reqs))
+        res = serving.run_stream(reqs)
+        out["serving"] = serving.summarize(res, len(reqs))
         out["serving"].update({"arrival_rate_per_s": args.serving_rate,
-                               "peak_inflight": stats["peak_inflight"],
-                               "peak_admitted_GiB": stats["peak_bytes"] / 2**30})
+                               "peak_inflight": res["stats"]["peak_inflight"],
+                               "peak_admitted_GiB": res["stats"]["peak_bytes"] / 2**30})
         log(f"[bench] serving: {out['serving']}")
 
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(n, args.seed)
+        out["cpu_baseline"] = cpu_baseline(n, args.seed, dt)
         log(f"[bench] cpu baseline: {out['cpu_baseline']['value']:.3g} gates/s")
 
     print(json.dumps(out), flush=True)

@@ -296,6 +296,17 @@ hs_status hs_plan_specialize(hs_plan p, hs_dtype dtype);
  * in circuit order.  HS_E_UNSUPPORTED for parts wider than 7 qubits. */
 hs_status hs_plan_part_unitary(hs_plan p, int part, int* w, double* out);
 
+/* Which kernel HS_EXEC_AUTO runs for each part of `p` at `dtype` on the
+ * current device: out[part] = 1 for the fused dense-unitary kernel, 0 for
+ * the gate-by-gate kernel (the specialized one if the plan has been
+ * specialized for `dtype` on this device, else the interpreter).  AUTO picks
+ * per part the lower of the two cost estimates, in HBM sweeps of the state:
+ * the gate-by-gate kernel's sweep plus its LDS re-layouts and register
+ * operations, against the fused kernel's measured cost for the part's width
+ * (Sec. III.A's cost argument: a part is memory-bound until its arithmetic
+ * outgrows the sweep).  out has num_parts entries (caller-owned). */
+hs_status hs_plan_auto_choice(hs_plan p, hs_dtype dtype, int32_t* out);
+
 hs_status hs_plan_destroy(hs_plan p);
 
 /* ---- simulation (Alg. 1) --------------------------------------------------- */

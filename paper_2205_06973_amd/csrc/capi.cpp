@@ -564,6 +564,14 @@ static hs_status check_exec(hs_exec exec) {
 // (AUTO) whichever the cost model prefers per part.  AUTO's gate-by-gate side
 // is the specialized kernels when hs_plan_specialize has built them for this
 // dtype and device (no hipRTC work starts here), else the interpreter.
+// AUTO's choice for part i: the fused kernel when the part has a fused form
+// and its cost (in HBM sweeps) is below the gate-by-gate kernel's -- the
+// specialized kernel's when the plan is specialized, else the interpreter's.
+static bool auto_picks_fused(Plan* p, hs_dtype dt, int i, bool specialized) {
+  const double gate_cost = specialized ? spec_part_cost(p->scomp[dt][i]) : lds_part_cost(p->comp[dt][i]);
+  return p->fused[i].w && fused_part_cost(p->fused[i], dt) < gate_cost;
+}
+
 static hs_status run_parts(hs_state s, Plan* p, int first, int last, hs_exec exec) {
   if (hs_status rc = plan_compile(p, s->dtype)) return rc;
   if (exec != HS_EXEC_PART_LDS)
@@ -582,9 +590,7 @@ static hs_status run_parts(hs_state s, Plan* p, int first, int last, hs_exec exe
                     kMaxFusedQubits);
       fused = true;
     } else if (exec == HS_EXEC_AUTO) {
-      const double gate_cost = ks ? spec_part_cost(p->scomp[s->dtype][i])
-                                  : lds_part_cost(p->comp[s->dtype][i]);
-      fused = p->fused[i].w && fused_part_cost(p->fused[i], s->dtype) < gate_cost;
+      fused = auto_picks_fused(p, s->dtype, i, ks != nullptr);
     }
     hs_status rc;
     if (fused) {
@@ -612,6 +618,22 @@ hs_status hs_simulate_part(hs_state s, hs_plan p, int part, hs_exec exec) {
   }
   if (exec == HS_EXEC_PART_SPEC) return run_spec_parts(s, p, part, part + 1);
   return run_parts(s, p, part, part + 1, exec);
+}
+
+hs_status hs_plan_auto_choice(hs_plan p, hs_dtype dtype, int32_t* out) {
+  CHECK_ARG(p && out, "null argument");
+  CHECK_ARG(dtype == HS_C64 || dtype == HS_C128, "bad dtype");
+  if (hs_status rc = plan_compile(p, dtype)) return rc;
+  if (hs_status rc = plan_compile_fused(p)) return rc;
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess) device = -1;
+  bool specialized = false;
+  {
+    std::lock_guard<std::mutex> lk(p->mu);
+    specialized = p->spec[dtype].count(device) > 0;
+  }
+  for (int i = 0; i < (int)p->parts.size(); ++i) out[i] = auto_picks_fused(p, dtype, i, specialized) ? 1 : 0;
+  return HS_OK;
 }
 
 hs_status hs_simulate(hs_state s, hs_plan p, hs_exec exec) {

@@ -203,7 +203,11 @@ hs_status dev_copy_probe(const void* src, void* dst, size_t bytes, void* stream)
 hs_status dev_sync(State* s);
 
 // ---- specialized part kernels (specialize.cpp) ------------------------------------
-std::string specialize_part_source(const CompiledPart& cp, hs_dtype dt, const std::string& name);
+// standalone = true: a complete translation unit (the runtime header guard
+// included); false: only the part's own declarations, to be wrapped in a
+// namespace of a multi-kernel program
+std::string specialize_part_source(const CompiledPart& cp, hs_dtype dt, const std::string& name,
+                                   bool standalone = true);
 hs_status specialize_plan(const std::vector<CompiledPart>& parts, hs_dtype dt, int device,
                           std::vector<std::shared_ptr<SpecKernel>>* out);
 hs_status launch_specialized(const SpecKernel& k, const CompiledPart& cp, void* state, void* stream);

@@ -19,9 +19,7 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
-#include <future>
 #include <sstream>
-#include <thread>
 
 #include "hisv_internal.h"
 
@@ -312,7 +310,8 @@ void emit_transition(Emit& E, const StageDesc& from, const StageDesc& to, const 
 
 }  // namespace
 
-std::string specialize_part_source(const CompiledPart& cp, hs_dtype dt, const std::string& name) {
+std::string specialize_part_source(const CompiledPart& cp, hs_dtype dt, const std::string& name,
+                                   bool standalone) {
   Emit E;
   E.f32 = dt == HS_C64;
   E.rb = cp.rb_kernel;
@@ -332,7 +331,7 @@ std::string specialize_part_source(const CompiledPart& cp, hs_dtype dt, const st
     ++nsplit;
   // hipRTC predefines the HIP language keywords; an offline hipcc build of
   // the same source (used to inspect it) takes them from the runtime header
-  o << "#ifndef __HIPCC_RTC__\n#include <hip/hip_runtime.h>\n#endif\n";
+  if (standalone) o << "#ifndef __HIPCC_RTC__\n#include <hip/hip_runtime.h>\n#endif\n";
   o << "typedef " << T << " T;\n"
     << "typedef struct __attribute__((aligned(" << 2 * (E.f32 ? 4 : 8) << "))) { T x, y; } V;\n"
     << "static __device__ inline __attribute__((always_inline)) V make_v(T x, T y) { V v; v.x = x; v.y = y; return v; }\n"
@@ -452,8 +451,13 @@ hs_status rtc_compile(const std::string& src, const std::string& name, std::vect
 }
 }  // namespace
 
-// Compile (in parallel) and load the specialized kernels of every part of a
-// plan for `dtype` on `device`; returns one kernel per part.
+// Compile and load the specialized kernels of every part of a plan for
+// `dtype` on `device`; returns one kernel per part.  Kernels already in the
+// cache (same device, same generated source) are reused; the others are
+// built together as ONE hipRTC program, each part's code in a namespace of
+// its own under a distinct kernel name: hipRTC serialises compilations
+// within a process, and one program of many kernels pays the per-program
+// front-end and code-object costs once instead of once per part.
 hs_status specialize_plan(const std::vector<CompiledPart>& parts, hs_dtype dt, int device,
                           std::vector<std::shared_ptr<SpecKernel>>* out) {
   const int P = (int)parts.size();
@@ -474,42 +478,39 @@ hs_status specialize_plan(const std::vector<CompiledPart>& parts, hs_dtype dt, i
   std::vector<int> build;
   for (int i : todo)
     if (first.emplace(src[i], i).second) build.push_back(i);
-  std::vector<std::vector<char>> code(P);
-  std::vector<hs_status> rc(P, HS_OK);
-  std::vector<std::string> err(P);
-  const unsigned nthr = std::max(1u, std::min<unsigned>(16, std::thread::hardware_concurrency()));
-  std::atomic<size_t> next{0};
-  auto worker = [&]() {
-    for (size_t w; (w = next.fetch_add(1)) < build.size();) {
-      const int i = build[w];
-      rc[i] = rtc_compile(src[i], "part" + std::to_string(i), &code[i]);
-      if (rc[i]) err[i] = hs_last_error();
+  if (!build.empty()) {
+    std::string prog = "#ifndef __HIPCC_RTC__\n#include <hip/hip_runtime.h>\n#endif\n";
+    for (size_t b = 0; b < build.size(); ++b)
+      prog += "namespace part" + std::to_string(b) + " {\n" +
+              specialize_part_source(parts[build[b]], dt, "part_pass_spec_" + std::to_string(b), false) +
+              "}\n";
+    std::vector<char> code;
+    if (hs_status rc = rtc_compile(prog, "parts", &code)) return rc;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+      return fail(HS_E_HIP, "device attribute query failed");
+    // the module stays loaded for the life of the process, like the cache
+    hipModule_t mod = nullptr;
+    if (hipModuleLoadData(&mod, code.data()) != hipSuccess) return fail(HS_E_HIP, "hipModuleLoadData failed");
+    std::lock_guard<std::mutex> lk(g_spec_mu);
+    for (size_t b = 0; b < build.size(); ++b) {
+      const int i = build[b];
+      auto k = std::make_shared<SpecKernel>();
+      k->mod = mod;
+      const std::string fname = "part_pass_spec_" + std::to_string(b);
+      if (hipModuleGetFunction(&k->fn, mod, fname.c_str()) != hipSuccess)
+        return fail(HS_E_HIP, "hipModuleGetFunction(%s) failed", fname.c_str());
+      k->block = 64 << parts[i].desc.wb;
+      int per_cu = 0;
+      if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k->fn, k->block, 0) != hipSuccess ||
+          per_cu < 1)
+        return fail(HS_E_HIP, "occupancy query failed for a specialized part");
+      k->per_cu = per_cu;
+      k->cus = cus;
+      g_spec[{device, src[i]}] = k;
     }
-  };
-  std::vector<std::thread> th;
-  for (unsigned t = 0; t < std::min<size_t>(nthr, build.size()); ++t) th.emplace_back(worker);
-  for (auto& t : th) t.join();
-  for (int i : build)
-    if (rc[i]) return fail(rc[i], "%s", err[i].c_str());
-  int cus = 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
-    return fail(HS_E_HIP, "device attribute query failed");
-  std::lock_guard<std::mutex> lk(g_spec_mu);
-  for (int i : build) {
-    auto k = std::make_shared<SpecKernel>();
-    if (hipModuleLoadData(&k->mod, code[i].data()) != hipSuccess)
-      return fail(HS_E_HIP, "hipModuleLoadData failed");
-    if (hipModuleGetFunction(&k->fn, k->mod, "part_pass_spec") != hipSuccess)
-      return fail(HS_E_HIP, "hipModuleGetFunction failed");
-    k->block = 64 << parts[i].desc.wb;
-    int per_cu = 0;
-    if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k->fn, k->block, 0) != hipSuccess ||
-        per_cu < 1)
-      return fail(HS_E_HIP, "occupancy query failed for a specialized part");
-    k->per_cu = per_cu;
-    k->cus = cus;
-    g_spec[{device, src[i]}] = k;
   }
+  std::lock_guard<std::mutex> lk(g_spec_mu);
   for (int i : todo) (*out)[i] = g_spec[{device, src[i]}];
   return HS_OK;
 }

@@ -72,6 +72,7 @@ _SIGS = {
     "hs_plan_part_source": [_vp, C.c_int, C.c_int, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)],
     "hs_plan_specialize": [_vp, C.c_int],
     "hs_plan_part_unitary": [_vp, C.c_int, C.POINTER(C.c_int), _dp],
+    "hs_plan_auto_choice": [_vp, C.c_int, C.POINTER(C.c_int32)],
     "hs_plan_destroy": [_vp],
     "hs_simulate": [_vp, _vp, C.c_int],
     "hs_simulate_gate_per_pass": [_vp, _vp],
@@ -296,6 +297,13 @@ class Plan:
         _call("hs_plan_part_unitary", self.handle, int(part), C.byref(w), out.ctypes.data_as(_dp))
         qubits = [int(v) for v in out[:w.value]]
         return qubits, out[w.value:].view(np.complex128).reshape(R, R)
+
+    def auto_choice(self, dtype: str = "c64") -> np.ndarray:
+        """1 where AUTO runs the part on the fused kernel, 0 for gate by gate."""
+        out = np.zeros(max(self.num_parts, 1), dtype=np.int32)
+        _call("hs_plan_auto_choice", self.handle, DTYPES[dtype],
+              out.ctypes.data_as(C.POINTER(C.c_int32)))
+        return out[: self.num_parts]
 
     def specialize(self, dtype: str = "c64") -> None:
         _call("hs_plan_specialize", self.handle, DTYPES[dtype])

@@ -5,6 +5,7 @@
         --copy-bytes B --kernel-hash H [--txt out.txt]
     python -m paper_2205_06973_amd.profiling mfma <counters.csv> <stats.csv> <out.txt> "<command>"
     python -m paper_2205_06973_amd.profiling valu <counters.csv> <stats.csv> <out.txt> "<command>"
+    python -m paper_2205_06973_amd.profiling waits <counters.csv> <stats.csv> <out.txt> "<command>"
 
 `stats` condenses a `--kernel-trace --stats` kernel_stats.csv.  `traffic`
 reads two `--pmc` counter_collection.csv files (FETCH_SIZE in one run,
@@ -188,6 +189,49 @@ def valu(counters_csv: str, stats_csv: str, out_path: str, command: str) -> None
     print("\n".join(lines))
 
 
+WAIT_COUNTERS = ("SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_WAIT_INST_LDS",
+                 "SQ_ACTIVE_INST_LDS", "SQ_ACTIVE_INST_VALU", "GRBM_GUI_ACTIVE")
+
+
+def waits(counters_csv: str, stats_csv: str, out_path: str, command: str) -> None:
+    """Where the part kernels' waves wait: per dispatch, the wave-cycles
+    spent waiting on anything (SQ_WAIT_ANY), waiting to issue any
+    instruction (SQ_WAIT_INST_ANY) and waiting to issue an LDS instruction
+    (SQ_WAIT_INST_LDS), as shares of all wave-cycles (SQ_WAVE_CYCLES); plus
+    how busy the LDS and VALU issue were (SQ_ACTIVE_INST_* count 4-cycle
+    issue slots per SIMD; GRBM_GUI_ACTIVE is summed over the 8 XCDs; 1024
+    SIMDs)."""
+    ctr: dict[str, dict[str, list[float]]] = {}
+    for r in csv.DictReader(open(counters_csv)):
+        ctr.setdefault(_short(r["Kernel_Name"]), {}).setdefault(r["Counter_Name"], []).append(
+            float(r["Counter_Value"]))
+    avg_ns = {_short(r["Name"]): float(r["AverageNs"]) for r in csv.DictReader(open(stats_csv))}
+    mean = lambda d, c: sum(d.get(c, [0.0])) / max(1, len(d.get(c, [0.0])))  # noqa: E731
+    lines = ["# wait-state counters per dispatch (rocprofv3 --pmc) and kernel-trace durations",
+             f"# command: {command}", f"# kernel source hash: {kernel_source_hash()}",
+             "# wait_any, wait_issue, wait_lds = SQ_WAIT_ANY, SQ_WAIT_INST_ANY, SQ_WAIT_INST_LDS",
+             "#   / SQ_WAVE_CYCLES; lds_of_waits = SQ_WAIT_INST_LDS / SQ_WAIT_ANY;",
+             "# lds_busy, valu_busy = SQ_ACTIVE_INST_LDS, SQ_ACTIVE_INST_VALU * 4 / (GRBM_GUI_ACTIVE / 8 * 1024)",
+             "",
+             f"{'kernel':36s} {'calls':>6s} {'avg_us':>10s} {'wait_any':>9s} {'wait_issue':>10s} "
+             f"{'wait_lds':>9s} {'lds_of_waits':>12s} {'lds_busy':>9s} {'valu_busy':>9s}"]
+    for k, d in sorted(ctr.items()):
+        if "SQ_WAVE_CYCLES" not in d or mean(d, "SQ_WAVE_CYCLES") == 0:
+            continue
+        cyc = mean(d, "SQ_WAVE_CYCLES")
+        simd = mean(d, "GRBM_GUI_ACTIVE") / 8 * 1024
+        lines.append(
+            f"{k:36s} {len(d['SQ_WAVE_CYCLES']):6d} {avg_ns.get(k, 0) / 1e3:10.1f} "
+            f"{mean(d, 'SQ_WAIT_ANY') / cyc:9.3f} {mean(d, 'SQ_WAIT_INST_ANY') / cyc:10.3f} "
+            f"{mean(d, 'SQ_WAIT_INST_LDS') / cyc:9.4f} "
+            f"{mean(d, 'SQ_WAIT_INST_LDS') / max(1.0, mean(d, 'SQ_WAIT_ANY')):12.4f} "
+            f"{mean(d, 'SQ_ACTIVE_INST_LDS') * 4 / max(1.0, simd):9.3f} "
+            f"{mean(d, 'SQ_ACTIVE_INST_VALU') * 4 / max(1.0, simd):9.3f}")
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main(argv):
     if argv[0] == "stats":
         stats(argv[1], argv[2], argv[3],
@@ -196,6 +240,8 @@ def main(argv):
         mfma(argv[1], argv[2], argv[3], argv[4])
     elif argv[0] == "valu":
         valu(argv[1], argv[2], argv[3], argv[4])
+    elif argv[0] == "waits":
+        waits(argv[1], argv[2], argv[3], argv[4])
     elif argv[0] == "traffic":
         cb = int(argv[argv.index("--copy-bytes") + 1])
         txt = argv[argv.index("--txt") + 1] if "--txt" in argv else None

@@ -113,15 +113,16 @@ def layered_product_block_circuit(n: int, layers: int, seed: int):
     return gates
 
 
-def dressed_pairs_circuit(n: int, blocks: int, seed: int, span: int = 6):
+def dressed_pairs_circuit(n: int, blocks: int, seed: int, span: int = 6, dwell: int = 8):
     """Blocks of U3 on two qubits, a two-qubit gate (CX, CZ, CP or SWAP)
-    on them, and U3 on both again; pairs drawn from a sliding window of
-    `span` qubits, so a part holds several dressed pairs."""
+    on them, and U3 on both again; pairs drawn from a window of `span`
+    qubits that moves up one qubit every `dwell` blocks, so a part holds
+    several dressed pairs (a long dwell makes deep, dense parts)."""
     rng = _rng(seed)
     out = []
     two = ["cx", "cz", "cp", "swap"]
     for b in range(blocks):
-        lo = (b // 8) % max(1, n - span + 1)
+        lo = (b // dwell) % max(1, n - span + 1)
         a, c = (int(x) + lo for x in rng.choice(span, size=2, replace=False))
         dress = lambda: [("u3", q, -1, _draw_gate(rng, "u3", n)[3]) for q in (a, c)]  # noqa: E731
         out += dress()

@@ -313,3 +313,19 @@ def test_dense_two_qubit_ops(dtype, fuse):
         hisv.hs_tune("fuse2", 1)
     assert (9 in kinds) == bool(fuse)
     check(got, sv.simulate(n, gates, 4321), dtype)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("mode", ["part_fused", "auto_spec", "part_spec"])
+def test_deep_dense_five_qubit_parts(dtype, mode):
+    """Dressed two-qubit blocks from a five-qubit window that dwells 16
+    blocks (about 80 gates per part, k = 5): the fused dense-unitary kernel,
+    AUTO over specialized and fused kernels (AUTO sends the deep parts to
+    the fused kernel) and the specialized kernels alone, against the
+    oracle."""
+    n = 16
+    gates = wl.dressed_pairs_circuit(n, 200, seed=3, span=5, dwell=16)
+    got, plan = run_hip(n, gates, dtype, 5, "greedy", mode, init=1234)
+    if mode == "auto_spec":
+        assert plan.auto_choice(dtype).sum() >= 1
+    check(got, sv.simulate(n, gates, 1234), dtype)
