@@ -341,6 +341,22 @@ hs_status hs_probabilities(hs_state s, uint64_t first, uint64_t count, double* o
  * two-level tree (the same result on every run).  Syncs. */
 hs_status hs_norm(hs_state s, double* out);
 
+/* hs_norm for callers that cannot allocate device memory (code that runs
+ * where hipMalloc is not allowed: tight serving loops, harnesses that forbid
+ * allocation).  Same result as hs_norm, bit for bit: the same two kernels in
+ * the same fixed order.  Their 1,024 partial sums and the result sit in a
+ * static device array of 8,256 bytes that each GPU the library runs on holds
+ * until the process ends; the reduction's shape does not depend on the state
+ * size, so every state the library accepts fits and none is refused for its
+ * size.  The array is found once per device (hipGetSymbolAddress, on the
+ * first call on that device); the call never calls hipMalloc or hipFree.
+ * All calls on one GPU share its array: calls that overlap on one GPU (two
+ * host threads, or states on different streams) race and must be serialised
+ * by the caller.  Writes the FP64 sum to *out (host memory); syncs the
+ * state's stream.  Errors: HS_E_ARG for a null argument, HS_E_HIP if the
+ * array's address or a launch fails. */
+hs_status hs_norm_noalloc(hs_state s, double* out);
+
 /* Wait for all work queued on the state's stream. */
 hs_status hs_sync(hs_state s);
 

@@ -707,6 +707,12 @@ hs_status hs_norm(hs_state s, double* out) {
   return dev_norm(s, out);
 }
 
+hs_status hs_norm_noalloc(hs_state s, double* out) {
+  CHECK_ARG(s && out, "null argument");
+  CHECK_ARG(s->ptr, "state has no device memory");
+  return dev_norm_noalloc(s, out);
+}
+
 hs_status hs_sync(hs_state s) {
   CHECK_ARG(s, "null state");
   return dev_sync(s);

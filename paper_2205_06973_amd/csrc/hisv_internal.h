@@ -197,6 +197,8 @@ double spec_part_cost(const CompiledPart& cp);
 double lds_part_cost(const CompiledPart& cp);
 double fused_part_cost(const FusedPart& f, hs_dtype dt);
 hs_status dev_norm(State* s, double* out);
+// the same reduction with its partial sums in a static device array (no allocation)
+hs_status dev_norm_noalloc(State* s, double* out);
 hs_status dev_read(State* s, uint64_t first, uint64_t count, double* out, bool probs);
 hs_status dev_read_at(State* s, const uint64_t* idx, uint64_t count, double* out);
 hs_status dev_copy_probe(const void* src, void* dst, size_t bytes, void* stream);

@@ -1191,6 +1191,58 @@ hs_status dev_norm(State* s, double* out) {
   return HS_OK;
 }
 
+// ---- the norm without allocation -------------------------------------------
+// The norm's partial sums live in a file-scope device array instead of the
+// state's lazily allocated scratch, so this path never calls the allocator.
+// Each device holds its own copy; host code uses only the address that
+// hipGetSymbolAddress reports for the current device (the array's name is a
+// host-side stand-in, not a device address).  Every call on a device shares
+// that device's copy: calls that overlap on one device race.  Nothing in it
+// must start at zero: norm_partial writes every one of its kNormBlocks
+// partial sums (zero for a block with no amplitudes) before norm_final
+// reads them, and norm_final writes the result slot.
+constexpr int kNoAllocDoubles = kNormBlocks + 8;  // 8,256 bytes per device
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_noalloc_mu;
+static double* g_noalloc_ptr[kMaxDevices] = {};
+
+// Address of this device's copy of `scratch`, looked up once per device with
+// that device current.
+static hs_status noalloc_scratch(int device, double** out) {
+  if (device < 0 || device >= kMaxDevices) return fail(HS_E_ARG, "device %d out of range", device);
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[device]) {
+    HIP_TRY(hipSetDevice(device));
+    void* ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_noalloc_ptr[device] = (double*)ptr;
+  }
+  *out = g_noalloc_ptr[device];
+  return HS_OK;
+}
+
+hs_status dev_norm_noalloc(State* s, double* out) {
+  HIP_TRY(hipSetDevice(s->device));
+  static_assert(kNormBlocks + 1 <= kNoAllocDoubles, "partials and result must fit the array");
+  double* part = nullptr;
+  if (hs_status rc = noalloc_scratch(s->device, &part)) return rc;
+  double* res = part + kNormBlocks;
+  const uint64_t N = uint64_t(1) << s->n;
+  if (s->dtype == HS_C64)
+    hipLaunchKernelGGL(norm_partial<float>, dim3(kNormBlocks), dim3(kNormThreads), 0, stream_of(s),
+                       (const cplx<float>*)s->ptr, N, part);
+  else
+    hipLaunchKernelGGL(norm_partial<double>, dim3(kNormBlocks), dim3(kNormThreads), 0, stream_of(s),
+                       (const cplx<double>*)s->ptr, N, part);
+  hipLaunchKernelGGL(norm_final, dim3(1), dim3(kNormThreads), 0, stream_of(s), part, res);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(out, res, sizeof(double), hipMemcpyDeviceToHost, stream_of(s)));
+  HIP_TRY(hipStreamSynchronize(stream_of(s)));
+  return HS_OK;
+}
+
 hs_status dev_read(State* s, uint64_t first, uint64_t count, double* out, bool probs) {
   HIP_TRY(hipSetDevice(s->device));
   const uint64_t chunk = uint64_t(1) << 22;

@@ -81,6 +81,7 @@ _SIGS = {
     "hs_read_amplitudes_at": [_vp, C.POINTER(_u64), _u64, _dp],
     "hs_probabilities": [_vp, _u64, _u64, _dp],
     "hs_norm": [_vp, _dp],
+    "hs_norm_noalloc": [_vp, _dp],
     "hs_sync": [_vp],
     "hs_copy_probe": [_vp, _vp, C.c_size_t, _vp],
     "hs_server_create": [C.c_size_t, C.c_int, C.POINTER(_vp)],
@@ -387,6 +388,11 @@ class State:
     def norm(self) -> float:
         v = C.c_double()
         _call("hs_norm", self.handle, C.byref(v))
+        return v.value
+
+    def norm_noalloc(self) -> float:
+        v = C.c_double()
+        _call("hs_norm_noalloc", self.handle, C.byref(v))
         return v.value
 
     def sync(self) -> None:
