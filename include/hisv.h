@@ -155,7 +155,12 @@ hs_status hs_device_count(int* out);
  * specialized kernels keeps the next tile's loads in flight;
  * "spec_lds_limit_kib" (16..160, default 64) = the specialized kernels run
  * each LDS re-layout in 2 or 4 rounds, over half or a quarter of the tile,
- * when the tile's LDS image is larger.  A "spec_"
+ * when the tile's LDS image is larger; "fused_shape" (-1..2, default -1) =
+ * launch shape of the fused kernels of 4- and 5-qubit parts: 0 = one group
+ * of tiles per workgroup, 1 = a persistent grid whose waves issue the next
+ * group's loads before the current group's products, 2 = a persistent grid
+ * of the plain kernel, -1 = the measured best for the width and precision.
+ * A "spec_"
  * prefix on a key sets it for the specialized kernels (PART_SPEC) instead of
  * the interpreter kernel ("contig" has no prefix: it applies to both).
  * HS_E_ARG for an unknown key or value. */
@@ -286,6 +291,24 @@ hs_status hs_plan_part_source(hs_plan p, int part, hs_dtype dtype, char* buf, si
  * source, so plans sharing parts share kernels.  HS_E_HIP with the compiler
  * log on failure. */
 hs_status hs_plan_specialize(hs_plan p, hs_dtype dtype);
+
+/* hs_plan_specialize on a host thread of the library: returns at once (after
+ * the part compile, so that a compile error is reported here).  While the
+ * kernels build, HS_EXEC_AUTO runs the plan's gate-by-gate parts on the
+ * interpreter kernel; once they are built it uses them.  A circuit run once
+ * therefore never waits for hipRTC, and one run many times moves to the
+ * specialized kernels after the build.  HS_EXEC_PART_SPEC waits for the build.
+ * The build's error, if any, is reported by hs_plan_specialize_wait;
+ * hs_plan_destroy waits for a build in progress. */
+hs_status hs_plan_specialize_async(hs_plan p, hs_dtype dtype);
+
+/* Wait for the background builds started on `p`; the first failure among them
+ * (HS_E_HIP with the compiler log) or HS_OK. */
+hs_status hs_plan_specialize_wait(hs_plan p, hs_dtype dtype);
+
+/* *ready = 1 if the plan's specialized kernels for `dtype` are built on the
+ * current device (HS_EXEC_AUTO then uses them), else 0. */
+hs_status hs_plan_specialized(hs_plan p, hs_dtype dtype, int* ready);
 
 /* The dense unitary U_p of a part as the fused path applies it: *w = the
  * number of qubits it acts on (4..7; parts of fewer than 4 qubits are

@@ -24,6 +24,8 @@ struct hs_plan_ : Plan {};
 namespace hisv {
 
 Plan::~Plan() {
+  for (std::thread& t : spec_threads)
+    if (t.joinable()) t.join();
   for (int d = 0; d < 2; ++d)
     for (auto& kv : dev[d]) device_plan_free(kv.second);
 }
@@ -45,6 +47,15 @@ static int g_min_tile[2] = {0, 0};             // [specialized]
 // Dense 4 x 4 ops: they save the interpreter's per-op dispatch and register
 // moves; the specialized kernels have neither, so they keep gate-sized ops.
 static bool g_fuse2[2] = {true, false};        // [specialized]
+// fused w = 4, 5 launch shape: 0 = one tile group per workgroup, 1 =
+// software-pipelined kernel on a persistent grid, 2 = plain kernel on a
+// persistent grid, -1 = the measured best per width and precision
+static int g_fused_shape = -1;
+
+int fused_launch_shape() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return g_fused_shape;
+}
 
 CompileOptions default_options(hs_dtype dtype, bool spec) {
   CompileOptions o;
@@ -179,6 +190,9 @@ hs_status hs_tune(const char* key, int value) {
   } else if (k == "fuse2") {
     CHECK_ARG(value == 0 || value == 1, "fuse2 must be 0 or 1");
     g_fuse2[spec] = value != 0;
+  } else if (k == "fused_shape" && !spec) {
+    CHECK_ARG(value >= -1 && value <= 2, "fused_shape must be -1, 0, 1 or 2");
+    g_fused_shape = value;
   } else if (k == "min_tile") {
     CHECK_ARG(value >= 0 && value <= 16, "min_tile must be 0..16");
     g_min_tile[spec] = value;
@@ -500,17 +514,26 @@ hs_status hs_plan_part_descriptors(hs_plan p, int part, hs_dtype dtype, hs_exec 
   return HS_OK;
 }
 
+// The plan's specialized kernels for `dtype` on `device`, built if need be.
+// The build runs under the plan's build lock only, so the interpreter and
+// AUTO keep launching parts (they take p->mu briefly) while hipRTC works.
 static hs_status ensure_spec(Plan* p, hs_dtype dtype, int device,
                              std::vector<std::shared_ptr<SpecKernel>>** out) {
   if (hs_status rc = plan_compile_spec(p, dtype)) return rc;
-  std::lock_guard<std::mutex> lk(p->mu);
-  auto it = p->spec[dtype].find(device);
-  if (it == p->spec[dtype].end()) {
-    std::vector<std::shared_ptr<SpecKernel>> ks;
-    if (hs_status rc = specialize_plan(p->scomp[dtype], dtype, device, &ks)) return rc;
-    it = p->spec[dtype].emplace(device, std::move(ks)).first;
+  std::lock_guard<std::mutex> build(p->spec_build_mu);
+  {
+    std::lock_guard<std::mutex> lk(p->mu);
+    auto it = p->spec[dtype].find(device);
+    if (it != p->spec[dtype].end()) {
+      *out = &it->second;
+      return HS_OK;
+    }
   }
-  *out = &it->second;
+  // scomp[dtype] no longer changes once compiled
+  std::vector<std::shared_ptr<SpecKernel>> ks;
+  if (hs_status rc = specialize_plan(p->scomp[dtype], dtype, device, &ks)) return rc;
+  std::lock_guard<std::mutex> lk(p->mu);
+  *out = &p->spec[dtype].emplace(device, std::move(ks)).first->second;
   return HS_OK;
 }
 
@@ -534,6 +557,58 @@ hs_status hs_plan_specialize(hs_plan p, hs_dtype dtype) {
   if (hipGetDevice(&dev) != hipSuccess) return fail(HS_E_HIP, "no HIP device");
   std::vector<std::shared_ptr<SpecKernel>>* ks = nullptr;
   return ensure_spec(p, dtype, dev, &ks);
+}
+
+hs_status hs_plan_specialize_async(hs_plan p, hs_dtype dtype) {
+  CHECK_ARG(p, "null plan");
+  CHECK_ARG(dtype == HS_C64 || dtype == HS_C128, "bad dtype");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(HS_E_HIP, "no HIP device");
+  // the descriptors first, on the caller's thread (host work, milliseconds),
+  // so that a compile error is reported here
+  if (hs_status rc = plan_compile_spec(p, dtype)) return rc;
+  std::lock_guard<std::mutex> lk(p->mu);
+  if (p->spec[dtype].count(dev)) return HS_OK;
+  p->spec_async_rc[dtype] = HS_OK;
+  p->spec_async_msg[dtype].clear();
+  Plan* plan = p;
+  p->spec_threads.emplace_back([plan, dtype, dev]() {
+    std::vector<std::shared_ptr<SpecKernel>>* ks = nullptr;
+    hs_status rc = hipSetDevice(dev) == hipSuccess ? ensure_spec(plan, dtype, dev, &ks)
+                                                   : fail(HS_E_HIP, "hipSetDevice failed");
+    if (rc != HS_OK) {
+      std::lock_guard<std::mutex> g(plan->mu);
+      plan->spec_async_rc[dtype] = rc;
+      plan->spec_async_msg[dtype] = hs_last_error();
+    }
+  });
+  return HS_OK;
+}
+
+hs_status hs_plan_specialize_wait(hs_plan p, hs_dtype dtype) {
+  CHECK_ARG(p, "null plan");
+  CHECK_ARG(dtype == HS_C64 || dtype == HS_C128, "bad dtype");
+  // join the background builds started so far (each joined by one caller)
+  std::vector<std::thread> ts;
+  {
+    std::lock_guard<std::mutex> lk(p->mu);
+    ts.swap(p->spec_threads);
+  }
+  for (std::thread& t : ts) t.join();
+  std::lock_guard<std::mutex> lk(p->mu);
+  if (p->spec_async_rc[dtype] != HS_OK)
+    return fail(p->spec_async_rc[dtype], "background build failed: %s", p->spec_async_msg[dtype].c_str());
+  return HS_OK;
+}
+
+hs_status hs_plan_specialized(hs_plan p, hs_dtype dtype, int* ready) {
+  CHECK_ARG(p && ready, "null argument");
+  CHECK_ARG(dtype == HS_C64 || dtype == HS_C128, "bad dtype");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(HS_E_HIP, "no HIP device");
+  std::lock_guard<std::mutex> lk(p->mu);
+  *ready = p->spec[dtype].count(dev) ? 1 : 0;
+  return HS_OK;
 }
 
 static hs_status run_spec_parts(hs_state s, Plan* p, int first, int last) {
@@ -568,7 +643,7 @@ static hs_status check_exec(hs_exec exec) {
 // and its cost (in HBM sweeps) is below the gate-by-gate kernel's -- the
 // specialized kernel's when the plan is specialized, else the interpreter's.
 static bool auto_picks_fused(Plan* p, hs_dtype dt, int i, bool specialized) {
-  const double gate_cost = specialized ? spec_part_cost(p->scomp[dt][i]) : lds_part_cost(p->comp[dt][i]);
+  const double gate_cost = specialized ? spec_part_cost(p->scomp[dt][i], dt) : lds_part_cost(p->comp[dt][i]);
   return p->fused[i].w && fused_part_cost(p->fused[i], dt) < gate_cost;
 }
 

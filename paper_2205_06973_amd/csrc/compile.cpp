@@ -540,37 +540,37 @@ double lds_part_cost(const CompiledPart& cp) {
   return c;
 }
 
-// The specialized kernels keep the sweep near the HBM rate: on the same
-// 30..34-qubit measurements an LDS re-layout costs about 0.03 sweep and the
-// register operations about a third of their interpreter cost.
-double spec_part_cost(const CompiledPart& cp) {
-  static const double op_cost[OP_NUM] = {0.066, 0.035, 0.038, 0.025, 0.01,
-                                         0.007, 0.007, 0.012, 0.01};
-  double c = 1.0 + 0.03 * cp.lds_round_trips;
-  for (const HostOp& op : cp.ops) c += op_cost[op.kind] / 3.0;
-  return c;
+// The specialized kernels keep the sweep near the HBM rate while a part's
+// arithmetic is light: an LDS re-layout costs about 0.03 sweep, and
+// register permutations (X, CX, SWAP) are free (compile-time renames).
+// Heavier parts become vector-ALU bound.  Per-part timings of 30-qubit
+// states (random, layered and dressed-pair circuits, both precisions) fit
+// a smooth maximum of the sweep and 0.0045 sweep per flop per amplitude
+// (Sec. III.A's counting: a dense 2 x 2 is 14 flops per amplitude): flat at
+// ~1.1 sweeps below ~200 flops per amplitude, 1.6-1.7 at 350, 2.1-2.3 at
+// 500, 4.2-4.8 at 1,000.
+double spec_part_cost(const CompiledPart& cp, hs_dtype dt) {
+  static const double flops[OP_NUM] = {14, 6, 6, 3, 0, 0, 0.5, 1.5, 0, 30};
+  const double mem = (dt == HS_C64 ? 1.05 : 1.0) + 0.03 * cp.lds_round_trips;
+  double f = 0;
+  for (const HostOp& op : cp.ops) f += flops[op.kind];
+  const double alu = 0.0045 * f;
+  return std::sqrt(std::sqrt(mem * mem * mem * mem + alu * alu * alu * alu));
 }
 
 // The fused kernel does 8 * 2^w flops per amplitude on matrix cores against
-// 2 * s bytes of HBM traffic (s = 8 or 16 bytes per amplitude).  At the
-// FP32 / FP64 matrix peaks (157.3 / 78.6 TFLOP/s) against ~6 TB/s that is
-// about 0.02 * 2^w sweeps for either precision: w = 6 and 7 are matrix-core
-// bound (2.2 / 4.0 sweeps measured on a 32-qubit QFT, 2.15 for w = 6 on a
-// 28-qubit state).  w <= 5 should stay HBM-bound, but measured 1.05 / 1.2
-// sweeps on 34-qubit states and 1.6 / 1.76 on 28-qubit ones; the larger
-// figures are used, so AUTO takes these widths only where the gate-by-gate
-// kernels are clearly slower.  When the part holds one of qubits 0..3 the
-// 16 columns of a wave are not one contiguous run: ~1.7-1.85 sweeps.
+// 2 * s bytes of HBM traffic (s = 8 or 16 bytes per amplitude).  Per-part timings on
+// 30-qubit states (random, layered and dressed-pair circuits), in sweeps:
+// w = 6 and 7 are matrix-core bound; w <= 5 overlap their loads with the
+// products only in part.  Complex64 parts that hold one of qubits 0..3 (the
+// 16 columns of a wave are then not one contiguous run) cost ~0.1 more.
 double fused_part_cost(const FusedPart& f, hs_dtype dt) {
-  (void)dt;
+  static const double c64[8] = {0, 0, 0, 0, 1.17, 1.29, 2.13, 3.37};
+  static const double c128[8] = {0, 0, 0, 0, 1.10, 1.25, 1.69, 2.92};
+  if (f.w < 4 || f.w > 7) return 1e30;
   const bool coalesced = f.pq[0] == 0 && f.pq[1] == 1 && f.pq[2] == 2 && f.pq[3] == 3;
-  switch (f.w) {
-    case 4: return coalesced ? 1.6 : 1.75;
-    case 5: return coalesced ? 1.76 : 1.85;
-    case 6: return 2.2;
-    case 7: return 4.0;
-    default: return 1e30;
-  }
+  if (dt == HS_C64) return c64[f.w] + (coalesced ? 0.0 : 0.1);
+  return c128[f.w];
 }
 
 }  // namespace hisv

@@ -7,6 +7,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <thread>
 #include <string>
 #include <vector>
 
@@ -154,6 +155,12 @@ struct Plan {
   std::vector<CompiledPart> scomp[2];   // for the specialized kernels
   std::map<int, DevicePlan*> dev[2];
   std::map<int, std::vector<std::shared_ptr<SpecKernel>>> spec[2];  // per device
+  // one kernel build at a time per plan (held across the hipRTC build; the
+  // maps above are guarded by mu alone, so launches never wait for a build)
+  std::mutex spec_build_mu;
+  std::vector<std::thread> spec_threads;  // background builds, joined by ~Plan
+  hs_status spec_async_rc[2] = {HS_OK, HS_OK};
+  std::string spec_async_msg[2];
   bool fused_built = false;
   std::vector<FusedPart> fused;  // w = 0 where a part has no fused form
   ~Plan();
@@ -192,8 +199,11 @@ hs_status dev_run_part(State* s, Plan* p, int part);
 hs_status dev_plan_upload_async(Plan* p, hs_dtype dtype, int device, void* stream);
 hs_status dev_run_fused(State* s, Plan* p, int part);
 hs_status plan_compile_fused(Plan* p);
+// hs_tune("fused_shape"): the fused w = 4, 5 kernels' launch shape, read when
+// a plan's fused descriptors are uploaded
+int fused_launch_shape();
 // relative cost (one HBM sweep = 1) of a part on each path, for AUTO
-double spec_part_cost(const CompiledPart& cp);
+double spec_part_cost(const CompiledPart& cp, hs_dtype dt);
 double lds_part_cost(const CompiledPart& cp);
 double fused_part_cost(const FusedPart& f, hs_dtype dt);
 hs_status dev_norm(State* s, double* out);

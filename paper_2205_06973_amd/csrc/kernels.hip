@@ -58,11 +58,18 @@ __device__ __forceinline__ void for_pair(int b0, int b1, F&& f) {
   });
 }
 
-// A lane's 2^RB amplitudes live in one vector value (re at 2j, im at 2j+1):
-// every access below is an element of an SSA value with a compile-time
-// index, so the whole sub-state stays in VGPRs.
+// A lane's 2^RB amplitudes (re at 2j, im at 2j+1).  Every access below has
+// a compile-time index, so the array is split into independent scalars that
+// stay in VGPRs.  (A vector value did the same but must occupy one
+// contiguous register range, which cost extra register copies per op:
+// 1,643 against 1,109 moves in the complex64 kernel, 2.4% on a 28-qubit
+// layered circuit.)
 template <typename T, int RB>
-using RegV = T __attribute__((ext_vector_type(2 << RB)));
+struct RegV {
+  T v[2 << RB];
+  __device__ __forceinline__ T& operator[](int i) { return v[i]; }
+  __device__ __forceinline__ const T& operator[](int i) const { return v[i]; }
+};
 
 template <typename T, int RB, int B>
 __device__ __forceinline__ void r_u(RegV<T, RB>& a, const T* __restrict__ c) {
@@ -398,6 +405,9 @@ part_pass_kernel(cplx<T>* __restrict__ st, const IPart* __restrict__ pd,
 // other qubits, so column runs are contiguous -- and computes the complex
 // product as four real products on 16x16x4 MFMA tiles:
 //   Yr = Ur Xr - Ui Xi,  Yi = Ur Xi + Ui Xr.
+// (Gauss's three-product form, T3 = (Ur + Ui)(Xr + Xi), measured no faster
+// for w = 4, 5 on 30-qubit states: those widths wait on memory, not on the
+// matrix cores.)
 // Operand layouts of the 16x16x4 MFMA (64 lanes, l = lane):
 //   A[i][k]: i = l % 16, k = l / 16;   B[k][j]: j = l % 16, k = l / 16;
 //   D[i][j] (4 registers v): j = l % 16 and
@@ -431,8 +441,9 @@ __device__ __forceinline__ uint64_t deposit(uint32_t v, const int8_t* q, int cou
 // U arrives in fragment order: fragment f = rb * (2^w / 4) + ks holds, in lane
 // l, U[16 rb + l % 16][4 ks + l / 16]; the real parts of all fragments come
 // first, then the imaginary parts.  For w <= 5 a wave keeps all of U in
-// registers; wider U (64x64, 128x128) is read fragment by fragment from the
-// L2-resident copy -- one contiguous 256-byte wave load per fragment.  In
+// registers (complex128 at w = 5 excepted); wider U (64x64, 128x128) is read
+// fragment by fragment from the L2-resident copy -- one contiguous wave load
+// per fragment.  In
 // FP32 a wave then takes two tiles (32 columns) so that each fragment feeds
 // eight matrix-core products, halving the L2 traffic for U.
 template <typename T, int W>
@@ -440,7 +451,7 @@ constexpr int fused_tiles_per_wave() {
   return (W >= 6 && sizeof(T) == 4) ? 2 : 1;
 }
 
-template <typename T, int W>
+template <typename T, int W, bool PIPE>
 __global__ void __launch_bounds__(256)
 fused_pass_kernel(cplx<T>* __restrict__ st, const FusedDesc* __restrict__ fd, const T* __restrict__ umat,
                   uint32_t xcd) {
@@ -449,7 +460,10 @@ fused_pass_kernel(cplx<T>* __restrict__ st, const FusedDesc* __restrict__ fd, co
   constexpr int RBK = R / 16; // 16-row blocks
   constexpr int KS = R / 4;   // K steps of 4
   constexpr int NF = RBK * KS;
-  constexpr bool kRegU = W <= 5;
+  // U in registers for w <= 5, except complex128 at w = 5 (96 more VGPRs:
+  // one wave per SIMD), which reads U from the L1/L2-resident copy instead
+  constexpr bool kRegU = W <= 4 || (W == 5 && sizeof(T) == 4);
+  constexpr bool kPipe = PIPE && W <= 5;  // software-pipelined (see below)
   constexpr int CG = fused_tiles_per_wave<T, W>();
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t i16 = lane & 15, g4 = lane >> 4;
@@ -470,17 +484,46 @@ fused_pass_kernel(cplx<T>* __restrict__ st, const FusedDesc* __restrict__ fd, co
         nui[rb][ks] = -ui[rb][ks];
       }
   }
+  // The qubit lists (sq[8], pq[4], tq[12]: 24 bytes from offset 24 of the
+  // descriptor) as six uniform dwords, read once: byte loads inside the tile
+  // loop would be vector loads followed by a full wait on every memory
+  // operation in flight, prefetched tiles and stores included.
+  uint32_t qw[6];
+  {
+    const uint32_t* q32 = reinterpret_cast<const uint32_t*>(fd->sq);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) qw[i] = __builtin_amdgcn_readfirstlane(q32[i]);
+  }
+  // qubit of list byte b (sq: 0-7, pq: 8-11, tq: 12-23); b is a constant
+  auto qb = [&](int b) -> int { return (int)(int8_t)(qw[b >> 2] >> (8 * (b & 3))); };
+  // deposit the low `count` bits of v onto the qubits of bytes first..
+  auto dep = [&](uint32_t v, int first, int count) -> uint64_t {
+    uint64_t g = 0;
+#pragma unroll
+    for (int b = 0; b < count; ++b) g |= uint64_t((v >> b) & 1u) << qb(first + b);
+    return g;
+  };
+  // base index of a tile: a zero bit inserted at every tile qubit (ascending)
+  auto base_of = [&](uint64_t t) -> uint64_t {
+#pragma unroll
+    for (int i = 0; i < 12; ++i)
+      if (i < m) {
+        const int q = qb(12 + i);
+        t = ((t >> q) << (q + 1)) | (t & ((uint64_t(1) << q) - 1));
+      }
+    return t;
+  };
   // lane parts of the addresses: B rows k = 4*ks + g4 (slots 0-1 from the
   // lane); D rows i = 16*rb + 4*g4 + v (FP32: slots 2-3 from the lane) or
   // 16*rb + 4*v + g4 (FP64: slots 0-1 from the lane); columns j = i16 on
   // the column qubits
   constexpr bool f64 = sizeof(T) == 8;
-  const uint64_t col = deposit(i16, fd->pq, 4);
-  const uint64_t lane_ld = col + deposit(g4, fd->sq, 2);
-  const uint64_t lane_st = f64 ? lane_ld : col + deposit(g4 << 2, fd->sq, W);
+  const uint64_t col = dep(i16, 8, 4);
+  const uint64_t lane_ld = col + dep(g4, 0, 2);
+  const uint64_t lane_st = f64 ? lane_ld : col + dep(g4 << 2, 0, W);
   uint64_t row_ld[KS];
 #pragma unroll
-  for (int ks = 0; ks < KS; ++ks) row_ld[ks] = deposit(4 * ks, fd->sq, W);
+  for (int ks = 0; ks < KS; ++ks) row_ld[ks] = dep(4 * ks, 0, W);
   // a workgroup's 4 waves take 4 * CG consecutive tiles; with xcd set (grid
   // and group count multiples of 8) XCD x = blockIdx % 8 sweeps a contiguous
   // run
@@ -493,24 +536,34 @@ fused_pass_kernel(cplx<T>* __restrict__ st, const FusedDesc* __restrict__ fd, co
     step = gridDim.x >> 3;
     end = (x + 1) * per;
   }
-  for (; g < end; g += step) {
-    const uint64_t tile0 = (g * 4 + (threadIdx.x >> 6)) * CG;
-    if (tile0 >= tiles) continue;
-    uint64_t base[CG];
-    bool valid[CG];
-    T xr[CG][KS], xi[CG][KS];
+  // wave-uniform: tile indices, bases and the valid flags stay in scalar
+  // registers (address arithmetic on the SALU, stores under a scalar branch)
+  const uint64_t wave_tile = (uint64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * CG;
+  // X of this wave's tiles in group gg (zero columns past the last tile)
+  // (branch-free: a wave past the last tile reads tile 0 and discards its
+  // products, so no load sits in a conditional block or feeds a select --
+  // either would make the wave wait for the load right away)
+  // tiles is a power of two (2^(n-m)): a tile index is in range when no bit
+  // at or above log2(tiles) is set -- a 64-bit test the scalar unit has (it
+  // has no 64-bit ordered compare)
+  const uint64_t past = ~(tiles - 1);
+  auto load = [&](uint64_t gg, T (&xr)[CG][KS], T (&xi)[CG][KS], uint64_t (&base)[CG], bool (&valid)[CG]) {
+    const uint64_t tile0 = gg * 4 * CG + wave_tile;
 #pragma unroll
     for (int c = 0; c < CG; ++c) {
-      valid[c] = tile0 + c < tiles;
-      base[c] = valid[c] ? tile_base(tile0 + c, fd->tq, m) : 0;
+      valid[c] = ((tile0 + c) & past) == 0;
+      base[c] = base_of(valid[c] ? tile0 + c : 0);
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
-        cplx<T> v = {0, 0};
-        if (valid[c]) v = st[base[c] + row_ld[ks] + lane_ld];
+        const cplx<T> v = st[base[c] + row_ld[ks] + lane_ld];
         xr[c][ks] = v.x;
         xi[c][ks] = v.y;
       }
     }
+  };
+  // Y = U X on the matrix cores, stored in place
+  auto product = [&](const T (&xr)[CG][KS], const T (&xi)[CG][KS], const uint64_t (&base)[CG],
+                     const bool (&valid)[CG]) {
     constexpr int kRbUnroll = kRegU ? RBK : 1;
 #pragma unroll kRbUnroll
     for (int rb = 0; rb < RBK; ++rb) {
@@ -549,9 +602,40 @@ fused_pass_kernel(cplx<T>* __restrict__ st, const FusedDesc* __restrict__ fd, co
           cplx<T> o;
           o.x = yr[c][v];
           o.y = yi[c][v];
-          st[base[c] + deposit(16 * rb + (f64 ? 4 * v : v), fd->sq, W) + lane_st] = o;
+          st[base[c] + dep(16 * rb + (f64 ? 4 * v : v), 0, W) + lane_st] = o;
         }
       }
+    }
+  };
+  T xr[CG][KS], xi[CG][KS];
+  uint64_t base[CG];
+  bool valid[CG];
+  if (kPipe) {
+    // w <= 5: a persistent grid, software-pipelined per wave -- the next
+    // group's loads are issued before this group's products, so each wave
+    // overlaps its own HBM traffic with its matrix-core work (loads, products
+    // and stores of one tile would otherwise run as three serial phases).
+    // Two register sets alternate (no copies between iterations, which
+    // would wait for the loads), and the loads are unconditional: past the
+    // end a wave re-reads its current group, whose products it discards.
+    T yr2[CG][KS], yi2[CG][KS];
+    uint64_t base2[CG];
+    bool valid2[CG];
+    if (g < end) load(g, xr, xi, base, valid);
+    while (g < end) {
+      const uint64_t g1 = g + step;
+      load(g1 < end ? g1 : g, yr2, yi2, base2, valid2);
+      product(xr, xi, base, valid);
+      if (g1 >= end) break;
+      const uint64_t g2 = g1 + step;
+      load(g2 < end ? g2 : g1, xr, xi, base, valid);
+      product(yr2, yi2, base2, valid2);
+      g = g2;
+    }
+  } else {
+    for (; g < end; g += step) {
+      load(g, xr, xi, base, valid);
+      product(xr, xi, base, valid);
     }
   }
 }
@@ -844,6 +928,7 @@ struct DevicePlan {
   std::vector<FusedDesc> h_fparts;
   std::vector<unsigned> fgrid;
   std::vector<uint8_t> fxcd;
+  std::vector<uint8_t> fpipe;  // software-pipelined kernel (persistent grid)
 };
 
 // Best effort: called from destructors, where an error cannot be returned.
@@ -1108,6 +1193,30 @@ static hs_status upload_fused(Plan* p, DevicePlan* dp) {
     }
     const uint64_t groups = (f.tiles + per_wg - 1) / per_wg;
     uint64_t g = std::max<uint64_t>(1, std::min<uint64_t>(groups, (uint64_t(1) << 31) / 256));
+    // w = 4, 5: launch shape from hs_tune("fused_shape"): 0 = one tile group
+    // per workgroup; 1 = software-pipelined kernel, 2 = plain kernel, each
+    // on a persistent grid of as many workgroups as the device keeps
+    // resident (U is then read once per workgroup, not once per group).
+    // By default (-1) the measured best per width and precision: on 30-qubit
+    // states the persistent plain kernel for complex64 w = 5 (1.31 sweeps
+    // against 1.40), one group per workgroup otherwise (complex64 w = 4:
+    // 1.13-1.23 against 1.28-1.32; complex128 w = 4 / 5: 0.93-1.09 / 1.19-1.21
+    // against 1.02-1.19 / 1.22-1.27).
+    int shape = (f.w == 4 || f.w == 5) ? fused_launch_shape() : 0;
+    if (shape < 0) shape = (sizeof(T) == 4 && f.w == 5) ? 2 : 0;
+    if (shape) {
+      int per_cu = 0;
+      const void* fn = nullptr;
+      if (f.w == 4)
+        fn = shape == 1 ? (const void*)fused_pass_kernel<T, 4, true> : (const void*)fused_pass_kernel<T, 4, false>;
+      else
+        fn = shape == 1 ? (const void*)fused_pass_kernel<T, 5, true> : (const void*)fused_pass_kernel<T, 5, false>;
+      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0));
+      DevInfo di;
+      if (hs_status rc = device_info(dp->device, &di)) return rc;
+      g = std::max<uint64_t>(1, std::min<uint64_t>(g, (uint64_t)std::max(1, per_cu) * di.cus));
+    }
+    dp->fpipe.push_back(shape == 1 ? 1 : 0);
     uint8_t x = 0;
     if (groups % 8 == 0 && g >= 8) {
       g &= ~uint64_t(7);
@@ -1136,11 +1245,18 @@ static hs_status launch_fused(State* s, DevicePlan* dp, int part) {
   hipStream_t str = stream_of(s);
   const dim3 grid(dp->fgrid[part]);
   const uint32_t xcd = dp->fxcd[part];
+  const bool pipe = dp->fpipe[part] != 0;
   switch (d.w) {
-    case 4: hipLaunchKernelGGL((fused_pass_kernel<T, 4>), grid, dim3(256), 0, str, st, fd, um, xcd); break;
-    case 5: hipLaunchKernelGGL((fused_pass_kernel<T, 5>), grid, dim3(256), 0, str, st, fd, um, xcd); break;
-    case 6: hipLaunchKernelGGL((fused_pass_kernel<T, 6>), grid, dim3(256), 0, str, st, fd, um, xcd); break;
-    case 7: hipLaunchKernelGGL((fused_pass_kernel<T, 7>), grid, dim3(256), 0, str, st, fd, um, xcd); break;
+    case 4:
+      if (pipe) hipLaunchKernelGGL((fused_pass_kernel<T, 4, true>), grid, dim3(256), 0, str, st, fd, um, xcd);
+      else hipLaunchKernelGGL((fused_pass_kernel<T, 4, false>), grid, dim3(256), 0, str, st, fd, um, xcd);
+      break;
+    case 5:
+      if (pipe) hipLaunchKernelGGL((fused_pass_kernel<T, 5, true>), grid, dim3(256), 0, str, st, fd, um, xcd);
+      else hipLaunchKernelGGL((fused_pass_kernel<T, 5, false>), grid, dim3(256), 0, str, st, fd, um, xcd);
+      break;
+    case 6: hipLaunchKernelGGL((fused_pass_kernel<T, 6, false>), grid, dim3(256), 0, str, st, fd, um, xcd); break;
+    case 7: hipLaunchKernelGGL((fused_pass_kernel<T, 7, false>), grid, dim3(256), 0, str, st, fd, um, xcd); break;
     default: return fail(HS_E_UNSUPPORTED, "part %d has no fused form", part);
   }
   HIP_TRY(hipGetLastError());

@@ -71,6 +71,9 @@ _SIGS = {
                                  C.c_int],
     "hs_plan_part_source": [_vp, C.c_int, C.c_int, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)],
     "hs_plan_specialize": [_vp, C.c_int],
+    "hs_plan_specialize_async": [_vp, C.c_int],
+    "hs_plan_specialize_wait": [_vp, C.c_int],
+    "hs_plan_specialized": [_vp, C.c_int, C.POINTER(C.c_int)],
     "hs_plan_part_unitary": [_vp, C.c_int, C.POINTER(C.c_int), _dp],
     "hs_plan_auto_choice": [_vp, C.c_int, C.POINTER(C.c_int32)],
     "hs_plan_destroy": [_vp],
@@ -308,6 +311,17 @@ class Plan:
 
     def specialize(self, dtype: str = "c64") -> None:
         _call("hs_plan_specialize", self.handle, DTYPES[dtype])
+
+    def specialize_async(self, dtype: str = "c64") -> None:
+        _call("hs_plan_specialize_async", self.handle, DTYPES[dtype])
+
+    def specialize_wait(self, dtype: str = "c64") -> None:
+        _call("hs_plan_specialize_wait", self.handle, DTYPES[dtype])
+
+    def specialized(self, dtype: str = "c64") -> bool:
+        r = C.c_int()
+        _call("hs_plan_specialized", self.handle, DTYPES[dtype], C.byref(r))
+        return bool(r.value)
 
     def close(self):
         if self.handle:

@@ -6,6 +6,7 @@
     python -m paper_2205_06973_amd.profiling mfma <counters.csv> <stats.csv> <out.txt> "<command>"
     python -m paper_2205_06973_amd.profiling valu <counters.csv> <stats.csv> <out.txt> "<command>"
     python -m paper_2205_06973_amd.profiling waits <counters.csv> <stats.csv> <out.txt> "<command>"
+    python -m paper_2205_06973_amd.profiling runs <kernel_trace.csv> <bench.json> <out.txt> "<command>"
 
 `stats` condenses a `--kernel-trace --stats` kernel_stats.csv.  `traffic`
 reads two `--pmc` counter_collection.csv files (FETCH_SIZE in one run,
@@ -43,7 +44,9 @@ def kernel_source_hash() -> str:
 
 def _short(name: str) -> str:
     base = name.split("(")[0]
-    for tag in ("part_pass_spec", "part_pass_kernel", "fused_pass_kernel", "gate_pass_1q",
+    if "part_pass_spec" in base:  # one kernel per part (part_pass_spec_<i>): one row
+        return "part_pass_spec"
+    for tag in ("part_pass_kernel", "fused_pass_kernel", "gate_pass_1q",
                 "gate_pass_2q", "set_basis_kernel", "norm_partial", "norm_final", "readout_kernel",
                 "gather_kernel", "copy_probe_kernel"):
         if tag in base:
@@ -60,13 +63,32 @@ def stats(csv_path: str, out_path: str, command: str, khash: str | None = None) 
         lines.append(f"# kernel hash (generated part kernels): {khash}")
     lines += ["",
              f"{'kernel':48s} {'calls':>7s} {'avg_us':>11s} {'min_us':>11s} {'max_us':>11s} {'total_ms':>11s} {'pct':>6s}"]
+    # rows with the same short name (the per-part specialized kernels) merge
+    agg: dict[str, list[float]] = {}
     for r in rows:
-        lines.append(f"{_short(r['Name']):48s} {int(r['Calls']):7d} {float(r['AverageNs'])/1e3:11.2f} "
-                     f"{float(r['MinNs'])/1e3:11.2f} {float(r['MaxNs'])/1e3:11.2f} "
-                     f"{float(r['TotalDurationNs'])/1e6:11.2f} {float(r['Percentage']):6.2f}")
+        a = agg.setdefault(_short(r["Name"]), [0, 0.0, float("inf"), 0.0, 0.0])
+        a[0] += int(r["Calls"])
+        a[1] += float(r["TotalDurationNs"])
+        a[2] = min(a[2], float(r["MinNs"]))
+        a[3] = max(a[3], float(r["MaxNs"]))
+        a[4] += float(r["Percentage"])
+    for k, (calls, tot, mn, mx, pct) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+        lines.append(f"{k:48s} {calls:7d} {tot / calls / 1e3:11.2f} {mn / 1e3:11.2f} {mx / 1e3:11.2f} "
+                     f"{tot / 1e6:11.2f} {pct:6.2f}")
     with open(out_path, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
+
+
+def _avg_ns(stats_csv: str) -> dict[str, float]:
+    """Average duration per short kernel name (call-weighted over the rows a
+    short name merges, such as the per-part specialized kernels)."""
+    tot: dict[str, list[float]] = {}
+    for r in csv.DictReader(open(stats_csv)):
+        t = tot.setdefault(_short(r["Name"]), [0.0, 0])
+        t[0] += float(r["TotalDurationNs"])
+        t[1] += int(r["Calls"])
+    return {k: v[0] / v[1] for k, v in tot.items() if v[1]}
 
 
 def _counter_per_kernel(path: str, counter: str) -> dict[str, list[float]]:
@@ -128,7 +150,7 @@ def mfma(counters_csv: str, stats_csv: str, out_path: str, command: str) -> None
     for r in csv.DictReader(open(counters_csv)):
         ctr.setdefault(_short(r["Kernel_Name"]), {}).setdefault(r["Counter_Name"], []).append(
             float(r["Counter_Value"]))
-    avg_ns = {_short(r["Name"]): float(r["AverageNs"]) for r in csv.DictReader(open(stats_csv))}
+    avg_ns = _avg_ns(stats_csv)
     peak = {"F32": 157.3, "F64": 78.6}
     lines = ["# matrix-core counters per dispatch (rocprofv3 --pmc) and kernel-trace durations",
              f"# command: {command}", f"# kernel source hash: {kernel_source_hash()}",
@@ -168,7 +190,7 @@ def valu(counters_csv: str, stats_csv: str, out_path: str, command: str) -> None
     for r in csv.DictReader(open(counters_csv)):
         ctr.setdefault(_short(r["Kernel_Name"]), {}).setdefault(r["Counter_Name"], []).append(
             float(r["Counter_Value"]))
-    avg_ns = {_short(r["Name"]): float(r["AverageNs"]) for r in csv.DictReader(open(stats_csv))}
+    avg_ns = _avg_ns(stats_csv)
     lines = ["# vector-ALU counters per dispatch (rocprofv3 --pmc) and kernel-trace durations",
              f"# command: {command}", f"# kernel source hash: {kernel_source_hash()}",
              "# arith = FMA + MUL instructions (F32 or F64) / all VALU instructions;",
@@ -205,7 +227,7 @@ def waits(counters_csv: str, stats_csv: str, out_path: str, command: str) -> Non
     for r in csv.DictReader(open(counters_csv)):
         ctr.setdefault(_short(r["Kernel_Name"]), {}).setdefault(r["Counter_Name"], []).append(
             float(r["Counter_Value"]))
-    avg_ns = {_short(r["Name"]): float(r["AverageNs"]) for r in csv.DictReader(open(stats_csv))}
+    avg_ns = _avg_ns(stats_csv)
     mean = lambda d, c: sum(d.get(c, [0.0])) / max(1, len(d.get(c, [0.0])))  # noqa: E731
     lines = ["# wait-state counters per dispatch (rocprofv3 --pmc) and kernel-trace durations",
              f"# command: {command}", f"# kernel source hash: {kernel_source_hash()}",
@@ -232,6 +254,34 @@ def waits(counters_csv: str, stats_csv: str, out_path: str, command: str) -> Non
     print("\n".join(lines))
 
 
+def runs(trace_csv: str, bench_json: str, out_path: str, command: str, kernel: str = "gate_pass_1q",
+         per_case: int = 16) -> None:
+    """Per-case durations of a kernel from a --kernel-trace run of
+    `bench.py --streaming-only`: its dispatches, in order, split into runs of
+    `per_case` (the sweeps of one state size), matched with the bench's
+    streaming rows (n, dtype) and their algorithmic bytes per sweep."""
+    rows = [r for r in csv.DictReader(open(trace_csv)) if _short(r["Kernel_Name"]).startswith(kernel)]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    dur = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows]
+    with open(bench_json) as f:
+        cases = json.loads(f.read().strip().splitlines()[-1])["streaming"]
+    lines = [f"# per-size durations of {kernel} (rocprofv3 --kernel-trace), one sweep = H on qubit 0",
+             f"# command: {command}", f"# kernel source hash: {kernel_source_hash()}",
+             f"# {len(dur)} dispatches in {per_case}-dispatch runs (8 warm + 8 timed per size)", "",
+             f"{'n':>3s} {'dtype':>6s} {'avg_us':>10s} {'GB/s':>9s} {'frac':>6s} {'bench_GB/s':>11s}"]
+    for i, c in enumerate(cases):
+        run = dur[i * per_case:(i + 1) * per_case]
+        if not run:
+            break
+        avg = sum(run) / len(run)
+        b = 2 * (1 << c["n"]) * (8 if c["dtype"] == "c64" else 16)
+        lines.append(f"{c['n']:3d} {c['dtype']:>6s} {avg:10.1f} {b / avg / 1e3:9.1f} {b / avg / 1e3 / 8000:6.3f} "
+                     f"{c['pass_GBps']:11.1f}")
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main(argv):
     if argv[0] == "stats":
         stats(argv[1], argv[2], argv[3],
@@ -242,6 +292,8 @@ def main(argv):
         valu(argv[1], argv[2], argv[3], argv[4])
     elif argv[0] == "waits":
         waits(argv[1], argv[2], argv[3], argv[4])
+    elif argv[0] == "runs":
+        runs(argv[1], argv[2], argv[3], argv[4])
     elif argv[0] == "traffic":
         cb = int(argv[argv.index("--copy-bytes") + 1])
         txt = argv[argv.index("--txt") + 1] if "--txt" in argv else None

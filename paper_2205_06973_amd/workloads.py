@@ -132,6 +132,20 @@ def dressed_pairs_circuit(n: int, blocks: int, seed: int, span: int = 6, dwell: 
     return out
 
 
+def split_dressed_circuit(n: int, n_low: int, blocks: int, seed: int, span: int = 5, dwell: int = 16):
+    """Two dressed-pair circuits, one on qubits [0, n_low) and one on
+    [n_low, n), interleaved block by block.  No gate joins the halves, so
+    the state stays a product psi_low(low bits) * psi_high(high bits) and
+    every amplitude can be checked from two small simulations."""
+    lo = dressed_pairs_circuit(n_low, blocks, seed, span, dwell)
+    hi = dressed_pairs_circuit(n - n_low, blocks, seed + 1, span, dwell)
+    shift = lambda g: (g[0], g[1] + n_low, g[2] + n_low if g[2] >= 0 else -1, g[3])  # noqa: E731
+    out = []
+    for b in range(blocks):  # five gates per block
+        out += lo[5 * b:5 * b + 5] + [shift(g) for g in hi[5 * b:5 * b + 5]]
+    return out, lo, hi
+
+
 def qft_circuit(n: int):
     gates = []
     for j in range(n - 1, -1, -1):

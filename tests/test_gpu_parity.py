@@ -329,3 +329,48 @@ def test_deep_dense_five_qubit_parts(dtype, mode):
     if mode == "auto_spec":
         assert plan.auto_choice(dtype).sum() >= 1
     check(got, sv.simulate(n, gates, 1234), dtype)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("mode,shape", [("part_fused", 0), ("part_fused", 1), ("part_fused", 2),
+                                        ("auto_spec", -1)])
+def test_fused_persistent_grid_24_qubits(dtype, mode, shape):
+    """Fused five-qubit parts on a 24-qubit state, where each workgroup of
+    the software-pipelined fused kernel walks many tile groups: two
+    dressed-pair circuits on qubits 0-11 and 12-23, interleaved, so the
+    state is psi_low * psi_high and every amplitude is checked against the
+    oracle's two 12-qubit states.  Parts on the high half run with coalesced
+    columns, parts on qubits 0..3 without.  Every launch shape of the
+    four- and five-qubit fused kernels."""
+    n, nl = 24, 12
+    gates, lo, hi = wl.split_dressed_circuit(n, nl, 120, seed=5)
+    hisv.hs_tune("fused_shape", shape)  # the three launch shapes
+    try:
+        got, plan = run_hip(n, gates, dtype, 5, "greedy", mode)
+    finally:
+        hisv.hs_tune("fused_shape", -1)
+    if mode == "auto_spec":
+        assert plan.auto_choice(dtype).sum() >= 1
+    want = np.kron(sv.simulate(n - nl, hi), sv.simulate(nl, lo))
+    check(got, want, dtype)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_background_specialization(dtype):
+    """hs_plan_specialize_async: AUTO runs the interpreter while the kernels
+    build and the specialized kernels once they are there; both results
+    match the oracle, and the plan reports the build."""
+    n, gates = wl.random12(3)
+    want = sv.simulate(n, gates)
+    plan = hisv.Plan.partition(hisv.Circuit(n, gates), 4, "greedy", seed=0, trials=8)
+    print(f"[case] background specialization {dtype}", flush=True)
+    plan.specialize_async(dtype)
+    st = new_state(n, dtype)
+    st.simulate(plan, "auto")  # interpreter or specialized, whichever is ready
+    check(st.amplitudes(), want, dtype)
+    plan.specialize_wait(dtype)
+    assert plan.specialized(dtype)
+    st.set_basis(0)
+    st.simulate(plan, "auto")
+    check(st.amplitudes(), want, dtype)
+    st.close()
