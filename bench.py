@@ -611,6 +611,8 @@ def main() -> int:
                     help="run only the 32-qubit QFT comparison (for kernel profiles)")
     ap.add_argument("--streaming-only", action="store_true",
                     help="run only the streaming-rate probe (for profiles)")
+    ap.add_argument("--dressed-only", action="store_true",
+                    help="run only the dense five-qubit-part comparison (for kernel profiles)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -643,6 +645,21 @@ def main() -> int:
         with torch.cuda.stream(stream):
             qbuf = torch.empty(1 << 32, dtype=torch.complex64, device="cuda")
         print(json.dumps({"qft32": run_qft(qbuf, stream, log, args.strategy, args.trials)}), flush=True)
+        return 0
+    if args.dressed_only:
+        with torch.cuda.stream(stream):
+            dbuf = torch.empty(1 << 30, dtype=torch.complex128, device="cuda")
+        out = {"dressed30": run_dressed(args, dbuf, stream, log)}
+        del dbuf
+        torch.cuda.empty_cache()
+        if args.copy_probe_gib > 0:
+            nbytes = int(args.copy_probe_gib * 2**30) // 16 * 16
+            a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+            b = torch.empty_like(a)
+            hisv.hs_copy_probe(a.data_ptr(), b.data_ptr(), nbytes, stream)
+            torch.cuda.synchronize()
+            out["copy_probe_bytes"] = nbytes
+        print(json.dumps(out), flush=True)
         return 0
     if args.streaming_only:
         with torch.cuda.stream(stream):

@@ -25,7 +25,17 @@
 //     when the union fits k and no other part lies on a path between them
 //     (so the contracted graph stays acyclic); parts are then renumbered in
 //     a topological order.
-// Coarsening is skipped: circuits here have at most ~10^4 gates.
+//   * coarsening (the agglomerative clustering that precedes the bisection):
+//     in circuit order, a gate joins the cluster holding all of its
+//     predecessors when the union stays within k qubits and the cluster
+//     within a size cap; otherwise it starts a cluster.  A gate that joins
+//     has no predecessor outside its cluster, so every edge between
+//     clusters enters a cluster at the gate that started it, from a cluster
+//     started earlier: the cluster graph is acyclic.  The bisection and its
+//     refinement then run on clusters (a cluster's qubits = the union of its
+//     gates'), the leaves are expanded back to gates, and the merge phase
+//     runs on gates.  Restarts with and without coarsening (two caps) keep
+//     the fewest parts.
 #include <algorithm>
 #include <numeric>
 
@@ -47,29 +57,22 @@ struct Rng {
   int below(int n) { return (int)(next() % (uint64_t)n); }
 };
 
+// The bisection works on items -- gates, or clusters of gates after
+// coarsening -- each with a qubit mask, joined by an item DAG.
 struct Ctx {
-  const std::vector<Gate>* gates;
-  const Dag* dag;
+  const std::vector<uint64_t>* mask;  // qubits of each item
+  const Dag* dag;                     // item DAG
   int n, k;
   uint64_t pad;  // qubits every part holds anyway (multi-level tiles)
   Rng rng;
   std::vector<int> side;   // scratch: -1 outside V, 0 / 1 inside
   std::vector<int> cnt0, cnt1;
-  std::vector<std::vector<int>> parts;  // leaves, in execution order
+  std::vector<std::vector<int>> parts;  // leaves (item ids), in execution order
 };
-
-inline int qubits_of(const Gate& g, int* q) {
-  q[0] = g.q0;
-  if (g.q1 >= 0) {
-    q[1] = g.q1;
-    return 2;
-  }
-  return 1;
-}
 
 uint64_t mask_of(const Ctx& c, const std::vector<int>& V) {
   uint64_t m = 0;
-  for (int v : V) m |= (*c.gates)[v].mask();
+  for (int v : V) m |= (*c.mask)[v];
   return m;
 }
 
@@ -113,11 +116,11 @@ void order_of(Ctx& c, const std::vector<int>& V, bool natural, std::vector<int>*
 std::pair<int, int> best_prefix_cut(const Ctx& c, const std::vector<int>& ord, int lo, int hi) {
   const int N = (int)ord.size();
   std::vector<uint64_t> suf(N + 1, 0);
-  for (int i = N - 1; i >= 0; --i) suf[i] = suf[i + 1] | (*c.gates)[ord[i]].mask();
+  for (int i = N - 1; i >= 0; --i) suf[i] = suf[i + 1] | (*c.mask)[ord[i]];
   uint64_t pre = 0;
   int best = -1, best_cost = 1 << 30;
   for (int i = 1; i < N; ++i) {
-    pre |= (*c.gates)[ord[i - 1]].mask();
+    pre |= (*c.mask)[ord[i - 1]];
     if (i < lo || i > hi) continue;
     const int cost = __builtin_popcountll(pre & ~c.pad) + __builtin_popcountll(suf[i] & ~c.pad);
     if (cost < best_cost) {
@@ -133,10 +136,8 @@ void refine(Ctx& c, const std::vector<int>& V, int lo, int hi) {
   std::fill(c.cnt0.begin(), c.cnt0.end(), 0);
   std::fill(c.cnt1.begin(), c.cnt1.end(), 0);
   int n0 = 0;
-  int q[2];
   for (int v : V) {
-    const int nq = qubits_of((*c.gates)[v], q);
-    for (int t = 0; t < nq; ++t) (c.side[v] ? c.cnt1 : c.cnt0)[q[t]]++;
+    for (uint64_t m = (*c.mask)[v]; m; m &= m - 1) (c.side[v] ? c.cnt1 : c.cnt0)[__builtin_ctzll(m)]++;
     n0 += c.side[v] == 0;
   }
   for (int pass = 0; pass < 8; ++pass) {
@@ -156,19 +157,19 @@ void refine(Ctx& c, const std::vector<int>& V, int lo, int hi) {
           if (c.side[w] == 1) { legal = false; break; }
       }
       if (!legal) continue;
-      const int nq = qubits_of((*c.gates)[v], q);
+      const uint64_t vm = (*c.mask)[v];
       std::vector<int>& from = s ? c.cnt1 : c.cnt0;
       std::vector<int>& to = s ? c.cnt0 : c.cnt1;
       int gain = 0;
-      for (int t = 0; t < nq; ++t) {
-        if (c.pad >> q[t] & 1) continue;  // held by both sides anyway
-        if (from[q[t]] == 1) ++gain;  // qubit leaves the source side
-        if (to[q[t]] == 0) --gain;    // qubit joins the destination side
+      for (uint64_t m = vm & ~c.pad; m; m &= m - 1) {  // pad qubits: held by both sides anyway
+        const int q = __builtin_ctzll(m);
+        if (from[q] == 1) ++gain;  // qubit leaves the source side
+        if (to[q] == 0) --gain;    // qubit joins the destination side
       }
       if (gain <= 0) continue;
-      for (int t = 0; t < nq; ++t) {
-        from[q[t]]--;
-        to[q[t]]++;
+      for (uint64_t m = vm; m; m &= m - 1) {
+        from[__builtin_ctzll(m)]--;
+        to[__builtin_ctzll(m)]++;
       }
       c.side[v] = 1 - s;
       n0 += s ? 1 : -1;
@@ -211,7 +212,7 @@ void bisect_rec(Ctx& c, std::vector<int> V, int depth) {
   for (int i = 0; i < N; ++i) c.side[best_ord[i]] = i < best_cut ? 0 : 1;
   refine(c, V, lo, hi);
   std::vector<int> V0, V1;
-  for (int v : V) (c.side[v] ? V1 : V0).push_back(v);  // V is in circuit order
+  for (int v : V) (c.side[v] ? V1 : V0).push_back(v);  // V is in item (topological) order
   for (int v : V) c.side[v] = -1;
   if (V0.empty() || V1.empty()) {
     c.parts.push_back(std::move(V));
@@ -332,25 +333,98 @@ int merge_and_number(const std::vector<Gate>& gates, const Dag& dag, int k, uint
   return next;
 }
 
+// Coarsening: clusters of gates (cluster_of per gate; clusters numbered in
+// circuit order of the gate that started them, a topological order of the
+// cluster graph), their qubit masks, gate lists and the cluster DAG.
+// cap = most gates a cluster takes.
+struct Coarse {
+  std::vector<int> cluster_of;
+  std::vector<uint64_t> mask;
+  std::vector<std::vector<int>> members;  // gate ids, circuit order
+  Dag dag;
+};
+
+Coarse coarsen(const std::vector<Gate>& gates, const Dag& dag, int k, uint64_t pad, int cap) {
+  Coarse cz;
+  const int G = (int)gates.size();
+  cz.cluster_of.assign(G, -1);
+  for (int v = 0; v < G; ++v) {
+    int c = -1;
+    bool one = !dag.pred[v].empty();
+    for (int p : dag.pred[v]) {
+      const int pc = cz.cluster_of[p];
+      if (c < 0) c = pc;
+      else if (pc != c) one = false;
+    }
+    const uint64_t gm = gates[v].mask();
+    if (one && c >= 0 && (int)cz.members[c].size() < cap &&
+        __builtin_popcountll(cz.mask[c] | gm | pad) <= k) {
+      cz.cluster_of[v] = c;
+      cz.mask[c] |= gm;
+      cz.members[c].push_back(v);
+    } else {
+      cz.cluster_of[v] = (int)cz.mask.size();
+      cz.mask.push_back(gm);
+      cz.members.push_back({v});
+    }
+  }
+  const int C = (int)cz.mask.size();
+  cz.dag.G = C;
+  cz.dag.succ.assign(C, {});
+  cz.dag.pred.assign(C, {});
+  for (int v = 0; v < G; ++v)
+    for (int w : dag.succ[v]) {
+      const int a = cz.cluster_of[v], b = cz.cluster_of[w];
+      if (a == b) continue;
+      if (std::find(cz.dag.succ[a].begin(), cz.dag.succ[a].end(), b) == cz.dag.succ[a].end()) {
+        cz.dag.succ[a].push_back(b);
+        cz.dag.pred[b].push_back(a);
+      }
+    }
+  return cz;
+}
+
 }  // namespace
 
 int partition_dagp(const std::vector<Gate>& gates, const Dag& dag, int n, int k, uint64_t seed,
                    std::vector<int32_t>* part, uint64_t pad) {
-  // a few seeded restarts of bisection + merge; keep the fewest parts
+  // seeded restarts of (coarsening +) bisection + merge; keep the fewest
+  // parts.  cap 1 = no coarsening (every gate its own item).
+  const int G = (int)gates.size();
+  std::vector<uint64_t> gmask(G);
+  for (int v = 0; v < G; ++v) gmask[v] = gates[v].mask();
+  const int caps[] = {1, 4, 16};
+  std::vector<Coarse> levels;
+  for (int cap : caps) levels.push_back(cap > 1 ? coarsen(gates, dag, k, pad, cap) : Coarse{});
   int best = -1;
   std::vector<int32_t> cand;
   for (int r = 0; r < 6; ++r) {
-    Ctx c{&gates, &dag, n, k, pad, Rng((seed ^ 0xda6bull) + 7919ull * r), {}, {}, {}, {}};
-    c.side.assign(gates.size(), -1);
-    c.cnt0.assign(64, 0);
-    c.cnt1.assign(64, 0);
-    std::vector<int> all(gates.size());
-    std::iota(all.begin(), all.end(), 0);
-    if (!gates.empty()) bisect_rec(c, std::move(all), 0);
-    const int np = merge_and_number(gates, dag, k, pad, c.parts, &cand);
-    if (best < 0 || np < best) {
-      best = np;
-      part->swap(cand);
+    for (size_t l = 0; l < levels.size(); ++l) {
+      const bool coarse = caps[l] > 1;
+      const Coarse& cz = levels[l];
+      const std::vector<uint64_t>* im = coarse ? &cz.mask : &gmask;
+      const Dag* id = coarse ? &cz.dag : &dag;
+      const int items = (int)im->size();
+      Ctx c{im, id, n, k, pad, Rng((seed ^ 0xda6bull) + 7919ull * r + 104729ull * l), {}, {}, {}, {}};
+      c.side.assign(items, -1);
+      c.cnt0.assign(64, 0);
+      c.cnt1.assign(64, 0);
+      std::vector<int> all(items);
+      std::iota(all.begin(), all.end(), 0);
+      if (items) bisect_rec(c, std::move(all), 0);
+      if (coarse) {  // leaves back to gates, in circuit order
+        for (std::vector<int>& leaf : c.parts) {
+          std::vector<int> gs;
+          for (int cl : leaf) gs.insert(gs.end(), cz.members[cl].begin(), cz.members[cl].end());
+          std::sort(gs.begin(), gs.end());
+          leaf.swap(gs);
+        }
+      }
+      const int np = merge_and_number(gates, dag, k, pad, c.parts, &cand);
+      if (best < 0 || np < best) {
+        best = np;
+        part->swap(cand);
+      }
     }
   }
   return best;

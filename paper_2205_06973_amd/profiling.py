@@ -7,6 +7,8 @@
     python -m paper_2205_06973_amd.profiling valu <counters.csv> <stats.csv> <out.txt> "<command>"
     python -m paper_2205_06973_amd.profiling waits <counters.csv> <stats.csv> <out.txt> "<command>"
     python -m paper_2205_06973_amd.profiling runs <kernel_trace.csv> <bench.json> <out.txt> "<command>"
+    python -m paper_2205_06973_amd.profiling kernel_traffic <fetch.csv> <write.csv> <stats.csv> <out.txt> \
+        "<command>" --copy-bytes B --c64-bytes S64 --c128-bytes S128
 
 `stats` condenses a `--kernel-trace --stats` kernel_stats.csv.  `traffic`
 reads two `--pmc` counter_collection.csv files (FETCH_SIZE in one run,
@@ -143,6 +145,45 @@ def traffic(fetch_csv: str, write_csv: str, key: str, command: str, copy_bytes: 
         json.dump(d, f, indent=1)
     print(json.dumps(rec, indent=1))
     return rec
+
+
+def kernel_traffic(fetch_csv: str, write_csv: str, stats_csv: str, out_path: str, command: str,
+                   copy_bytes: int, state_bytes: dict[str, int]) -> None:
+    """Per kernel of a run: mean calibrated FETCH_SIZE + WRITE_SIZE bytes per
+    dispatch against the algorithmic bytes of one sweep of its state (read
+    + write every amplitude), with the traced average duration and the
+    achieved fraction of the 8 TB/s HBM peak.  state_bytes maps a dtype tag
+    ("float" / "double") to the state's bytes."""
+    fetch = _counter_per_kernel(fetch_csv, "FETCH_SIZE")
+    write = _counter_per_kernel(write_csv, "WRITE_SIZE")
+    cf = [v for k, v in fetch.items() if k.startswith("copy_probe_kernel")][0]
+    cw = [v for k, v in write.items() if k.startswith("copy_probe_kernel")][0]
+    f_scale = copy_bytes / (sum(cf) / len(cf) * 1024.0)
+    w_scale = copy_bytes / (sum(cw) / len(cw) * 1024.0)
+    avg_ns = _avg_ns(stats_csv)
+    lines = ["# HBM traffic and duration per dispatch (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE;",
+             "# durations from --kernel-trace --stats of the same command)",
+             f"# command: {command}", f"# kernel source hash: {kernel_source_hash()}",
+             f"# calibration on copy_probe_kernel ({copy_bytes} B each way): FETCH x {f_scale:.4f}, "
+             f"WRITE x {w_scale:.4f}", "",
+             f"{'kernel':40s} {'calls':>6s} {'avg_us':>10s} {'GB/call':>9s} {'algo_GB':>9s} {'ratio':>6s} "
+             f"{'GB/s':>8s} {'frac':>6s}"]
+    for k in sorted(fetch):
+        if k not in write or k.startswith("copy_probe") or k not in avg_ns:
+            continue
+        tag = "double" if "double" in k else "float"
+        if tag not in state_bytes:
+            continue
+        b = (sum(fetch[k]) / len(fetch[k]) * f_scale + sum(write[k]) / len(write[k]) * w_scale) * 1024.0
+        algo = 2 * state_bytes[tag]
+        if b < 0.5 * algo:  # readouts and other partial sweeps
+            continue
+        gbs = algo / avg_ns[k]
+        lines.append(f"{k:40s} {len(fetch[k]):6d} {avg_ns[k] / 1e3:10.1f} {b / 1e9:9.2f} {algo / 1e9:9.2f} "
+                     f"{b / algo:6.3f} {gbs:8.1f} {gbs / 8000:6.3f}")
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def mfma(counters_csv: str, stats_csv: str, out_path: str, command: str) -> None:
@@ -294,6 +335,11 @@ def main(argv):
         waits(argv[1], argv[2], argv[3], argv[4])
     elif argv[0] == "runs":
         runs(argv[1], argv[2], argv[3], argv[4])
+    elif argv[0] == "kernel_traffic":
+        sb = {"float": int(argv[argv.index("--c64-bytes") + 1]),
+              "double": int(argv[argv.index("--c128-bytes") + 1])}
+        kernel_traffic(argv[1], argv[2], argv[3], argv[4], argv[5],
+                       int(argv[argv.index("--copy-bytes") + 1]), sb)
     elif argv[0] == "traffic":
         cb = int(argv[argv.index("--copy-bytes") + 1])
         txt = argv[argv.index("--txt") + 1] if "--txt" in argv else None
