@@ -368,6 +368,19 @@ def test_dagp_merges_interleaved_groups():
     assert p.num_parts == 2
 
 
+def test_dagp_with_coarsening_on_the_headline_distribution():
+    """The clustering phase (Sec. IV.B.3) before the bisection: on 1,000
+    random gates over 34 qubits at k = 5, dagP's best restart comes from a
+    coarsened graph and beats the greedy ready-set partitioner, and the
+    plan passes the oracle's exact validity check."""
+    n, gates = wl.random34(0)
+    c = hisv.Circuit(n, gates)
+    d = hisv.Plan.partition(c, 5, "dagp", seed=0)
+    g = hisv.Plan.partition(c, 5, "greedy", seed=0, trials=32)
+    assert d.num_parts < g.num_parts
+    assert op.check_partition(n, gates, d.part_of_gate().tolist(), 5) == []
+
+
 def test_dagp_beats_cutoffs_on_qft():
     n = 24
     gates = wl.qft_circuit(n)
