@@ -574,6 +574,31 @@ def streaming_ceiling(buf, stream, log, cases):
     return rows
 
 
+def tile_scan(buf, stream, log, sizes=(28, 30, 32, 34), reps=8):
+    """One part whose tile is a single contiguous run (H twice on qubits
+    6-12, tile = qubits 0-12, complex64), specialized, at several state
+    sizes: the part kernel's rate without scattered runs or re-layouts."""
+    import torch
+    from paper_2205_06973_amd import hisv
+    rows = []
+    for n in sizes:
+        if (1 << n) * 8 > buf.numel() * buf.element_size():
+            continue
+        gates = [("h", q, -1, ()) for q in range(6, 13)] * 2
+        plan = hisv.Plan.partition(hisv.Circuit(n, gates), 7, "greedy", seed=0, trials=4)
+        plan.specialize("c64")
+        view = buf.view(torch.uint8)[: (1 << n) * 8].view(torch.complex64)
+        st = hisv.State.wrap_tensor(view, stream)
+        st.set_basis(0)
+        sec = timed_plan(st, plan, stream, steps=reps)
+        gbs = part_pass_bytes(n, "c64") / sec / 1e9
+        rows.append({"n": n, "dtype": "c64", "parts": plan.num_parts, "ms_per_pass": sec * 1e3,
+                     "pass_GBps": gbs, "frac": gbs / HBM_PEAK_GBS})
+        st.close()
+        log(f"[bench] tile scan {rows[-1]}")
+    return rows
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -611,6 +636,8 @@ def main() -> int:
                     help="run only the 32-qubit QFT comparison (for kernel profiles)")
     ap.add_argument("--streaming-only", action="store_true",
                     help="run only the streaming-rate probe (for profiles)")
+    ap.add_argument("--tile-scan-only", action="store_true",
+                    help="run only the contiguous-tile part at 28-34 qubits (for profiles)")
     ap.add_argument("--dressed-only", action="store_true",
                     help="run only the dense five-qubit-part comparison (for kernel profiles)")
     args = ap.parse_args()
@@ -645,6 +672,11 @@ def main() -> int:
         with torch.cuda.stream(stream):
             qbuf = torch.empty(1 << 32, dtype=torch.complex64, device="cuda")
         print(json.dumps({"qft32": run_qft(qbuf, stream, log, args.strategy, args.trials)}), flush=True)
+        return 0
+    if args.tile_scan_only:
+        with torch.cuda.stream(stream):
+            tbuf = torch.empty(1 << 34, dtype=torch.complex64, device="cuda")
+        print(json.dumps({"streaming": tile_scan(tbuf, stream, log)}), flush=True)
         return 0
     if args.dressed_only:
         with torch.cuda.stream(stream):

@@ -6,7 +6,8 @@
     python -m paper_2205_06973_amd.profiling mfma <counters.csv> <stats.csv> <out.txt> "<command>"
     python -m paper_2205_06973_amd.profiling valu <counters.csv> <stats.csv> <out.txt> "<command>"
     python -m paper_2205_06973_amd.profiling waits <counters.csv> <stats.csv> <out.txt> "<command>"
-    python -m paper_2205_06973_amd.profiling runs <kernel_trace.csv> <bench.json> <out.txt> "<command>"
+    python -m paper_2205_06973_amd.profiling runs <kernel_trace.csv> <bench.json> <out.txt> "<command>" \
+        [--kernel K] [--per-case N]
     python -m paper_2205_06973_amd.profiling kernel_traffic <fetch.csv> <write.csv> <stats.csv> <out.txt> \
         "<command>" --copy-bytes B --c64-bytes S64 --c128-bytes S128
 
@@ -169,15 +170,16 @@ def kernel_traffic(fetch_csv: str, write_csv: str, stats_csv: str, out_path: str
              f"{'kernel':40s} {'calls':>6s} {'avg_us':>10s} {'GB/call':>9s} {'algo_GB':>9s} {'ratio':>6s} "
              f"{'GB/s':>8s} {'frac':>6s}"]
     for k in sorted(fetch):
-        if k not in write or k.startswith("copy_probe") or k not in avg_ns:
+        # kernels whose name carries the precision (the per-part specialized
+        # kernels do not, and readouts are not sweeps)
+        if k not in write or k not in avg_ns or not k.startswith(("fused_pass_kernel", "part_pass_kernel",
+                                                                   "gate_pass")):
             continue
         tag = "double" if "double" in k else "float"
         if tag not in state_bytes:
             continue
         b = (sum(fetch[k]) / len(fetch[k]) * f_scale + sum(write[k]) / len(write[k]) * w_scale) * 1024.0
         algo = 2 * state_bytes[tag]
-        if b < 0.5 * algo:  # readouts and other partial sweeps
-            continue
         gbs = algo / avg_ns[k]
         lines.append(f"{k:40s} {len(fetch[k]):6d} {avg_ns[k] / 1e3:10.1f} {b / 1e9:9.2f} {algo / 1e9:9.2f} "
                      f"{b / algo:6.3f} {gbs:8.1f} {gbs / 8000:6.3f}")
@@ -306,9 +308,11 @@ def runs(trace_csv: str, bench_json: str, out_path: str, command: str, kernel: s
     dur = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows]
     with open(bench_json) as f:
         cases = json.loads(f.read().strip().splitlines()[-1])["streaming"]
-    lines = [f"# per-size durations of {kernel} (rocprofv3 --kernel-trace), one sweep = H on qubit 0",
+    what = ("one sweep = H on qubit 0 (8 warm + 8 timed per size)" if kernel == "gate_pass_1q" else
+            "one part, H twice on qubits 6-12, tile = qubits 0-12 (1 warm + 8 timed per size)")
+    lines = [f"# per-size durations of {kernel} (rocprofv3 --kernel-trace), {what}",
              f"# command: {command}", f"# kernel source hash: {kernel_source_hash()}",
-             f"# {len(dur)} dispatches in {per_case}-dispatch runs (8 warm + 8 timed per size)", "",
+             f"# {len(dur)} dispatches in {per_case}-dispatch runs", "",
              f"{'n':>3s} {'dtype':>6s} {'avg_us':>10s} {'GB/s':>9s} {'frac':>6s} {'bench_GB/s':>11s}"]
     for i, c in enumerate(cases):
         run = dur[i * per_case:(i + 1) * per_case]
@@ -334,7 +338,9 @@ def main(argv):
     elif argv[0] == "waits":
         waits(argv[1], argv[2], argv[3], argv[4])
     elif argv[0] == "runs":
-        runs(argv[1], argv[2], argv[3], argv[4])
+        kern = argv[argv.index("--kernel") + 1] if "--kernel" in argv else "gate_pass_1q"
+        per = int(argv[argv.index("--per-case") + 1]) if "--per-case" in argv else 16
+        runs(argv[1], argv[2], argv[3], argv[4], kern, per)
     elif argv[0] == "kernel_traffic":
         sb = {"float": int(argv[argv.index("--c64-bytes") + 1]),
               "double": int(argv[argv.index("--c128-bytes") + 1])}
