@@ -44,7 +44,8 @@ Prints ONE JSON line on stdout:
              gate-by-gate (specialized) vs fused-unitary (matrix cores) vs
              AUTO, with the fused kernel's matrix-core roofline
   serving    p50/p99 latency (from each request's scheduled arrival) and
-             circuits/s of a Poisson stream of 1,000 requests
+             circuits/s of a Poisson stream of 1,000 requests at 40/s, and a
+             latency-against-load curve of 250 requests at 20, 80, 160/s
   accuracy   U^-1 U |0> against |0> on sampled amplitudes of the headline
              state (untimed)
   cpu_baseline  the oracle (numpy complex128, one thread) on a bounded
@@ -619,6 +620,9 @@ def main() -> int:
                     help="timed steps of the 34-qubit complex64 companion run (0 = skip)")
     ap.add_argument("--serving", type=int, default=1000, help="serving requests (0 = skip)")
     ap.add_argument("--serving-rate", type=float, default=40.0, help="arrivals per second")
+    ap.add_argument("--serving-curve", type=float, nargs="*", default=[20.0, 80.0, 160.0],
+                    help="further arrival rates, each with --serving-curve-requests requests")
+    ap.add_argument("--serving-curve-requests", type=int, default=250)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--tune", action="append", default=[], metavar="KEY=VALUE",
                     help="layout knob passed to hs_tune before the plan is compiled")
@@ -809,6 +813,18 @@ def main() -> int:
                                "peak_inflight": res["stats"]["peak_inflight"],
                                "peak_admitted_GiB": res["stats"]["peak_bytes"] / 2**30})
         log(f"[bench] serving: {out['serving']}")
+        # latency against load: shorter streams at other arrival rates
+        curve = []
+        for rate in args.serving_curve:
+            creqs = wl.serving_stream(args.serving_curve_requests, rate, seed=args.seed + 1)
+            cres = serving.run_stream(creqs)
+            row = serving.summarize(cres, len(creqs))
+            curve.append({"arrival_rate_per_s": rate, "requests": len(creqs), "p50_ms": row["p50_ms"],
+                          "p99_ms": row["p99_ms"], "circuits_per_s": row["circuits_per_s"],
+                          "host_share": row["host_share"]})
+            log(f"[bench] serving curve {curve[-1]}")
+        if curve:
+            out["serving"]["curve"] = curve
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n, args.seed, dt)
