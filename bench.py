@@ -149,6 +149,9 @@ def cpu_baseline(n_target: int, seed: int, dtype: str, budget_s: float = 20.0, n
                    f"distribution at n={n_cpu} ({dt:.1f} s); per-gate time x2^{n_target - n_cpu} "
                    f"to n={n_target} (the GPU state is {dtype})"),
         "extrapolated_from_n": n_cpu,
+        # the oracle's own sweep rate at the sampled size (read + write of
+        # every complex128 amplitude per gate)
+        "oracle_GBps": 2 * (1 << n_cpu) * 16 / per_gate / 1e9,
         "host_cpus": len(os.sched_getaffinity(0)),
     }
 
