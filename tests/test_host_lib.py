@@ -577,3 +577,20 @@ def test_bench_inverse_gates_undo_the_circuit():
     np.testing.assert_allclose(got, psi0, atol=1e-12, rtol=0)
     with pytest.raises(ValueError):
         bench.inverse_gates([("s", 0, -1, ())])
+
+
+def test_auto_choice_follows_the_cost_model():
+    """hs_plan_auto_choice on the host (no device, so the gate-by-gate side
+    is the interpreter): deep dense five-qubit parts (~80 gates each) go to
+    the fused kernel, the light parts of a random circuit mostly stay gate
+    by gate, and the answer has one entry per part."""
+    n = 30
+    deep = wl.dressed_pairs_circuit(n, 600, seed=3, span=5, dwell=16)
+    p = hisv.Plan.partition(hisv.Circuit(n, deep), 5, "greedy", seed=0, trials=8)
+    ch = p.auto_choice("c64")
+    assert ch.shape == (p.num_parts,) and set(ch.tolist()) <= {0, 1}
+    assert ch.sum() >= p.num_parts * 3 // 4
+    _, light = wl.random34(0, n=n)
+    q = hisv.Plan.partition(hisv.Circuit(n, light), 7, "greedy", seed=0, trials=8)
+    for dt in ("c64", "c128"):
+        assert q.auto_choice(dt).sum() <= q.num_parts // 4
