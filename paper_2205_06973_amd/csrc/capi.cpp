@@ -643,7 +643,7 @@ static hs_status check_exec(hs_exec exec) {
 // and its cost (in HBM sweeps) is below the gate-by-gate kernel's -- the
 // specialized kernel's when the plan is specialized, else the interpreter's.
 static bool auto_picks_fused(Plan* p, hs_dtype dt, int i, bool specialized) {
-  const double gate_cost = specialized ? spec_part_cost(p->scomp[dt][i], dt) : lds_part_cost(p->comp[dt][i]);
+  const double gate_cost = specialized ? spec_part_cost(p->scomp[dt][i], dt) : lds_part_cost(p->comp[dt][i], dt);
   return p->fused[i].w && fused_part_cost(p->fused[i], dt) < gate_cost;
 }
 

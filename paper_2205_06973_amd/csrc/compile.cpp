@@ -527,17 +527,21 @@ hs_status compile_fused(int n, const std::vector<Gate>& pg, FusedPart* out) {
 
 namespace hisv {
 
-// Relative cost of a part (one HBM sweep of the state = 1), from timings of
-// the part-pass kernel on MI355X with a 30-qubit complex64 state: each LDS
-// re-layout of the tile costs about 0.14 sweep, each register operation on
-// a 16-amplitude lane as listed (dense complex 2x2 ~0.066 sweep, real or
-// diagonal ~0.035, controlled/permutation ~0.007).  Used by AUTO only.
-double lds_part_cost(const CompiledPart& cp) {
-  static const double op_cost[OP_NUM] = {0.066, 0.035, 0.038, 0.025, 0.01,
-                                         0.007, 0.007, 0.012, 0.01};
-  double c = 1.0 + 0.14 * cp.lds_round_trips;
-  for (const HostOp& op : cp.ops) c += op_cost[op.kind];
-  return c;
+// Relative cost of a part on the interpreter kernel (one HBM sweep of the
+// state = 1), fitted to per-part timings of 30-qubit states (random,
+// layered and dressed-pair circuits; 820 parts, mean |log error| 0.05): a
+// smooth maximum of the sweep (+0.03 / 0.02 per LDS re-layout, complex64 /
+// complex128) and the vector-ALU work -- 0.005 / 0.004 sweep per flop per
+// amplitude (Sec. III.A's counting) plus 0.03 per register op for the
+// interpreter's dispatch and register copies.  Used by AUTO only.
+double lds_part_cost(const CompiledPart& cp, hs_dtype dt) {
+  static const double flops[OP_NUM] = {14, 6, 6, 3, 0, 0, 0.5, 1.5, 0, 30};
+  const bool f32 = dt == HS_C64;
+  const double mem = 1.0 + (f32 ? 0.03 : 0.02) * cp.lds_round_trips;
+  double f = 0;
+  for (const HostOp& op : cp.ops) f += flops[op.kind];
+  const double alu = (f32 ? 0.005 : 0.004) * f + 0.03 * (double)cp.ops.size();
+  return std::cbrt(mem * mem * mem + alu * alu * alu);
 }
 
 // The specialized kernels keep the sweep near the HBM rate while a part's

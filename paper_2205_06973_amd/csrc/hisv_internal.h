@@ -204,7 +204,7 @@ hs_status plan_compile_fused(Plan* p);
 int fused_launch_shape();
 // relative cost (one HBM sweep = 1) of a part on each path, for AUTO
 double spec_part_cost(const CompiledPart& cp, hs_dtype dt);
-double lds_part_cost(const CompiledPart& cp);
+double lds_part_cost(const CompiledPart& cp, hs_dtype dt);
 double fused_part_cost(const FusedPart& f, hs_dtype dt);
 hs_status dev_norm(State* s, double* out);
 // the same reduction with its partial sums in a static device array (no allocation)

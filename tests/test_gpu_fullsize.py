@@ -94,7 +94,7 @@ def test_layered28_product_block(n, dtype, k, strategy, layers):
     gates = wl.layered_product_block_circuit(n, layers, seed=1)
     st, buf = simulate(n, gates, dtype, k, strategy)
     pe, po = product_factors(n, gates)
-    idx = sample_indices(n, 1 << 16, 2)
+    idx = sample_indices(n, 1 << 20, 2)
     d = np.abs(st.amplitudes_at(idx) - product_amp(idx, n, pe, po))
     assert report("layered28 product", d, n) <= TOL[dtype]
     assert abs(st.norm() - 1) <= (1e-5 if dtype == "c64" else 1e-12)
@@ -117,10 +117,11 @@ def test_layered28_round_trip(dtype):
 def test_qft32_closed_form(strategy, mode):
     """The 32-qubit QFT on a random basis state (32 GiB complex64), k = 7:
     gate-by-gate specialized kernels, the fused dense-unitary kernels on
-    matrix cores, and AUTO over both."""
+    matrix cores, and AUTO over both; 2^24 random amplitudes and the first
+    and last 4,096 against the closed form."""
     n, gates, x = wl.qft32(0)
     st, buf = simulate(n, gates, "c64", 7, strategy, mode=mode, init=x)
-    idx = sample_indices(n, 1 << 18, 4)
+    idx = sample_indices(n, 1 << 24, 4)
     want = np.exp(2j * np.pi * ((np.uint64(x) * idx) % np.uint64(1 << n)).astype(np.float64)
                   / (1 << n)) / math.sqrt(1 << n)
     d = np.abs(st.amplitudes_at(idx) - want)
@@ -135,7 +136,7 @@ def test_random34_product_block(n, dtype, strategy):
     gates = wl.product_block_circuit(n, 1000, wl.RANDOM34_KINDS, seed=5)
     st, buf = simulate(n, gates, dtype, 7, strategy)
     pe, po = product_factors(n, gates)
-    idx = sample_indices(n, 1 << 16, 6)
+    idx = sample_indices(n, 1 << 20, 6)
     d = np.abs(st.amplitudes_at(idx) - product_amp(idx, n, pe, po))
     assert report(f"random{n} product", d, n) <= TOL[dtype]
     assert abs(st.norm() - 1) <= (1e-5 if dtype == "c64" else 1e-12)
@@ -150,7 +151,7 @@ def test_random34_product_block_k_and_interpreter(k, mode):
     gates = wl.product_block_circuit(n, 1000, wl.RANDOM34_KINDS, seed=5)
     st, buf = simulate(n, gates, dtype, k, "greedy", mode=mode)
     pe, po = product_factors(n, gates)
-    idx = sample_indices(n, 1 << 16, 6 + k)
+    idx = sample_indices(n, 1 << 20, 6 + k)
     d = np.abs(st.amplitudes_at(idx) - product_amp(idx, n, pe, po))
     assert report(f"random{n} product k={k} {mode}", d, n) <= TOL[dtype]
     assert abs(st.norm() - 1) <= 1e-5
