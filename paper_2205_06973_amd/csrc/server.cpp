@@ -11,12 +11,17 @@
 //             the interpreter descriptors and uploads them with the
 //             stream-ordered allocator on its own stream -- all without the
 //             server lock.
-//   admit     the worker thread admits prepared requests in ticket order
-//             while the bytes of resident states (plus their descriptors) stay
-//             within the budget, allocates the state on the stream of a pool
-//             with the least outstanding work, enqueues set-basis and one
-//             part-pass per part, and records an event.  Requests admitted
-//             while others run overlap with them on the device.
+//   admit     the worker thread admits prepared requests strictly in ticket
+//             order while the bytes of resident states (plus their
+//             descriptors) stay within the budget, allocates the state on the
+//             stream of a pool with the least outstanding work, enqueues
+//             set-basis and one part-pass per part, and records an event.
+//             Requests admitted while others run overlap with them on the
+//             device.  (Preparation finishes out of order on the host
+//             threads; admitting in that order could let later requests
+//             fill the budget and hold it until released, while a client
+//             releasing in submission order waits for an earlier one that
+//             no longer fits.)
 //   retire    the worker polls the events; a finished request keeps its state
 //             resident until it is read and released.
 //   release   state and descriptors go back with hipFreeAsync (no device-wide
@@ -83,6 +88,7 @@ struct hs_server_ {
   std::condition_variable cv;
   std::deque<Request*> prep_queue;
   std::map<uint64_t, Request*> ready;  // prepared, waiting for admission (ticket order)
+  uint64_t next_admit = 1;              // the lowest ticket not yet admitted or failed
   std::vector<Request*> running;
   std::map<uint64_t, Request*> reqs;
   bool stop = false;
@@ -156,6 +162,11 @@ void prep_main(hs_server_* sv, int idx) {
   }
 }
 
+Request* find(hs_server_* sv, uint64_t t) {
+  auto it = sv->reqs.find(t);
+  return it == sv->reqs.end() ? nullptr : it->second;
+}
+
 // Launch everything for an admitted request (called with the lock held;
 // nothing here waits on the device) on the stream with the least
 // outstanding work, so that small requests do not queue behind large ones
@@ -208,11 +219,20 @@ void worker_main(hs_server_* sv) {
         ++i;
       }
     }
-    // admit prepared requests in ticket order while the budget allows
-    while (!sv->ready.empty()) {
-      Request* r = sv->ready.begin()->second;
+    // admit prepared requests strictly in ticket order while the budget
+    // allows: skip tickets that failed in preparation, stop at one still
+    // being prepared or one that does not fit yet
+    while (sv->next_admit < sv->next_ticket) {
+      Request* nr = find(sv, sv->next_admit);
+      if (!nr || nr->status == RQ_FAILED || nr->status == RQ_RELEASED) {
+        ++sv->next_admit;
+        continue;
+      }
+      if (nr->status != RQ_READY) break;
+      Request* r = nr;
       if (sv->cur_bytes + r->bytes > sv->budget) break;
-      sv->ready.erase(sv->ready.begin());
+      sv->ready.erase(r->ticket);
+      ++sv->next_admit;
       sv->cur_bytes += r->bytes;
       sv->peak_bytes = std::max(sv->peak_bytes, sv->cur_bytes);
       r->t_launch = now_s();
@@ -254,11 +274,6 @@ void worker_main(hs_server_* sv) {
       sv->cv.wait_for(lk, std::chrono::microseconds(sv->running.empty() ? 2000 : 20));
   }
   sv->cv.notify_all();
-}
-
-Request* find(hs_server_* sv, uint64_t t) {
-  auto it = sv->reqs.find(t);
-  return it == sv->reqs.end() ? nullptr : it->second;
 }
 
 // Free a request's device memory and handles; no lock held.

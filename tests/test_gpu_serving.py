@@ -97,3 +97,26 @@ def test_arrival_stamp_and_errors():
     assert e.value.code == "HS_E_ADMISSION"
     srv.release(t)
     srv.close()
+
+
+def test_admission_follows_ticket_order_under_a_tight_budget():
+    """Requests finish preparing out of order on the server's host threads
+    (a long circuit first, short ones after).  Admission still follows
+    ticket order, so a client that waits for and releases its requests in
+    submission order is never left waiting on one that later, finished but
+    unreleased requests keep out of the byte budget."""
+    n = 14  # complex128: 256 KiB states
+    big = wl.layered28(1, n=n, layers=400)[1]  # 8,400 gates: slow to partition and compile
+    small = [wl.layered28(2 + i, n=n, layers=2)[1] for i in range(8)]
+    # the long request and about three short ones fit together, not all nine
+    srv = hisv.Server(budget_bytes=(7 << 20) // 2, num_streams=2)
+    print("[case] tight budget, long request first", flush=True)
+    tickets = [srv.submit(n, big, "c128", 0, 7, "greedy")]
+    tickets += [srv.submit(n, g, "c128", 0, 7, "greedy") for g in small]
+    for t in tickets:
+        srv.wait(t, timeout_ms=60000)  # fails (HS_E_STATE) rather than hangs
+        srv.release(t)
+    stats = srv.stats()
+    assert stats["completed"] == len(tickets)
+    assert stats["cur_bytes"] == 0 and stats["peak_bytes"] <= (7 << 20) // 2
+    srv.close()
