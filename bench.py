@@ -32,6 +32,8 @@ Prints ONE JSON line on stdout:
              (complex64), n = 34 at k = 5 and 6, and the largest states that
              fit (35-qubit complex64, 34-qubit complex128; 256 GiB): one
              timed run each
+  seed_spread  the headline distribution at 30 qubits complex128 over seeds
+             0-4: median and spread of gates/s, pass rate and part count
   multilevel the same circuits with the multi-level partition (first level
              bounded by the padded LDS tile, 14 qubits complex64 / 13
              complex128; second level = register stages)
@@ -208,6 +210,38 @@ def run_sweep(args, buf, stream, log):
             raise RuntimeError(f"norm drift in sweep case {row}")
         rows.append(row)
     return rows
+
+
+def run_seed_spread(args, buf, stream, log, n=30, dt="c128", k=7, seeds=(0, 1, 2, 3, 4)):
+    """The headline distribution at 30 qubits, complex128, over five seeds:
+    median and spread of the per-circuit rate and part count."""
+    import statistics
+    import torch
+    from paper_2205_06973_amd import hisv
+    from paper_2205_06973_amd import workloads as wl
+    amp = 8 if dt == "c64" else 16
+    view = buf.view(torch.uint8)[: (1 << n) * amp].view(torch.complex64 if dt == "c64" else torch.complex128)
+    st = hisv.State.wrap_tensor(view, stream)
+    rows = []
+    for sd in seeds:
+        st.set_basis(0)
+        _, gates = wl.random34(sd, n=n, num_gates=args.gates)
+        plan = hisv.Plan.partition(hisv.Circuit(n, gates), k, args.strategy, seed=sd, trials=args.trials)
+        plan.specialize(dt)
+        sec = timed_plan(st, plan, stream)
+        gbs = part_pass_bytes(n, dt) * plan.num_parts / sec / 1e9
+        rows.append({"seed": sd, "parts": plan.num_parts, "gates_per_s": len(gates) / sec,
+                     "pass_GBps": gbs, "frac": gbs / HBM_PEAK_GBS})
+    st.close()
+    g = [r["gates_per_s"] for r in rows]
+    f = [r["frac"] for r in rows]
+    out = {"n": n, "dtype": dt, "k": k, "seeds": list(seeds), "rows": rows,
+           "gates_per_s_median": statistics.median(g), "gates_per_s_min": min(g), "gates_per_s_max": max(g),
+           "frac_median": statistics.median(f), "frac_min": min(f), "frac_max": max(f),
+           "parts": [r["parts"] for r in rows]}
+    log(f"[bench] seed spread {out['gates_per_s_median']:.1f} gates/s median "
+        f"({out['gates_per_s_min']:.1f}-{out['gates_per_s_max']:.1f}), parts {out['parts']}")
+    return out
 
 
 def run_multilevel(args, buf, stream, log):
@@ -786,6 +820,7 @@ def main() -> int:
             out["streaming"] = streaming_ceiling(buf, stream, log, stream_cases)
         if not args.no_sweep:
             out["sweep"] = run_sweep(args, buf, stream, log)
+            out["seed_spread"] = run_seed_spread(args, buf, stream, log)
         if not args.no_multilevel:
             out["multilevel"] = run_multilevel(args, buf, stream, log)
         if not args.no_layered:
