@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cstring>
 #include <map>
 #include <type_traits>
@@ -484,10 +485,13 @@ fused_pass_kernel(cplx<T>* __restrict__ st, const FusedDesc* __restrict__ fd, co
         nui[rb][ks] = -ui[rb][ks];
       }
   }
-  // The qubit lists (sq[8], pq[4], tq[12]: 24 bytes from offset 24 of the
+  // The qubit lists (sq[8], pq[4], tq[12]: 24 contiguous bytes of the
   // descriptor) as six uniform dwords, read once: byte loads inside the tile
   // loop would be vector loads followed by a full wait on every memory
   // operation in flight, prefetched tiles and stores included.
+  static_assert(offsetof(FusedDesc, sq) % 4 == 0 && offsetof(FusedDesc, pq) == offsetof(FusedDesc, sq) + 8 &&
+                    offsetof(FusedDesc, tq) == offsetof(FusedDesc, sq) + 12 && sizeof(FusedDesc::tq) == 12,
+                "the qubit lists must be 24 contiguous bytes on a dword boundary");
   uint32_t qw[6];
   {
     const uint32_t* q32 = reinterpret_cast<const uint32_t*>(fd->sq);
