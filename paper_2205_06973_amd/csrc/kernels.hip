@@ -72,37 +72,12 @@ struct RegV {
   __device__ __forceinline__ const T& operator[](int i) const { return v[i]; }
 };
 
-template <typename T, int RB, int B>
-__device__ __forceinline__ void r_u(RegV<T, RB>& a, const T* __restrict__ c) {
-  const T u00r = c[0], u00i = c[1], u01r = c[2], u01i = c[3];
-  const T u10r = c[4], u10i = c[5], u11r = c[6], u11i = c[7];
-#pragma unroll
-  for (int j = 0; j < (1 << RB); ++j) {
-    if (j & (1 << B)) continue;
-    const int k = j | (1 << B);
-    const T px = a[2 * j], py = a[2 * j + 1], qx = a[2 * k], qy = a[2 * k + 1];
-    a[2 * j] = u00r * px - u00i * py + u01r * qx - u01i * qy;
-    a[2 * j + 1] = u00r * py + u00i * px + u01r * qy + u01i * qx;
-    a[2 * k] = u10r * px - u10i * py + u11r * qx - u11i * qy;
-    a[2 * k + 1] = u10r * py + u10i * px + u11r * qy + u11i * qx;
-  }
-}
-
-template <typename T, int RB, int B>
-__device__ __forceinline__ void r_r(RegV<T, RB>& a, const T* __restrict__ c) {
-  const T u00 = c[0], u01 = c[1], u10 = c[2], u11 = c[3];
-#pragma unroll
-  for (int j = 0; j < (1 << RB); ++j) {
-    if (j & (1 << B)) continue;
-    const int k = j | (1 << B);
-    const T px = a[2 * j], py = a[2 * j + 1], qx = a[2 * k], qy = a[2 * k + 1];
-    a[2 * j] = u00 * px + u01 * qx;
-    a[2 * j + 1] = u00 * py + u01 * qy;
-    a[2 * k] = u10 * px + u11 * qx;
-    a[2 * k + 1] = u10 * py + u11 * qy;
-  }
-}
-
+// Every register operation reads one register set (a) and writes every
+// register of another (b).  The interpreter alternates the two sets from op
+// to op, so the switch over op kinds leaves its results where the next op
+// reads them.  (Updating one set in place made the compiler assign each
+// case's results to fresh registers and copy the whole set back after
+// every op: 32 moves per op for complex64 with 16 amplitudes a lane.)
 template <typename T>
 __device__ __forceinline__ void cmul(cplx<T>& v, T cr, T ci) {
   const cplx<T> p = v;
@@ -110,83 +85,123 @@ __device__ __forceinline__ void cmul(cplx<T>& v, T cr, T ci) {
   v.y = p.x * ci + p.y * cr;
 }
 
+// A register copy.  The empty asm keeps the compiler from merging the
+// copies of different cases (different register indices) into copies
+// through a selected address, which would move the register set to memory.
 template <typename T, int RB>
-__device__ __forceinline__ void cmul_at(RegV<T, RB>& a, int j, T cr, T ci) {
-  const T px = a[2 * j], py = a[2 * j + 1];
-  a[2 * j] = px * cr - py * ci;
-  a[2 * j + 1] = px * ci + py * cr;
+__device__ __forceinline__ void cp_at(const RegV<T, RB>& a, RegV<T, RB>& b, int j, int k) {
+  T x = a[2 * k], y = a[2 * k + 1];
+  asm volatile("" : "+v"(x), "+v"(y));
+  b[2 * j] = x;
+  b[2 * j + 1] = y;
 }
 
 template <typename T, int RB>
-__device__ __forceinline__ void swap_at(RegV<T, RB>& a, int j, int k) {
-  const T tx = a[2 * j], ty = a[2 * j + 1];
-  a[2 * j] = a[2 * k];
-  a[2 * j + 1] = a[2 * k + 1];
-  a[2 * k] = tx;
-  a[2 * k + 1] = ty;
+__device__ __forceinline__ void cmul_at(const RegV<T, RB>& a, RegV<T, RB>& b, int j, T cr, T ci) {
+  const T px = a[2 * j], py = a[2 * j + 1];
+  b[2 * j] = px * cr - py * ci;
+  b[2 * j + 1] = px * ci + py * cr;
 }
 
 template <typename T, int RB, int B>
-__device__ __forceinline__ void r_d(RegV<T, RB>& a, const T* __restrict__ c) {
-  const T d0r = c[0], d0i = c[1], d1r = c[2], d1i = c[3];
+__device__ __forceinline__ void r_u(const RegV<T, RB>& a, RegV<T, RB>& b, const T* __restrict__ c) {
+  const T u00r = c[0], u00i = c[1], u01r = c[2], u01i = c[3];
+  const T u10r = c[4], u10i = c[5], u11r = c[6], u11i = c[7];
 #pragma unroll
   for (int j = 0; j < (1 << RB); ++j) {
-    if (j & (1 << B)) cmul_at<T, RB>(a, j, d1r, d1i);
-    else cmul_at<T, RB>(a, j, d0r, d0i);
+    if (j & (1 << B)) continue;
+    const int k = j | (1 << B);
+    const T px = a[2 * j], py = a[2 * j + 1], qx = a[2 * k], qy = a[2 * k + 1];
+    b[2 * j] = u00r * px - u00i * py + u01r * qx - u01i * qy;
+    b[2 * j + 1] = u00r * py + u00i * px + u01r * qy + u01i * qx;
+    b[2 * k] = u10r * px - u10i * py + u11r * qx - u11i * qy;
+    b[2 * k + 1] = u10r * py + u10i * px + u11r * qy + u11i * qx;
   }
 }
 
 template <typename T, int RB, int B>
-__device__ __forceinline__ void r_d1(RegV<T, RB>& a, const T* __restrict__ c) {
-  const T d1r = c[0], d1i = c[1];
+__device__ __forceinline__ void r_r(const RegV<T, RB>& a, RegV<T, RB>& b, const T* __restrict__ c) {
+  const T u00 = c[0], u01 = c[1], u10 = c[2], u11 = c[3];
 #pragma unroll
-  for (int j = 0; j < (1 << RB); ++j)
-    if (j & (1 << B)) cmul_at<T, RB>(a, j, d1r, d1i);
+  for (int j = 0; j < (1 << RB); ++j) {
+    if (j & (1 << B)) continue;
+    const int k = j | (1 << B);
+    const T px = a[2 * j], py = a[2 * j + 1], qx = a[2 * k], qy = a[2 * k + 1];
+    b[2 * j] = u00 * px + u01 * qx;
+    b[2 * j + 1] = u00 * py + u01 * qy;
+    b[2 * k] = u10 * px + u11 * qx;
+    b[2 * k + 1] = u10 * py + u11 * qy;
+  }
 }
 
 template <typename T, int RB, int B>
-__device__ __forceinline__ void r_x(RegV<T, RB>& a) {
+__device__ __forceinline__ void r_d(const RegV<T, RB>& a, RegV<T, RB>& b, const T* __restrict__ c) {
+  const T d0r = c[0], d0i = c[1], d1r = c[2], d1i = c[3];
 #pragma unroll
-  for (int j = 0; j < (1 << RB); ++j)
-    if (!(j & (1 << B))) swap_at<T, RB>(a, j, j | (1 << B));
+  for (int j = 0; j < (1 << RB); ++j) {
+    if (j & (1 << B)) cmul_at<T, RB>(a, b, j, d1r, d1i);
+    else cmul_at<T, RB>(a, b, j, d0r, d0i);
+  }
+}
+
+template <typename T, int RB, int B>
+__device__ __forceinline__ void r_d1(const RegV<T, RB>& a, RegV<T, RB>& b, const T* __restrict__ c) {
+  const T d1r = c[0], d1i = c[1];
+#pragma unroll
+  for (int j = 0; j < (1 << RB); ++j) {
+    if (j & (1 << B)) cmul_at<T, RB>(a, b, j, d1r, d1i);
+    else cp_at<T, RB>(a, b, j, j);
+  }
+}
+
+template <typename T, int RB, int B>
+__device__ __forceinline__ void r_x(const RegV<T, RB>& a, RegV<T, RB>& b) {
+#pragma unroll
+  for (int j = 0; j < (1 << RB); ++j) cp_at<T, RB>(a, b, j, j ^ (1 << B));
 }
 
 template <typename T, int RB, int C, int G>
-__device__ __forceinline__ void r_cx(RegV<T, RB>& a) {
+__device__ __forceinline__ void r_cx(const RegV<T, RB>& a, RegV<T, RB>& b) {
 #pragma unroll
-  for (int j = 0; j < (1 << RB); ++j)
-    if ((j & (1 << C)) && !(j & (1 << G))) swap_at<T, RB>(a, j, j | (1 << G));
+  for (int j = 0; j < (1 << RB); ++j) cp_at<T, RB>(a, b, j, (j & (1 << C)) ? j ^ (1 << G) : j);
 }
 
 template <typename T, int RB, int B0, int B1>
-__device__ __forceinline__ void r_swap(RegV<T, RB>& a) {
+__device__ __forceinline__ void r_swap(const RegV<T, RB>& a, RegV<T, RB>& b) {
 #pragma unroll
-  for (int j = 0; j < (1 << RB); ++j)
-    if ((j & (1 << B0)) && !(j & (1 << B1))) swap_at<T, RB>(a, j, j ^ (1 << B0) ^ (1 << B1));
+  for (int j = 0; j < (1 << RB); ++j) {
+    const int k = ((j >> B0 & 1) != (j >> B1 & 1)) ? j ^ (1 << B0) ^ (1 << B1) : j;
+    cp_at<T, RB>(a, b, j, k);
+  }
 }
 
 template <typename T, int RB, int B0, int B1>
-__device__ __forceinline__ void r_cz(RegV<T, RB>& a) {
+__device__ __forceinline__ void r_cz(const RegV<T, RB>& a, RegV<T, RB>& b) {
 #pragma unroll
-  for (int j = 0; j < (1 << RB); ++j)
+  for (int j = 0; j < (1 << RB); ++j) {
     if ((j & (1 << B0)) && (j & (1 << B1))) {
-      a[2 * j] = -a[2 * j];
-      a[2 * j + 1] = -a[2 * j + 1];
+      b[2 * j] = -a[2 * j];
+      b[2 * j + 1] = -a[2 * j + 1];
+    } else {
+      cp_at<T, RB>(a, b, j, j);
     }
+  }
 }
 
 template <typename T, int RB, int B0, int B1>
-__device__ __forceinline__ void r_cp(RegV<T, RB>& a, const T* __restrict__ c) {
+__device__ __forceinline__ void r_cp(const RegV<T, RB>& a, RegV<T, RB>& b, const T* __restrict__ c) {
   const T cr = c[0], ci = c[1];
 #pragma unroll
-  for (int j = 0; j < (1 << RB); ++j)
-    if ((j & (1 << B0)) && (j & (1 << B1))) cmul_at<T, RB>(a, j, cr, ci);
+  for (int j = 0; j < (1 << RB); ++j) {
+    if ((j & (1 << B0)) && (j & (1 << B1))) cmul_at<T, RB>(a, b, j, cr, ci);
+    else cp_at<T, RB>(a, b, j, j);
+  }
 }
 
 // Dense 4 x 4 on bits B0 < B1: y = M x over every quad of amplitudes that
 // differ only in those bits (index within the quad = bit B0 + 2 bit B1).
 template <typename T, int RB, int B0, int B1>
-__device__ __forceinline__ void r_u2(RegV<T, RB>& a, const T* __restrict__ c) {
+__device__ __forceinline__ void r_u2(const RegV<T, RB>& a, RegV<T, RB>& b, const T* __restrict__ c) {
 #pragma unroll
   for (int j = 0; j < (1 << RB); ++j) {
     if ((j >> B0 & 1) || (j >> B1 & 1)) continue;
@@ -207,49 +222,51 @@ __device__ __forceinline__ void r_u2(RegV<T, RB>& a, const T* __restrict__ c) {
         yr += m[2 * k] * xr[k] - m[2 * k + 1] * xi[k];
         yi += m[2 * k] * xi[k] + m[2 * k + 1] * xr[k];
       }
-      a[2 * ix[i]] = yr;
-      a[2 * ix[i] + 1] = yi;
+      b[2 * ix[i]] = yr;
+      b[2 * ix[i] + 1] = yi;
     }
   }
 }
 
+// b = op(a).
 template <typename T, int RB>
-__device__ __forceinline__ void apply_op(RegV<T, RB>& a, const OpDesc<T>* __restrict__ op) {
+__device__ __forceinline__ void apply_op(const RegV<T, RB>& a, RegV<T, RB>& b,
+                                         const OpDesc<T>* __restrict__ op) {
   const int kind = __builtin_amdgcn_readfirstlane(op->kind);
   const int b0 = __builtin_amdgcn_readfirstlane(op->b0);
   const int b1 = __builtin_amdgcn_readfirstlane(op->b1);
   const T* c = op->c;
   switch (kind) {
-    case OP_U: for_bit<RB>(b0, [&](auto B) __attribute__((always_inline)) { r_u<T, RB, decltype(B)::value>(a, c); }); break;
-    case OP_R: for_bit<RB>(b0, [&](auto B) __attribute__((always_inline)) { r_r<T, RB, decltype(B)::value>(a, c); }); break;
-    case OP_D: for_bit<RB>(b0, [&](auto B) __attribute__((always_inline)) { r_d<T, RB, decltype(B)::value>(a, c); }); break;
-    case OP_D1: for_bit<RB>(b0, [&](auto B) __attribute__((always_inline)) { r_d1<T, RB, decltype(B)::value>(a, c); }); break;
-    case OP_X: for_bit<RB>(b0, [&](auto B) __attribute__((always_inline)) { r_x<T, RB, decltype(B)::value>(a); }); break;
+    case OP_U: for_bit<RB>(b0, [&](auto B) __attribute__((always_inline)) { r_u<T, RB, decltype(B)::value>(a, b, c); }); break;
+    case OP_R: for_bit<RB>(b0, [&](auto B) __attribute__((always_inline)) { r_r<T, RB, decltype(B)::value>(a, b, c); }); break;
+    case OP_D: for_bit<RB>(b0, [&](auto B) __attribute__((always_inline)) { r_d<T, RB, decltype(B)::value>(a, b, c); }); break;
+    case OP_D1: for_bit<RB>(b0, [&](auto B) __attribute__((always_inline)) { r_d1<T, RB, decltype(B)::value>(a, b, c); }); break;
+    case OP_X: for_bit<RB>(b0, [&](auto B) __attribute__((always_inline)) { r_x<T, RB, decltype(B)::value>(a, b); }); break;
     case OP_CX:
       for_pair<RB>(b0, b1, [&](auto B0, auto B1) __attribute__((always_inline)) {
-        r_cx<T, RB, decltype(B0)::value, decltype(B1)::value>(a);
+        r_cx<T, RB, decltype(B0)::value, decltype(B1)::value>(a, b);
       });
       break;
     case OP_CZ:
       for_pair<RB>(b0, b1, [&](auto B0, auto B1) __attribute__((always_inline)) {
-        r_cz<T, RB, decltype(B0)::value, decltype(B1)::value>(a);
+        r_cz<T, RB, decltype(B0)::value, decltype(B1)::value>(a, b);
       });
       break;
     case OP_CP:
       for_pair<RB>(b0, b1, [&](auto B0, auto B1) __attribute__((always_inline)) {
-        r_cp<T, RB, decltype(B0)::value, decltype(B1)::value>(a, c);
+        r_cp<T, RB, decltype(B0)::value, decltype(B1)::value>(a, b, c);
       });
       break;
     case OP_SWAP:
       for_pair<RB>(b0, b1, [&](auto B0, auto B1) __attribute__((always_inline)) {
-        r_swap<T, RB, decltype(B0)::value, decltype(B1)::value>(a);
+        r_swap<T, RB, decltype(B0)::value, decltype(B1)::value>(a, b);
       });
       break;
     case OP_U2:
       if constexpr (RB >= 2) {
         for_pair<RB>(b0, b1, [&](auto B0, auto B1) __attribute__((always_inline)) {
           if constexpr (decltype(B0)::value < decltype(B1)::value)
-            r_u2<T, RB, decltype(B0)::value, decltype(B1)::value>(a, c);
+            r_u2<T, RB, decltype(B0)::value, decltype(B1)::value>(a, b, c);
           else
             __builtin_unreachable();
         });
@@ -355,7 +372,7 @@ part_pass_kernel(cplx<T>* __restrict__ st, const IPart* __restrict__ pd,
   }
   // (no software prefetch of the next tile: with up to 1024 threads a lane
   // has 128 VGPRs, and a second tile's registers would spill)
-  RegV<T, RB> a;
+  RegV<T, RB> a, b;
   for (; tile < end; tile += step) {
     cplx<T>* const base = st + tile_base32(tile, pd->tq, m);
     if (active) tile_io<T, RB, false>(base + ld_lane, a, pd->load.reg);
@@ -389,8 +406,17 @@ part_pass_kernel(cplx<T>* __restrict__ st, const IPart* __restrict__ pd,
           a[2 * j + 1] = v.y;
         }
       }
+      // two ops an iteration: a -> b, then b -> a
       const int o1 = e.op_end;
-      for (int o = e.op_begin; o < o1; ++o) apply_op<T, RB>(a, ops + o);
+      int o = e.op_begin;
+      for (; o + 1 < o1; o += 2) {
+        apply_op<T, RB>(a, b, ops + o);
+        apply_op<T, RB>(b, a, ops + o + 1);
+      }
+      if (o < o1) {
+        apply_op<T, RB>(a, b, ops + o);
+        a = b;
+      }
     }
     // ---- scatter (last entry is the store layout)
     if (active) tile_io<T, RB, true>(base + sv_lane, a, pd->store.reg);
