@@ -2,8 +2,10 @@
 """Benchmark of the partitioned state-vector hot path on one MI355X.
 
 A step is one pass of the whole path over one circuit: the gate list is
-loaded, partitioned (greedy ready-set partitioner; --strategy picks Nat,
-DFS or dagP of Sec. IV.B instead) and compiled (the specialized part
+loaded, partitioned (closure partitioner: each part's qubit set chosen so
+that the gates it can take from the current front weigh most; --strategy
+picks Nat, DFS or dagP of Sec. IV.B, or the greedy ready-set partitioner,
+instead) and compiled (the specialized part
 kernels come from the kernel cache after the first pass), every part is
 applied as one in-place Gather-Execute-Scatter sweep of a state resident in
 HBM (Alg. 1), and the FP64 norm is read back.  Default workload: a 33-qubit
@@ -366,7 +368,7 @@ def run_dressed(args, buf, stream, log):
     return rows
 
 
-def run_qft(buf, stream, log, strategy="greedy", trials=256):
+def run_qft(buf, stream, log, strategy="closure", trials=16):
     """32-qubit QFT (H + controlled-phase ladder + swaps) on a random basis
     state, dagP k = 7: gate-by-gate specialized kernels (a) vs the fused dense
     unitary on matrix cores (b) vs AUTO; sampled amplitudes against the closed
@@ -646,9 +648,10 @@ def main() -> int:
     ap.add_argument("--gates", type=int, default=1000)
     ap.add_argument("--k", type=int, default=7)
     ap.add_argument("--dtype", default="c128", choices=["c64", "c128"])
-    ap.add_argument("--strategy", default="greedy", choices=["nat", "dfs", "dagp", "greedy"])
-    ap.add_argument("--trials", type=int, default=256,
-                    help="orders (DFS) or tie-break draws (greedy) tried per partition")
+    ap.add_argument("--strategy", default="closure", choices=["nat", "dfs", "dagp", "greedy", "closure"])
+    ap.add_argument("--trials", type=int, default=None,
+                    help="orders (DFS) or tie-break draws (greedy, closure) tried per partition "
+                         "(default: 16 for closure, else 256)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--mode", default="part_spec", choices=["part_lds", "part_spec", "auto"])
     ap.add_argument("--gpp-gates", type=int, default=24,
@@ -682,6 +685,8 @@ def main() -> int:
     ap.add_argument("--dressed-only", action="store_true",
                     help="run only the dense five-qubit-part comparison (for kernel profiles)")
     args = ap.parse_args()
+    if args.trials is None:
+        args.trials = 16 if args.strategy == "closure" else 256
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

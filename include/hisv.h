@@ -96,7 +96,13 @@ typedef struct {
  * adds the fewest new qubits, closing when none fits; trial 0 breaks ties by
  * gate index, the other trials by seeded random keys; fewest parts win.
  * Its parts are contiguous pieces of a topological order, hence acyclic. */
-typedef enum { HS_PART_NAT = 0, HS_PART_DFS = 1, HS_PART_DAGP = 2, HS_PART_GREEDY = 3 } hs_strategy;
+typedef enum {
+  HS_PART_NAT = 0,
+  HS_PART_DFS = 1,
+  HS_PART_DAGP = 2,
+  HS_PART_GREEDY = 3,
+  HS_PART_CLOSURE = 4
+} hs_strategy;
 
 /* How hs_simulate applies a plan:
  *   GATE_PER_PASS -- ignore the partition; one sweep of the state per gate
@@ -214,8 +220,14 @@ hs_status hs_circuit_destroy(hs_circuit c);
 /* Partition the circuit's gate DAG into acyclic parts of at most k qubits
  * (Sec. IV.A conditions i-ii), minimising the part count heuristically
  * (condition iii).  `seed` and `trials` drive DFS (trial 0 is the natural
- * order, so DFS never returns more parts than Nat) and GREEDY, and are
- * ignored by Nat.
+ * order, so DFS never returns more parts than Nat), GREEDY and CLOSURE,
+ * and are ignored by Nat.
+ * Strategies: NAT and DFS cut one topological order (Sec. IV.B.1-2); DAGP
+ * bisects the DAG (Sec. IV.B.3); GREEDY grows each part one ready gate at
+ * a time, fewest new qubits first; CLOSURE fixes each part by a qubit set
+ * chosen so that the gates it can take from the current front (its
+ * closure) weigh most, then improved by one-qubit exchanges (its trials run
+ * on up to 8 host threads).
  * Parts are numbered in a topological order of the part-graph.
  * HS_E_ARITY_GT_K if a gate is wider than k; HS_E_ARG if k < 1. */
 hs_status hs_partition(hs_circuit c, int k, hs_strategy strategy, uint64_t seed,
@@ -409,7 +421,7 @@ hs_status hs_server_create(size_t budget_bytes, int num_streams, hs_server* out)
 hs_status hs_server_clock(hs_server sv, double* seconds);
 
 /* Queue a circuit (copied and validated here) to be partitioned with limit
- * k by `strategy` (DFS and GREEDY with 16 trials), simulated from
+ * k by `strategy` (DFS and GREEDY with 16 trials, CLOSURE with 4), simulated from
  * |init_basis> in `dtype`, and kept resident until released.  `arrival_s`
  * is the request's arrival time on the server clock, where its latency
  * starts (negative: the time of this call; HS_E_ARG if it lies after the

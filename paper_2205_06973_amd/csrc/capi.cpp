@@ -361,6 +361,10 @@ hs_status hs_partition(hs_circuit c, int k, hs_strategy strategy, uint64_t seed,
       CHECK_ARG(trials >= 1, "GREEDY needs trials >= 1");
       partition_greedy(c->gates, dag, k, seed, trials, &part);
       break;
+    case HS_PART_CLOSURE:
+      CHECK_ARG(trials >= 1, "CLOSURE needs trials >= 1");
+      partition_closure(c->gates, dag, k, seed, trials, &part);
+      break;
     default: return fail(HS_E_ARG, "unknown strategy %d", (int)strategy);
   }
   auto* p = new hs_plan_();
@@ -397,6 +401,10 @@ hs_status hs_partition_multilevel(hs_circuit c, int tile_qubits, int pad_qubits,
     case HS_PART_GREEDY:
       CHECK_ARG(trials >= 1, "GREEDY needs trials >= 1");
       partition_greedy(c->gates, dag, tile_qubits, seed, trials, &part, pad);
+      break;
+    case HS_PART_CLOSURE:
+      CHECK_ARG(trials >= 1, "CLOSURE needs trials >= 1");
+      partition_closure(c->gates, dag, tile_qubits, seed, trials, &part, pad);
       break;
     default: return fail(HS_E_ARG, "unknown strategy %d", (int)strategy);
   }

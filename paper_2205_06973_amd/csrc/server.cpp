@@ -117,6 +117,7 @@ hs_status prepare(hs_server_* sv, Request* r, hipStream_t stream) {
     case HS_PART_DFS: partition_dfs(gs, dag, r->k, seed, 16, &part); break;
     case HS_PART_DAGP: partition_dagp(gs, dag, r->n, r->k, seed, &part); break;
     case HS_PART_GREEDY: partition_greedy(gs, dag, r->k, seed, 16, &part); break;
+    case HS_PART_CLOSURE: partition_closure(gs, dag, r->k, seed, 4, &part); break;
     default: return fail(HS_E_ARG, "unknown strategy %d", (int)r->strategy);
   }
   auto plan = std::make_unique<Plan>();
@@ -356,7 +357,7 @@ hs_status hs_server_submit(hs_server sv, int n, const hs_gate* gates, size_t cou
   if (dtype != HS_C64 && dtype != HS_C128) return fail(HS_E_ARG, "bad dtype");
   if (init_basis >= (uint64_t(1) << n)) return fail(HS_E_ARG, "basis index outside the state");
   if (k < 1) return fail(HS_E_ARG, "k = %d < 1", k);
-  if (strategy < HS_PART_NAT || strategy > HS_PART_GREEDY)
+  if (strategy < HS_PART_NAT || strategy > HS_PART_CLOSURE)
     return fail(HS_E_ARG, "unknown strategy %d", (int)strategy);
   if (arrival_s > t_call) return fail(HS_E_ARG, "arrival time lies in the future");
   auto r = std::make_unique<Request>();

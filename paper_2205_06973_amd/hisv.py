@@ -24,7 +24,7 @@ STATUS = {0: "HS_OK", 1: "HS_E_ARG", 2: "HS_E_QUBIT_RANGE", 3: "HS_E_ARITY_GT_K"
 DTYPES = {"c64": 0, "c128": 1}
 KINDS = {"h": 0, "x": 1, "y": 2, "z": 3, "s": 4, "t": 5, "rx": 6, "ry": 7, "rz": 8,
          "p": 9, "u3": 10, "cx": 11, "cz": 12, "cp": 13, "swap": 14, "ccx": 15, "cswap": 16}
-STRATEGIES = {"nat": 0, "dfs": 1, "dagp": 2, "greedy": 3}
+STRATEGIES = {"nat": 0, "dfs": 1, "dagp": 2, "greedy": 3, "closure": 4}
 EXEC = {"gate_per_pass": 0, "part_lds": 1, "part_fused": 2, "auto": 3, "part_spec": 4}
 
 

@@ -28,7 +28,7 @@ def part_limit(n: int, dtype: str) -> int:
 
 
 def run_stream(requests, budget_bytes: int = 0, num_streams: int = 4, read_states: bool = False,
-               time_scale: float = 1.0, strategy: str = "greedy"):
+               time_scale: float = 1.0, strategy: str = "closure"):
     """Submit `requests` (workloads.Request) at their arrival times.
 
     Returns a dict: per-request latency (s) and its four parts (host queue,

@@ -43,12 +43,13 @@ def simulate(n, gates, dtype, k, strategy, mode="part_spec", init=0, extra=None)
     buf = torch.empty(1 << n, dtype=TDT[dtype], device="cuda")
     st = hisv.State.wrap_tensor(buf, torch.cuda.current_stream())
     st.set_basis(init)
+    trials = 16 if strategy.endswith("closure") else 32  # closure: the bench's draws
     for gs in [gates] + ([extra] if extra else []):
         if strategy.startswith("ml-"):  # multi-level: parts fill the kernel tile
             plan = hisv.Plan.partition_multilevel(hisv.Circuit(n, gs), strategy=strategy[3:],
-                                                  dtype=dtype, seed=0, trials=32)
+                                                  dtype=dtype, seed=0, trials=trials)
         else:
-            plan = hisv.Plan.partition(hisv.Circuit(n, gs), k, strategy, seed=0, trials=32)
+            plan = hisv.Plan.partition(hisv.Circuit(n, gs), k, strategy, seed=0, trials=trials)
         if mode == "auto_spec":  # AUTO over specialized gate-by-gate and fused kernels
             plan.specialize(dtype)
             st.simulate(plan, "auto")
@@ -113,7 +114,8 @@ def test_layered28_round_trip(dtype):
 
 @pytest.mark.parametrize("strategy,mode", [("dagp", "part_spec"), ("ml-dagp", "part_spec"),
                                            ("greedy", "part_spec"), ("ml-greedy", "part_spec"),
-                                           ("greedy", "part_fused"), ("greedy", "auto_spec")])
+                                           ("closure", "part_spec"), ("ml-closure", "part_spec"),
+                                           ("greedy", "part_fused"), ("closure", "auto_spec")])
 def test_qft32_closed_form(strategy, mode):
     """The 32-qubit QFT on a random basis state (32 GiB complex64), k = 7:
     gate-by-gate specialized kernels, the fused dense-unitary kernels on
@@ -131,7 +133,9 @@ def test_qft32_closed_form(strategy, mode):
 
 @pytest.mark.parametrize("n,dtype,strategy", [(34, "c64", "dfs"), (33, "c128", "dfs"),
                                               (34, "c64", "ml-dfs"), (33, "c128", "ml-dfs"),
-                                              (34, "c64", "greedy"), (33, "c128", "ml-greedy")])
+                                              (34, "c64", "greedy"), (33, "c128", "ml-greedy"),
+                                              (34, "c64", "closure"), (33, "c128", "closure"),
+                                              (34, "c64", "ml-closure")])
 def test_random34_product_block(n, dtype, strategy):
     gates = wl.product_block_circuit(n, 1000, wl.RANDOM34_KINDS, seed=5)
     st, buf = simulate(n, gates, dtype, 7, strategy)
@@ -149,7 +153,7 @@ def test_random34_product_block_k_and_interpreter(k, mode):
     variant of its gate distribution."""
     n, dtype = 34, "c64"
     gates = wl.product_block_circuit(n, 1000, wl.RANDOM34_KINDS, seed=5)
-    st, buf = simulate(n, gates, dtype, k, "greedy", mode=mode)
+    st, buf = simulate(n, gates, dtype, k, "closure", mode=mode)
     pe, po = product_factors(n, gates)
     idx = sample_indices(n, 1 << 20, 6 + k)
     d = np.abs(st.amplitudes_at(idx) - product_amp(idx, n, pe, po))
@@ -166,13 +170,14 @@ def headline22():
     return n, gates, sv.simulate(n, gates)
 
 
+@pytest.mark.parametrize("strategy", ["closure", "greedy"])
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
-def test_headline_configuration_full_vector(dtype, headline22):
-    """The headline launch configuration -- greedy partition, k = 7,
-    specialized kernels -- against the oracle on every amplitude at 22
-    qubits (max |d| and ||d||_2 bars)."""
+def test_headline_configuration_full_vector(dtype, strategy, headline22):
+    """The headline launch configuration -- closure partition (and the
+    greedy one), k = 7, specialized kernels -- against the oracle on every
+    amplitude at 22 qubits (max |d| and ||d||_2 bars)."""
     n, gates, want = headline22
-    st, buf = simulate(n, gates, dtype, 7, "greedy")
+    st, buf = simulate(n, gates, dtype, 7, strategy)
     got = st.amplitudes()
     d = np.abs(got - want)
     report(f"random{n} full vector {dtype}", d, n)
@@ -201,8 +206,8 @@ def test_largest_state_round_trip(n, dtype):
 @pytest.mark.parametrize("n,dtype", [(34, "c64"), (33, "c128")])
 def test_random34_round_trip(n, dtype):
     _, gates = wl.random34(0, n=n)
-    # the headline configuration: greedy partition, k = 7, specialized kernels
-    st, buf = simulate(n, gates, dtype, 7, "greedy", extra=sv.inverse_circuit(gates))
+    # the headline configuration: closure partition, k = 7, specialized kernels
+    st, buf = simulate(n, gates, dtype, 7, "closure", extra=sv.inverse_circuit(gates))
     idx = sample_indices(n, 1 << 14, 7)
     got = st.amplitudes_at(idx)
     want = np.zeros(idx.size, dtype=np.complex128)

@@ -83,6 +83,7 @@ def test_random12_k4(dtype, mode):
     (1, 1, "nat"), (2, 2, "nat"), (3, 3, "dfs"), (5, 2, "dfs"), (6, 6, "nat"), (7, 3, "dfs"),
     (9, 5, "dfs"), (10, 7, "dfs"), (12, 12, "nat"), (13, 6, "dfs"), (14, 8, "dfs"),
     (16, 4, "nat"), (17, 7, "dfs"), (11, 6, "greedy"), (15, 7, "greedy"),
+    (12, 5, "closure"), (16, 7, "closure"),
 ])
 @pytest.mark.parametrize("mode", ["part_lds", "part_spec"])
 def test_random_all_kinds(n, k, strategy, dtype, mode):
