@@ -220,14 +220,15 @@ hs_status hs_circuit_destroy(hs_circuit c);
 /* Partition the circuit's gate DAG into acyclic parts of at most k qubits
  * (Sec. IV.A conditions i-ii), minimising the part count heuristically
  * (condition iii).  `seed` and `trials` drive DFS (trial 0 is the natural
- * order, so DFS never returns more parts than Nat), GREEDY and CLOSURE,
- * and are ignored by Nat.
+ * order, so DFS never returns more parts than Nat) and GREEDY; `trials` is
+ * CLOSURE's beam width; Nat ignores both.
  * Strategies: NAT and DFS cut one topological order (Sec. IV.B.1-2); DAGP
  * bisects the DAG (Sec. IV.B.3); GREEDY grows each part one ready gate at
  * a time, fewest new qubits first; CLOSURE fixes each part by a qubit set
- * chosen so that the gates it can take from the current front (its
- * closure) weigh most, then improved by one-qubit exchanges (its trials run
- * on up to 8 host threads).
+ * chosen so that the two-qubit gates it can take from the current front
+ * (its closure) are most, improved by one-qubit exchanges, and with
+ * trials > 1 searches a beam of that many partial partitions (on up to 8
+ * host threads; the result does not depend on their number).
  * Parts are numbered in a topological order of the part-graph.
  * HS_E_ARITY_GT_K if a gate is wider than k; HS_E_ARG if k < 1. */
 hs_status hs_partition(hs_circuit c, int k, hs_strategy strategy, uint64_t seed,
@@ -421,7 +422,7 @@ hs_status hs_server_create(size_t budget_bytes, int num_streams, hs_server* out)
 hs_status hs_server_clock(hs_server sv, double* seconds);
 
 /* Queue a circuit (copied and validated here) to be partitioned with limit
- * k by `strategy` (DFS and GREEDY with 16 trials, CLOSURE with 4), simulated from
+ * k by `strategy` (DFS and GREEDY with 16 trials, CLOSURE with beam width 1), simulated from
  * |init_basis> in `dtype`, and kept resident until released.  `arrival_s`
  * is the request's arrival time on the server clock, where its latency
  * starts (negative: the time of this call; HS_E_ARG if it lies after the

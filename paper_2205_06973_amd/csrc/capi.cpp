@@ -363,7 +363,7 @@ hs_status hs_partition(hs_circuit c, int k, hs_strategy strategy, uint64_t seed,
       break;
     case HS_PART_CLOSURE:
       CHECK_ARG(trials >= 1, "CLOSURE needs trials >= 1");
-      partition_closure(c->gates, dag, k, seed, trials, &part);
+      partition_closure(c->gates, dag, k, trials, &part);
       break;
     default: return fail(HS_E_ARG, "unknown strategy %d", (int)strategy);
   }
@@ -404,7 +404,7 @@ hs_status hs_partition_multilevel(hs_circuit c, int tile_qubits, int pad_qubits,
       break;
     case HS_PART_CLOSURE:
       CHECK_ARG(trials >= 1, "CLOSURE needs trials >= 1");
-      partition_closure(c->gates, dag, tile_qubits, seed, trials, &part, pad);
+      partition_closure(c->gates, dag, tile_qubits, trials, &part, pad);
       break;
     default: return fail(HS_E_ARG, "unknown strategy %d", (int)strategy);
   }

@@ -12,6 +12,8 @@
 // part-graph topologically.
 #include <algorithm>
 #include <climits>
+#include <condition_variable>
+#include <mutex>
 #include <thread>
 
 #include "hisv_internal.h"
@@ -182,10 +184,19 @@ int partition_greedy(const std::vector<Gate>& gates, const Dag& dag, int k, uint
 }
 
 namespace {
-// One closure-partition run (see partition_closure).
-class ClosureRun {
+// Closure parts and the beam search over them (see partition_closure).
+class ClosureSearch {
  public:
-  ClosureRun(const std::vector<Gate>& gates, const Dag& dag, int k, uint64_t pad)
+  // A partial partition: the gates placed so far.
+  struct Node {
+    std::vector<int> indeg;      // unplaced predecessors of each gate
+    std::vector<int> ready;      // unplaced gates with none, ascending
+    std::vector<int32_t> part;   // part id per gate, -1 = unplaced
+    int placed = 0;              // gates placed
+    int weight = 0;              // two-qubit gates placed
+  };
+
+  ClosureSearch(const std::vector<Gate>& gates, const Dag& dag, int k, uint64_t pad)
       : dag_(dag), k_(k), pad_(pad), G_(dag.G) {
     mask_.resize(G_);
     weight_.resize(G_);
@@ -197,55 +208,84 @@ class ClosureRun {
     tstamp_.assign(G_, 0);
   }
 
-  // Parts of one run with tie-break keys from `rng` (none: the first
-  // candidate wins ties).
-  int run(Rng* rng, std::vector<int32_t>* part) {
-    part->assign(G_, -1);
-    indeg_.resize(G_);
-    ready_.clear();
+  Node root() const {
+    Node r;
+    r.indeg.resize(G_);
+    r.part.assign(G_, -1);
     for (int i = 0; i < G_; ++i) {
-      indeg_[i] = (int)dag_.pred[i].size();
-      if (!indeg_[i]) ready_.push_back(i);
+      r.indeg[i] = (int)dag_.pred[i].size();
+      if (!r.indeg[i]) r.ready.push_back(i);
     }
-    int placed = 0, np = 0;
-    std::vector<int> take;
-    while (placed < G_) {
-      const uint64_t Q = choose(rng);
-      take.clear();
-      eval(Q, &take, nullptr);
-      if (take.empty()) return -1;  // cannot happen: every gate fits k with the padding
-      for (int i : take) {
-        (*part)[i] = np;
-        for (int s : dag_.succ[i]) --indeg_[s];
-      }
-      placed += (int)take.size();
-      ++np;
-      // the new front: untaken ready gates, then successors that became ready
-      next_.clear();
-      for (int i : ready_)
-        if ((*part)[i] < 0) next_.push_back(i);
-      for (int i : take)
-        for (int s : dag_.succ[i])
-          if (!indeg_[s] && (*part)[s] < 0) next_.push_back(s);
-      std::sort(next_.begin(), next_.end());
-      next_.erase(std::unique(next_.begin(), next_.end()), next_.end());
-      ready_.swap(next_);
-    }
-    return np;
+    return r;
   }
 
+  // Up to m distinct qubit sets for the next part of `nd`: the m best
+  // first steps of the growth, each grown and improved (m = 1: the plain
+  // closure rule).
+  void candidates(const Node& nd, int m, std::vector<uint64_t>* out) {
+    cur_ = &nd;
+    out->clear();
+    front_.clear();
+    eval(pad_, nullptr, &front_);
+    struct Seed {
+      int64_t sc;
+      size_t pos;
+      uint64_t set;
+    };
+    std::vector<Seed> seeds;
+    for (size_t r = 0; r < front_.size(); ++r) {
+      const uint64_t c = pad_ | mask_[front_[r]];
+      if (c == pad_ || __builtin_popcountll(c) > k_) continue;
+      bool dup = false;
+      for (const Seed& e : seeds) dup |= e.set == c;
+      if (dup) continue;
+      seeds.push_back({score(c), r, c});
+    }
+    std::stable_sort(seeds.begin(), seeds.end(), [](const Seed& x, const Seed& y) { return x.sc > y.sc; });
+    if (seeds.empty()) seeds.push_back({0, 0, pad_});
+    for (size_t i = 0; i < seeds.size() && (int)out->size() < m; ++i) {
+      const uint64_t Q = improve(grow(seeds[i].set));
+      if (std::find(out->begin(), out->end(), Q) == out->end()) out->push_back(Q);
+    }
+  }
+
+  // `nd` with the closure of Q placed as part `id`.
+  Node apply(const Node& nd, uint64_t Q, int id) {
+    cur_ = &nd;
+    take_.clear();
+    eval(Q, &take_, nullptr);
+    Node r = nd;
+    for (int i : take_) {
+      r.part[i] = id;
+      r.weight += weight_[i];
+      for (int s : dag_.succ[i]) --r.indeg[s];
+    }
+    r.placed += (int)take_.size();
+    r.ready.clear();
+    for (int i : nd.ready)
+      if (r.part[i] < 0) r.ready.push_back(i);
+    for (int i : take_)
+      for (int s : dag_.succ[i])
+        if (!r.indeg[s] && r.part[s] < 0) r.ready.push_back(s);
+    std::sort(r.ready.begin(), r.ready.end());
+    r.ready.erase(std::unique(r.ready.begin(), r.ready.end()), r.ready.end());
+    return r;
+  }
+
+  int gates() const { return G_; }
+
  private:
-  // Weight of the closure of Q from the current front: the unplaced gates
-  // on qubits in Q whose predecessors are placed or in the closure.  Lists
-  // the closure in `take` and the gates just outside it (all predecessors
-  // placed or taken, some qubit outside Q) in `front`.
+  // Two-qubit weight of the closure of Q from the current node's front: the
+  // unplaced gates on qubits in Q whose predecessors are placed or taken.
+  // Lists the closure in `take` and the gates just outside it (predecessors
+  // placed or taken, a qubit outside Q) in `front`, in the order found.
   int eval(uint64_t Q, std::vector<int>* take, std::vector<int>* front) {
     if (++stamp_ == 0) {
       std::fill(tstamp_.begin(), tstamp_.end(), 0u);
       stamp_ = 1;
     }
     stack_.clear();
-    for (int i : ready_) {
+    for (int i : cur_->ready) {
       if (!(mask_[i] & ~Q)) stack_.push_back(i);
       else if (front) front->push_back(i);
     }
@@ -258,7 +298,7 @@ class ClosureRun {
       for (int s : dag_.succ[i]) {
         if (tstamp_[s] != stamp_) {
           tstamp_[s] = stamp_;
-          tin_[s] = indeg_[s];
+          tin_[s] = cur_->indeg[s];
         }
         if (--tin_[s] == 0) {
           if (!(mask_[s] & ~Q)) stack_.push_back(s);
@@ -269,34 +309,34 @@ class ClosureRun {
     return w;
   }
 
-  uint64_t choose(Rng* rng) {
-    // grow: add the qubits of the frontier gate whose closure weighs most;
-    // ties to fewer qubits, then to the earlier frontier gate (trial 0) or
-    // the lower random key
-    uint64_t Q = pad_;
+  // closure weight first, then fewer qubits
+  int64_t score(uint64_t Q) { return ((int64_t)eval(Q, nullptr, nullptr) << 8) - __builtin_popcountll(Q); }
+
+  // Add the qubits of the frontier gate whose closure scores best (ties to
+  // the earlier frontier gate) while any fits.
+  uint64_t grow(uint64_t Q) {
     for (;;) {
       front_.clear();
       eval(Q, nullptr, &front_);
       uint64_t best = Q;
       int64_t best_s = INT64_MIN;
-      uint64_t best_key = 0;
-      for (size_t r = 0; r < front_.size(); ++r) {
-        const int f = front_[r];
+      for (int f : front_) {
         const uint64_t c = Q | mask_[f];
         if (c == Q || __builtin_popcountll(c) > k_) continue;
-        const int64_t sc = ((int64_t)eval(c, nullptr, nullptr) << 8) - __builtin_popcountll(c);
-        const uint64_t key = rng ? rng->next() : (uint64_t)r;
-        if (sc > best_s || (sc == best_s && key < best_key)) {
+        const int64_t sc = score(c);
+        if (sc > best_s) {
           best_s = sc;
           best = c;
-          best_key = key;
         }
       }
-      if (best == Q) break;
+      if (best == Q) return Q;
       Q = best;
     }
-    // improve: exchange one qubit (never a padding qubit) while the closure
-    // gains weight; the candidates to bring in are the frontier's qubits
+  }
+
+  // Exchange one qubit (never a padding qubit; lowest bits first) for one of
+  // the frontier's while the closure gains weight.
+  uint64_t improve(uint64_t Q) {
     int cur = eval(Q, nullptr, nullptr);
     for (int round = 0; round < 4 * k_; ++round) {
       front_.clear();
@@ -327,8 +367,9 @@ class ClosureRun {
   const int k_;
   const uint64_t pad_;
   const int G_;
+  const Node* cur_ = nullptr;
   std::vector<uint64_t> mask_;
-  std::vector<int> weight_, indeg_, ready_, next_, front_, stack_, tin_;
+  std::vector<int> weight_, front_, take_, stack_, tin_;
   std::vector<uint32_t> tstamp_;
   uint32_t stamp_ = 0;
 };
@@ -338,50 +379,126 @@ class ClosureRun {
 // with the padding): it takes every unplaced gate on qubits in Q whose
 // predecessors are placed or taken -- the closure of Q from the current
 // front.  Q grows from the padding by the frontier gate whose qubits give
-// the closure with the most two-qubit gates (fewer qubits on ties), then
-// exchanges one qubit at a time, lowest bits first, while that count grows.
-// One-qubit gates do not count: any later part on their qubit takes them,
-// and counting them measured 2% more parts on random circuits.  Parts are
-// taken in order, so every edge runs forward and the part-graph is acyclic
-// (Sec. IV.A condition ii).  Trial 0 breaks the remaining ties to the
-// first frontier gate (ready gates in index order, then the gates the
-// closure frees, as it frees them), later trials by a seeded random key;
-// the fewest parts win, ties to the lowest trial.
-int partition_closure(const std::vector<Gate>& gates, const Dag& dag, int k, uint64_t seed,
-                      int trials, std::vector<int32_t>* part, uint64_t pad) {
-  const int T = std::max(1, trials);
-  const int nthreads = std::max(1, std::min({T, 8, (int)std::thread::hardware_concurrency()}));
-  std::vector<int> best_np(nthreads, -1);
-  std::vector<int> best_t(nthreads, -1);
-  std::vector<std::vector<int32_t>> best_part(nthreads);
-  auto worker = [&](int w) {
-    ClosureRun run(gates, dag, k, pad);
-    std::vector<int32_t> cand;
-    for (int t = w; t < T; t += nthreads) {
-      Rng rng(seed * 0x100000001B3ull + 0x51ull + (uint64_t)t);
-      const int np = run.run(t == 0 ? nullptr : &rng, &cand);
-      if (np > 0 && (best_np[w] < 0 || np < best_np[w])) {
-        best_np[w] = np;
-        best_t[w] = t;
-        best_part[w] = cand;
-      }
+// the closure with the most two-qubit gates (fewer qubits, then the earlier
+// frontier gate on ties), then exchanges one qubit at a time while that
+// count grows.  One-qubit gates do not count: any later part on their qubit
+// takes them, and counting them measured 2% more parts on random circuits.
+// Parts are taken in order, so every edge runs forward and the part-graph
+// is acyclic (Sec. IV.A condition ii).
+//
+// `width` > 1 runs a beam search: each of the `width` best partial
+// partitions (most two-qubit gates placed, then most gates) is extended by
+// up to four parts -- the growth started from each of its four best first
+// gates -- and the first partition to place every gate wins, unless the
+// plain rule (width 1) needs fewer parts.  The result does not depend on
+// the number of host threads.
+int partition_closure(const std::vector<Gate>& gates, const Dag& dag, int k, int width,
+                      std::vector<int32_t>* part, uint64_t pad) {
+  using Node = ClosureSearch::Node;
+  if (dag.G == 0) {
+    part->clear();
+    return 0;
+  }
+  const int B = std::max(1, width);
+  const int M = B > 1 ? 4 : 1;
+  // the beam's expansions run on up to 8 host threads, node i on thread i % T
+  const int T = std::max(1, std::min({B, 8, (int)std::thread::hardware_concurrency()}));
+  std::vector<ClosureSearch> cs(T, ClosureSearch(gates, dag, k, pad));
+  std::vector<Node> beam{cs[0].root()};
+  std::vector<std::vector<Node>> grown(B);
+  std::vector<std::vector<uint64_t>> qs(T);
+  int result = -1;
+  bool done = false;
+
+  auto expand = [&](int t, int id) {
+    for (size_t i = t; i < beam.size(); i += T) {
+      cs[t].candidates(beam[i], M, &qs[t]);
+      grown[i].clear();
+      for (uint64_t Q : qs[t]) grown[i].push_back(cs[t].apply(beam[i], Q, id));
     }
   };
-  if (nthreads == 1 || gates.size() < 64) {
-    for (int w = 0; w < nthreads; ++w) worker(w);
+  // the best `B` distinct expansions become the next beam; the first that
+  // places every gate ends the search
+  auto select = [&](int id) {
+    std::vector<Node> next;
+    for (size_t i = 0; i < beam.size(); ++i)
+      for (auto& nd : grown[i]) next.push_back(std::move(nd));
+    std::stable_sort(next.begin(), next.end(), [](const Node& x, const Node& y) {
+      return x.weight != y.weight ? x.weight > y.weight : x.placed > y.placed;
+    });
+    for (auto& nd : next)
+      if (nd.placed == dag.G) {
+        part->swap(nd.part);
+        result = id + 1;
+        done = true;
+        return;
+      }
+    if (next.empty()) {  // cannot happen: every gate fits k with the padding
+      done = true;
+      return;
+    }
+    beam.clear();
+    for (auto& nd : next) {
+      bool dup = false;
+      for (const auto& b : beam)
+        if (b.placed == nd.placed && b.weight == nd.weight && b.ready == nd.ready && b.indeg == nd.indeg) {
+          dup = true;
+          break;
+        }
+      if (dup) continue;
+      beam.push_back(std::move(nd));
+      if ((int)beam.size() == B) break;
+    }
+  };
+
+  if (T == 1) {
+    for (int id = 0; !done; ++id) {
+      expand(0, id);
+      select(id);
+    }
   } else {
+    struct Barrier {
+      std::mutex m;
+      std::condition_variable cv;
+      int n, count = 0;
+      uint64_t gen = 0;
+      explicit Barrier(int n_) : n(n_) {}
+      void wait() {
+        std::unique_lock<std::mutex> l(m);
+        const uint64_t g = gen;
+        if (++count == n) {
+          count = 0;
+          ++gen;
+          cv.notify_all();
+        } else {
+          cv.wait(l, [&] { return gen != g; });
+        }
+      }
+    } bar(T);
+    auto team = [&](int t) {
+      for (int id = 0;; ++id) {
+        expand(t, id);
+        bar.wait();
+        if (t == 0) select(id);
+        bar.wait();
+        if (done) return;
+      }
+    };
     std::vector<std::thread> pool;
-    for (int w = 0; w < nthreads; ++w) pool.emplace_back(worker, w);
+    for (int t = 1; t < T; ++t) pool.emplace_back(team, t);
+    team(0);
     for (auto& th : pool) th.join();
   }
-  int bw = -1;
-  for (int w = 0; w < nthreads; ++w)
-    if (best_np[w] > 0 && (bw < 0 || best_np[w] < best_np[bw] ||
-                           (best_np[w] == best_np[bw] && best_t[w] < best_t[bw])))
-      bw = w;
-  if (bw < 0) return partition_nat(gates, k, part, pad);
-  part->swap(best_part[bw]);
-  return best_np[bw];
+  if (result < 0) return partition_nat(gates, k, part, pad);
+  if (B > 1) {  // never more parts than the plain rule
+    std::vector<int32_t> plain;
+    const int np = partition_closure(gates, dag, k, 1, &plain, pad);
+    if (np < result) {
+      part->swap(plain);
+      result = np;
+    }
+  }
+  return result;
 }
 
 std::string check_partition(const std::vector<Gate>& gates, const Dag& dag,

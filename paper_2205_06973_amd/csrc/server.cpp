@@ -117,7 +117,7 @@ hs_status prepare(hs_server_* sv, Request* r, hipStream_t stream) {
     case HS_PART_DFS: partition_dfs(gs, dag, r->k, seed, 16, &part); break;
     case HS_PART_DAGP: partition_dagp(gs, dag, r->n, r->k, seed, &part); break;
     case HS_PART_GREEDY: partition_greedy(gs, dag, r->k, seed, 16, &part); break;
-    case HS_PART_CLOSURE: partition_closure(gs, dag, r->k, seed, 4, &part); break;
+    case HS_PART_CLOSURE: partition_closure(gs, dag, r->k, 1, &part); break;
     default: return fail(HS_E_ARG, "unknown strategy %d", (int)r->strategy);
   }
   auto plan = std::make_unique<Plan>();

@@ -343,9 +343,9 @@ def test_greedy_not_below_brute_force(seed):
 @pytest.mark.parametrize("k", [2, 3, 5, 7])
 def test_closure_valid_and_deterministic(name, make, k):
     """Every plan passes the oracle's exact validity check (qubit bound,
-    coverage, acyclic part-graph), alone and with multi-level padding; the
-    same seed gives the same plan whatever the host threads do; more trials
-    never give more parts."""
+    coverage, acyclic part-graph), alone and with multi-level padding; a
+    beam search (trials = its width, run on host threads) returns the same
+    plan every time and never more parts than the plain rule (width 1)."""
     n, gates = make()
     c = hisv.Circuit(n, gates)
     p = hisv.Plan.partition(c, k, "closure", seed=7, trials=16)
@@ -362,7 +362,8 @@ def test_closure_valid_and_deterministic(name, make, k):
 def test_closure_near_brute_force():
     """Against the exact minimum on 80 small DAGs (5 qubits, 8 gates,
     k = 2 and 3): never below it (it is a minimum), equal in all but a few
-    (78 of 80 when written; greedy 58, DFS 78)."""
+    (78 of 80 with a beam of 8 when written; the plain rule 74, greedy 58,
+    DFS 78)."""
     hits = 0
     for seed in range(40):
         n = 5
@@ -377,9 +378,10 @@ def test_closure_near_brute_force():
 
 
 def test_closure_on_the_benchmark_circuits():
-    """Fewer parts than the greedy ready-set partitioner (256 draws) on the
-    1,000-gate random circuit at k = 5, 6, 7 and on the 28-qubit layered
-    circuit at k = 6, and fewer than dagP on a 24-qubit QFT at k = 7."""
+    """With the bench's beam of 16: fewer parts than the greedy ready-set
+    partitioner (256 draws) on the 1,000-gate random circuit at k = 5, 6, 7
+    and on the 28-qubit layered circuit at k = 6, and fewer than dagP on a
+    24-qubit QFT at k = 7."""
     n, gates = wl.random34(0)
     c = hisv.Circuit(n, gates)
     for k in (5, 6, 7):
