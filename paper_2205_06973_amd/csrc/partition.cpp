@@ -12,8 +12,7 @@
 // part-graph topologically.
 #include <algorithm>
 #include <climits>
-#include <condition_variable>
-#include <mutex>
+#include <atomic>
 #include <thread>
 
 #include "hisv_internal.h"
@@ -194,6 +193,7 @@ class ClosureSearch {
     std::vector<int32_t> part;   // part id per gate, -1 = unplaced
     int placed = 0;              // gates placed
     int weight = 0;              // two-qubit gates placed
+    uint64_t key = 0;            // XOR of the placed gates' random keys
   };
 
   ClosureSearch(const std::vector<Gate>& gates, const Dag& dag, int k, uint64_t pad)
@@ -206,6 +206,9 @@ class ClosureSearch {
     }
     tin_.assign(G_, 0);
     tstamp_.assign(G_, 0);
+    zkey_.resize(G_);
+    Rng rng(0x5a17u);
+    for (int i = 0; i < G_; ++i) zkey_[i] = rng.next();
   }
 
   Node root() const {
@@ -258,6 +261,7 @@ class ClosureSearch {
     for (int i : take_) {
       r.part[i] = id;
       r.weight += weight_[i];
+      r.key ^= zkey_[i];
       for (int s : dag_.succ[i]) --r.indeg[s];
     }
     r.placed += (int)take_.size();
@@ -368,7 +372,7 @@ class ClosureSearch {
   const uint64_t pad_;
   const int G_;
   const Node* cur_ = nullptr;
-  std::vector<uint64_t> mask_;
+  std::vector<uint64_t> mask_, zkey_;
   std::vector<int> weight_, front_, take_, stack_, tin_;
   std::vector<uint32_t> tstamp_;
   uint32_t stamp_ = 0;
@@ -401,7 +405,7 @@ int partition_closure(const std::vector<Gate>& gates, const Dag& dag, int k, int
   }
   const int B = std::max(1, width);
   const int M = B > 1 ? 4 : 1;
-  // the beam's expansions run on up to 8 host threads, node i on thread i % T
+  // the beam's expansions run on up to 8 host threads
   const int T = std::max(1, std::min({B, 8, (int)std::thread::hardware_concurrency()}));
   std::vector<ClosureSearch> cs(T, ClosureSearch(gates, dag, k, pad));
   std::vector<Node> beam{cs[0].root()};
@@ -410,8 +414,11 @@ int partition_closure(const std::vector<Gate>& gates, const Dag& dag, int k, int
   int result = -1;
   bool done = false;
 
+  // nodes are taken from a shared counter; node i's expansions go to
+  // grown[i] whichever thread makes them, so the result is the same
+  std::atomic<size_t> next_node{0};
   auto expand = [&](int t, int id) {
-    for (size_t i = t; i < beam.size(); i += T) {
+    for (size_t i; (i = next_node.fetch_add(1, std::memory_order_relaxed)) < beam.size();) {
       cs[t].candidates(beam[i], M, &qs[t]);
       grown[i].clear();
       for (uint64_t Q : qs[t]) grown[i].push_back(cs[t].apply(beam[i], Q, id));
@@ -420,6 +427,7 @@ int partition_closure(const std::vector<Gate>& gates, const Dag& dag, int k, int
   // the best `B` distinct expansions become the next beam; the first that
   // places every gate ends the search
   auto select = [&](int id) {
+    next_node.store(0, std::memory_order_relaxed);
     std::vector<Node> next;
     for (size_t i = 0; i < beam.size(); ++i)
       for (auto& nd : grown[i]) next.push_back(std::move(nd));
@@ -441,7 +449,7 @@ int partition_closure(const std::vector<Gate>& gates, const Dag& dag, int k, int
     for (auto& nd : next) {
       bool dup = false;
       for (const auto& b : beam)
-        if (b.placed == nd.placed && b.weight == nd.weight && b.ready == nd.ready && b.indeg == nd.indeg) {
+        if (b.key == nd.key && b.placed == nd.placed && b.ready == nd.ready && b.indeg == nd.indeg) {
           dup = true;
           break;
         }
@@ -457,21 +465,20 @@ int partition_closure(const std::vector<Gate>& gates, const Dag& dag, int k, int
       select(id);
     }
   } else {
+    // a spinning barrier: a level's work is a fraction of a millisecond,
+    // about what waking a sleeping thread costs
     struct Barrier {
-      std::mutex m;
-      std::condition_variable cv;
-      int n, count = 0;
-      uint64_t gen = 0;
+      std::atomic<int> count{0};
+      std::atomic<uint64_t> gen{0};
+      const int n;
       explicit Barrier(int n_) : n(n_) {}
       void wait() {
-        std::unique_lock<std::mutex> l(m);
-        const uint64_t g = gen;
-        if (++count == n) {
-          count = 0;
-          ++gen;
-          cv.notify_all();
+        const uint64_t g = gen.load(std::memory_order_acquire);
+        if (count.fetch_add(1, std::memory_order_acq_rel) == n - 1) {
+          count.store(0, std::memory_order_relaxed);
+          gen.fetch_add(1, std::memory_order_release);
         } else {
-          cv.wait(l, [&] { return gen != g; });
+          while (gen.load(std::memory_order_acquire) == g) std::this_thread::yield();
         }
       }
     } bar(T);
