@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <climits>
 #include <atomic>
+#include <memory>
 #include <thread>
 
 #include "hisv_internal.h"
@@ -186,14 +187,26 @@ namespace {
 // Closure parts and the beam search over them (see partition_closure).
 class ClosureSearch {
  public:
-  // A partial partition: the gates placed so far.
+  // The parts taken so far, newest first (shared between beam nodes).
+  struct History {
+    mutable std::shared_ptr<const History> prev;
+    std::vector<int> gates;
+    ~History() {  // unlink a long chain iteratively, not by recursion
+      std::shared_ptr<const History> p = std::move(prev);
+      while (p && p.use_count() == 1) p = std::move(p->prev);
+    }
+  };
+  // A partial partition: the gates placed so far.  Its size is O(G / 64 +
+  // front), so extending a beam node costs little on long circuits.
   struct Node {
-    std::vector<int> indeg;      // unplaced predecessors of each gate
-    std::vector<int> ready;      // unplaced gates with none, ascending
-    std::vector<int32_t> part;   // part id per gate, -1 = unplaced
-    int placed = 0;              // gates placed
-    int weight = 0;              // two-qubit gates placed
-    uint64_t key = 0;            // XOR of the placed gates' random keys
+    std::vector<uint64_t> placed;          // bit per gate
+    std::vector<int> ready;                // unplaced gates whose predecessors are placed, ascending
+    std::shared_ptr<const History> parts;  // the parts, newest first
+    int count = 0;                         // gates placed
+    int nparts = 0;
+    int weight = 0;                        // two-qubit gates placed
+    uint64_t key = 0;                      // XOR of the placed gates' random keys
+    bool is_placed(int i) const { return placed[i >> 6] >> (i & 63) & 1; }
   };
 
   ClosureSearch(const std::vector<Gate>& gates, const Dag& dag, int k, uint64_t pad)
@@ -213,13 +226,19 @@ class ClosureSearch {
 
   Node root() const {
     Node r;
-    r.indeg.resize(G_);
-    r.part.assign(G_, -1);
-    for (int i = 0; i < G_; ++i) {
-      r.indeg[i] = (int)dag_.pred[i].size();
-      if (!r.indeg[i]) r.ready.push_back(i);
-    }
+    r.placed.assign((G_ + 63) / 64, 0);
+    for (int i = 0; i < G_; ++i)
+      if (dag_.pred[i].empty()) r.ready.push_back(i);
     return r;
+  }
+
+  // part id per gate of a complete partition
+  static void assign(const Node& nd, std::vector<int32_t>* part) {
+    int id = nd.nparts;
+    for (const History* h = nd.parts.get(); h; h = h->prev.get()) {
+      --id;
+      for (int i : h->gates) (*part)[i] = id;
+    }
   }
 
   // Up to m distinct qubit sets for the next part of `nd`: the m best
@@ -252,25 +271,35 @@ class ClosureSearch {
     }
   }
 
-  // `nd` with the closure of Q placed as part `id`.
-  Node apply(const Node& nd, uint64_t Q, int id) {
+  // `nd` with the closure of Q placed as its next part.
+  Node apply(const Node& nd, uint64_t Q) {
     cur_ = &nd;
     take_.clear();
     eval(Q, &take_, nullptr);
-    Node r = nd;
+    Node r;
+    r.placed = nd.placed;
+    r.count = nd.count + (int)take_.size();
+    r.nparts = nd.nparts + 1;
+    r.weight = nd.weight;
+    r.key = nd.key;
     for (int i : take_) {
-      r.part[i] = id;
+      r.placed[i >> 6] |= uint64_t(1) << (i & 63);
       r.weight += weight_[i];
       r.key ^= zkey_[i];
-      for (int s : dag_.succ[i]) --r.indeg[s];
     }
-    r.placed += (int)take_.size();
-    r.ready.clear();
+    auto h = std::make_shared<History>();
+    h->prev = nd.parts;
+    h->gates = take_;
+    r.parts = std::move(h);
     for (int i : nd.ready)
-      if (r.part[i] < 0) r.ready.push_back(i);
+      if (!r.is_placed(i)) r.ready.push_back(i);
     for (int i : take_)
-      for (int s : dag_.succ[i])
-        if (!r.indeg[s] && r.part[s] < 0) r.ready.push_back(s);
+      for (int s : dag_.succ[i]) {
+        if (r.is_placed(s)) continue;
+        bool ok = true;
+        for (int q : dag_.pred[s]) ok &= r.is_placed(q);
+        if (ok) r.ready.push_back(s);
+      }
     std::sort(r.ready.begin(), r.ready.end());
     r.ready.erase(std::unique(r.ready.begin(), r.ready.end()), r.ready.end());
     return r;
@@ -300,9 +329,11 @@ class ClosureSearch {
       w += weight_[i];
       if (take) take->push_back(i);
       for (int s : dag_.succ[i]) {
-        if (tstamp_[s] != stamp_) {
+        if (tstamp_[s] != stamp_) {  // its unplaced predecessors (at most one per qubit)
           tstamp_[s] = stamp_;
-          tin_[s] = cur_->indeg[s];
+          int u = 0;
+          for (int q : dag_.pred[s]) u += !cur_->is_placed(q);
+          tin_[s] = u;
         }
         if (--tin_[s] == 0) {
           if (!(mask_[s] & ~Q)) stack_.push_back(s);
@@ -417,27 +448,28 @@ int partition_closure(const std::vector<Gate>& gates, const Dag& dag, int k, int
   // nodes are taken from a shared counter; node i's expansions go to
   // grown[i] whichever thread makes them, so the result is the same
   std::atomic<size_t> next_node{0};
-  auto expand = [&](int t, int id) {
+  auto expand = [&](int t) {
     for (size_t i; (i = next_node.fetch_add(1, std::memory_order_relaxed)) < beam.size();) {
       cs[t].candidates(beam[i], M, &qs[t]);
       grown[i].clear();
-      for (uint64_t Q : qs[t]) grown[i].push_back(cs[t].apply(beam[i], Q, id));
+      for (uint64_t Q : qs[t]) grown[i].push_back(cs[t].apply(beam[i], Q));
     }
   };
   // the best `B` distinct expansions become the next beam; the first that
   // places every gate ends the search
-  auto select = [&](int id) {
+  auto select = [&]() {
     next_node.store(0, std::memory_order_relaxed);
     std::vector<Node> next;
     for (size_t i = 0; i < beam.size(); ++i)
       for (auto& nd : grown[i]) next.push_back(std::move(nd));
     std::stable_sort(next.begin(), next.end(), [](const Node& x, const Node& y) {
-      return x.weight != y.weight ? x.weight > y.weight : x.placed > y.placed;
+      return x.weight != y.weight ? x.weight > y.weight : x.count > y.count;
     });
     for (auto& nd : next)
-      if (nd.placed == dag.G) {
-        part->swap(nd.part);
-        result = id + 1;
+      if (nd.count == dag.G) {
+        part->assign(dag.G, -1);
+        ClosureSearch::assign(nd, part);
+        result = nd.nparts;
         done = true;
         return;
       }
@@ -449,7 +481,7 @@ int partition_closure(const std::vector<Gate>& gates, const Dag& dag, int k, int
     for (auto& nd : next) {
       bool dup = false;
       for (const auto& b : beam)
-        if (b.key == nd.key && b.placed == nd.placed && b.ready == nd.ready && b.indeg == nd.indeg) {
+        if (b.key == nd.key && b.count == nd.count && b.placed == nd.placed) {
           dup = true;
           break;
         }
@@ -460,9 +492,9 @@ int partition_closure(const std::vector<Gate>& gates, const Dag& dag, int k, int
   };
 
   if (T == 1) {
-    for (int id = 0; !done; ++id) {
-      expand(0, id);
-      select(id);
+    while (!done) {
+      expand(0);
+      select();
     }
   } else {
     // a spinning barrier: a level's work is a fraction of a millisecond,
@@ -483,10 +515,10 @@ int partition_closure(const std::vector<Gate>& gates, const Dag& dag, int k, int
       }
     } bar(T);
     auto team = [&](int t) {
-      for (int id = 0;; ++id) {
-        expand(t, id);
+      for (;;) {
+        expand(t);
         bar.wait();
-        if (t == 0) select(id);
+        if (t == 0) select();
         bar.wait();
         if (done) return;
       }
