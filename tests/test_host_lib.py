@@ -359,6 +359,18 @@ def test_closure_valid_and_deterministic(name, make, k):
         assert op.check_partition(n, gates, m.part_of_gate().tolist(), k, padding=range(pad)) == []
 
 
+def test_closure_beam_on_a_long_circuit():
+    """A 9,000-gate layered circuit: the beam's plan passes the oracle's
+    exact check and needs fewer parts than the plain rule (its per-node
+    state is a placed-gate bitset, so long circuits stay cheap)."""
+    n, gates = wl.layered28(4, n=20, layers=200)
+    c = hisv.Circuit(n, gates)
+    beam = hisv.Plan.partition(c, 6, "closure", seed=0, trials=4)
+    plain = hisv.Plan.partition(c, 6, "closure", seed=0, trials=1)
+    assert beam.num_parts < plain.num_parts
+    assert op.check_partition(n, gates, beam.part_of_gate().tolist(), 6) == []
+
+
 def test_closure_near_brute_force():
     """Against the exact minimum on 80 small DAGs (5 qubits, 8 gates,
     k = 2 and 3): never below it (it is a minimum), equal in all but a few
