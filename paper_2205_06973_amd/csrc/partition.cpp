@@ -251,20 +251,19 @@ class ClosureSearch {
     eval(pad_, nullptr, &front_);
     struct Seed {
       int64_t sc;
-      size_t pos;
       uint64_t set;
     };
-    std::vector<Seed> seeds;
-    for (size_t r = 0; r < front_.size(); ++r) {
-      const uint64_t c = pad_ | mask_[front_[r]];
+    std::vector<Seed> seeds;  // in front order, so the stable sort breaks ties to the earlier gate
+    for (int f : front_) {
+      const uint64_t c = pad_ | mask_[f];
       if (c == pad_ || __builtin_popcountll(c) > k_) continue;
       bool dup = false;
       for (const Seed& e : seeds) dup |= e.set == c;
       if (dup) continue;
-      seeds.push_back({score(c), r, c});
+      seeds.push_back({score(c), c});
     }
     std::stable_sort(seeds.begin(), seeds.end(), [](const Seed& x, const Seed& y) { return x.sc > y.sc; });
-    if (seeds.empty()) seeds.push_back({0, 0, pad_});
+    if (seeds.empty()) seeds.push_back({0, pad_});
     for (size_t i = 0; i < seeds.size() && (int)out->size() < m; ++i) {
       const uint64_t Q = improve(grow(seeds[i].set));
       if (std::find(out->begin(), out->end(), Q) == out->end()) out->push_back(Q);
