@@ -422,7 +422,7 @@ class ClosureSearch {
 //
 // `width` > 1 runs a beam search: each of the `width` best partial
 // partitions (most two-qubit gates placed, then most gates) is extended by
-// up to four parts -- the growth started from each of its four best first
+// up to six parts -- the growth started from each of its six best first
 // gates -- and the first partition to place every gate wins, unless the
 // plain rule (width 1) needs fewer parts.  The result does not depend on
 // the number of host threads.
@@ -434,7 +434,7 @@ int partition_closure(const std::vector<Gate>& gates, const Dag& dag, int k, int
     return 0;
   }
   const int B = std::max(1, width);
-  const int M = B > 1 ? 4 : 1;
+  const int M = B > 1 ? 6 : 1;
   // the beam's expansions run on up to 8 host threads
   const int T = std::max(1, std::min({B, 8, (int)std::thread::hardware_concurrency()}));
   std::vector<ClosureSearch> cs(T, ClosureSearch(gates, dag, k, pad));
