@@ -166,7 +166,9 @@ hs_status hs_device_count(int* out);
  * of tiles per workgroup, 1 = a persistent grid whose waves issue the next
  * group's loads before the current group's products, 2 = a persistent grid
  * of the plain kernel, -1 = the measured best for the width and precision.
- * A "spec_"
+ * Host side: "host_threads" (0..64, default 0 = up to 8 as the host has
+ * them) = threads a CLOSURE beam search may use; its plans are the same
+ * for every value.  A "spec_"
  * prefix on a key sets it for the specialized kernels (PART_SPEC) instead of
  * the interpreter kernel ("contig" has no prefix: it applies to both).
  * HS_E_ARG for an unknown key or value. */

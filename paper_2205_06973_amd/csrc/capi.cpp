@@ -51,10 +51,16 @@ static bool g_fuse2[2] = {true, false};        // [specialized]
 // software-pipelined kernel on a persistent grid, 2 = plain kernel on a
 // persistent grid, -1 = the measured best per width and precision
 static int g_fused_shape = -1;
+static int g_host_threads = 0;
 
 int fused_launch_shape() {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   return g_fused_shape;
+}
+
+int host_threads() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return g_host_threads;
 }
 
 CompileOptions default_options(hs_dtype dtype, bool spec) {
@@ -193,6 +199,9 @@ hs_status hs_tune(const char* key, int value) {
   } else if (k == "fused_shape" && !spec) {
     CHECK_ARG(value >= -1 && value <= 2, "fused_shape must be -1, 0, 1 or 2");
     g_fused_shape = value;
+  } else if (k == "host_threads" && !spec) {
+    CHECK_ARG(value >= 0 && value <= 64, "host_threads must be 0..64");
+    g_host_threads = value;
   } else if (k == "min_tile") {
     CHECK_ARG(value >= 0 && value <= 16, "min_tile must be 0..16");
     g_min_tile[spec] = value;

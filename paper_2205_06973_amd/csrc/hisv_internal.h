@@ -67,6 +67,9 @@ int partition_dagp(const std::vector<Gate>& gates, const Dag& dag, int n, int k,
                    uint64_t seed, std::vector<int32_t>* part, uint64_t pad = 0);
 int partition_greedy(const std::vector<Gate>& gates, const Dag& dag, int k, uint64_t seed,
                      int trials, std::vector<int32_t>* part, uint64_t pad = 0);
+// hs_tune("host_threads"): threads a partition search may use (0 = up to 8,
+// as the host has them).
+int host_threads();
 int partition_closure(const std::vector<Gate>& gates, const Dag& dag, int k, int width,
                       std::vector<int32_t>* part, uint64_t pad = 0);
 // Exact validity check; returns "" when valid, else the first violation.

@@ -435,8 +435,9 @@ int partition_closure(const std::vector<Gate>& gates, const Dag& dag, int k, int
   }
   const int B = std::max(1, width);
   const int M = B > 1 ? 6 : 1;
-  // the beam's expansions run on up to 8 host threads
-  const int T = std::max(1, std::min({B, 8, (int)std::thread::hardware_concurrency()}));
+  // the beam's expansions run on up to 8 host threads (hs_tune "host_threads")
+  const int want = host_threads();
+  const int T = std::max(1, std::min(B, want > 0 ? want : std::min(8, (int)std::thread::hardware_concurrency())));
   std::vector<ClosureSearch> cs(T, ClosureSearch(gates, dag, k, pad));
   std::vector<Node> beam{cs[0].root()};
   std::vector<std::vector<Node>> grown(B);

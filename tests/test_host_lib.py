@@ -371,6 +371,22 @@ def test_closure_beam_on_a_long_circuit():
     assert op.check_partition(n, gates, beam.part_of_gate().tolist(), 6) == []
 
 
+def test_closure_beam_does_not_depend_on_host_threads():
+    """The beam search hands nodes to host threads from a shared counter;
+    each node's extensions land in its own slot, so 1, 3 and 8 threads
+    give the same plan."""
+    n, gates = wl.random34(0, n=24, num_gates=600)
+    c = hisv.Circuit(n, gates)
+    plans = []
+    try:
+        for t in (1, 3, 8):
+            hisv.hs_tune("host_threads", t)
+            plans.append(hisv.Plan.partition(c, 6, "closure", seed=0, trials=16).part_of_gate().tolist())
+    finally:
+        hisv.hs_tune("host_threads", 0)
+    assert plans[0] == plans[1] == plans[2]
+
+
 def test_closure_near_brute_force():
     """Against the exact minimum on 80 small DAGs (5 qubits, 8 gates,
     k = 2 and 3): never below it (it is a minimum), equal in all but a few
