@@ -297,6 +297,47 @@ def waits(counters_csv: str, stats_csv: str, out_path: str, command: str) -> Non
     print("\n".join(lines))
 
 
+def issue(counters_a: str, counters_b: str, out_path: str, command: str) -> None:
+    """Where the fused and part kernels' issue slots go: from one --pmc run,
+    the share of wave cycles spent waiting on anything and waiting to issue,
+    and how busy the VALU, scalar unit and matrix cores were; from a second,
+    the instructions per wave by kind."""
+    def load(path):
+        d: dict[str, dict[str, list[float]]] = {}
+        for r in csv.DictReader(open(path)):
+            d.setdefault(_short(r["Kernel_Name"]), {}).setdefault(r["Counter_Name"], []).append(
+                float(r["Counter_Value"]))
+        return d
+    a, b = load(counters_a), load(counters_b)
+    mean = lambda d, c: sum(d[c]) / len(d[c])  # noqa: E731
+    lines = ["# issue counters per dispatch (two rocprofv3 --pmc runs of one command)",
+             f"# command: {command}", f"# kernel source hash: {kernel_source_hash()}",
+             "# wait_any, wait_issue = SQ_WAIT_ANY, SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES; valu, salu busy =",
+             "# SQ_ACTIVE_INST_VALU, SQ_ACTIVE_INST_SCA * 4 / (GRBM_GUI_ACTIVE / 8 * 1024 SIMDs); mfma busy =",
+             "# SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / 8 * 1024); per-wave counts from SQ_INSTS_*", "",
+             f"{'kernel':36s} {'calls':>5s} {'wait_any':>8s} {'wait_iss':>8s} {'valu':>6s} {'salu':>6s} {'mfma':>6s}"
+             f" {'VALU/w':>8s} {'SALU/w':>8s} {'MFMA/w':>8s} {'VMEMrd/w':>8s} {'VMEMwr/w':>8s}"]
+    for k in sorted(a):
+        if not k.startswith(("fused_pass_kernel", "part_pass")) or "SQ_WAVE_CYCLES" not in a[k]:
+            continue
+        d = a[k]
+        wc = mean(d, "SQ_WAVE_CYCLES")
+        simd = mean(d, "GRBM_GUI_ACTIVE") / 8 * 1024
+        row = (f"{k:36s} {len(d['SQ_WAVES']):5d} {mean(d, 'SQ_WAIT_ANY') / wc:8.3f} {mean(d, 'SQ_WAIT_INST_ANY') / wc:8.3f}"
+               f" {mean(d, 'SQ_ACTIVE_INST_VALU') * 4 / simd:6.3f} {mean(d, 'SQ_ACTIVE_INST_SCA') * 4 / simd:6.3f}"
+               f" {mean(d, 'SQ_VALU_MFMA_BUSY_CYCLES') / simd:6.3f}")
+        e = b.get(k)
+        if e and "SQ_WAVES" in e:
+            w = mean(e, "SQ_WAVES")
+            row += (f" {mean(e, 'SQ_INSTS_VALU') / w:8.0f} {mean(e, 'SQ_INSTS_SALU') / w:8.0f}"
+                    f" {mean(e, 'SQ_INSTS_VALU_MFMA_F32') / w:8.0f} {mean(e, 'SQ_INSTS_VMEM_RD') / w:8.0f}"
+                    f" {mean(e, 'SQ_INSTS_VMEM_WR') / w:8.0f}")
+        lines.append(row)
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def runs(trace_csv: str, bench_json: str, out_path: str, command: str, kernel: str = "gate_pass_1q",
          per_case: int = 16) -> None:
     """Per-case durations of a kernel from a --kernel-trace run of
@@ -335,6 +376,8 @@ def main(argv):
         mfma(argv[1], argv[2], argv[3], argv[4])
     elif argv[0] == "valu":
         valu(argv[1], argv[2], argv[3], argv[4])
+    elif argv[0] == "issue":
+        issue(argv[1], argv[2], argv[3], argv[4])
     elif argv[0] == "waits":
         waits(argv[1], argv[2], argv[3], argv[4])
     elif argv[0] == "runs":
