@@ -650,7 +650,7 @@ def main() -> int:
     ap.add_argument("--dtype", default="c128", choices=["c64", "c128"])
     ap.add_argument("--strategy", default="closure", choices=["nat", "dfs", "dagp", "greedy", "closure"])
     ap.add_argument("--trials", type=int, default=None,
-                    help="orders (DFS) or tie-break draws (greedy, closure) tried per partition "
+                    help="orders (DFS), tie-break draws (greedy) or beam width (closure) per partition "
                          "(default: 16 for closure, else 256)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--mode", default="part_spec", choices=["part_lds", "part_spec", "auto"])

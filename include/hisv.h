@@ -95,7 +95,12 @@ typedef struct {
  * GREEDY (not in the paper): each part grows by the ready gate that fits and
  * adds the fewest new qubits, closing when none fits; trial 0 breaks ties by
  * gate index, the other trials by seeded random keys; fewest parts win.
- * Its parts are contiguous pieces of a topological order, hence acyclic. */
+ * Its parts are contiguous pieces of a topological order, hence acyclic.
+ * CLOSURE (not in the paper): each part is the closure of a qubit set from
+ * the current front (every unplaced gate on those qubits whose
+ * predecessors are placed), the set chosen for the most two-qubit gates;
+ * `trials` > 1 is the width of a beam search over such parts.  Parts are
+ * taken in order, hence acyclic. */
 typedef enum {
   HS_PART_NAT = 0,
   HS_PART_DFS = 1,
