@@ -199,9 +199,21 @@ hs_status dev_set_basis(State* s, uint64_t x);
 hs_status dev_gate_pass(State* s, const Gate& g);
 hs_status dev_run_part(State* s, Plan* p, int part);
 // Upload the plan's interpreter descriptors for `dtype` on `device` with the
-// stream-ordered allocator on `stream` (waits for the copies); the plan later
-// frees them with hipFreeAsync on that stream, never with a device-wide wait.
-hs_status dev_plan_upload_async(Plan* p, hs_dtype dtype, int device, void* stream);
+// stream-ordered allocator on `stream`, without waiting for the copies; the
+// plan later frees them with hipFreeAsync on that stream, never with a
+// device-wide wait.  A launch on another stream first calls
+// dev_plan_stream_wait, which makes that stream wait for the copies.
+// Pinned host staging for those copies (one per preparing thread): used
+// when large enough and `busy` (recorded after its last copies) has passed;
+// otherwise the copies go from pageable memory.
+struct PinnedStaging {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  void* busy = nullptr;  // hipEvent_t
+};
+hs_status dev_plan_upload_async(Plan* p, hs_dtype dtype, int device, void* stream,
+                                const PinnedStaging* pin = nullptr);
+hs_status dev_plan_stream_wait(Plan* p, hs_dtype dtype, int device, void* stream);
 hs_status dev_run_fused(State* s, Plan* p, int part);
 hs_status plan_compile_fused(Plan* p);
 // hs_tune("fused_shape"): the fused w = 4, 5 kernels' launch shape, read when

@@ -944,6 +944,9 @@ struct DevicePlan {
   // hipFreeAsync on free_stream, so a teardown never waits for the device
   bool async_alloc = false;
   void* free_stream = nullptr;
+  // recorded after the asynchronous descriptor copies on free_stream; a
+  // launch on another stream waits for it on the device
+  hipEvent_t upload_done = nullptr;
   IPart* parts = nullptr;
   IStage* stages = nullptr;
   void* ops = nullptr;
@@ -972,8 +975,19 @@ void device_plan_free(DevicePlan* d) {
   }
   if (d->fparts) (void)hipFree(d->fparts);
   if (d->fmat) (void)hipFree(d->fmat);
+  if (d->upload_done) (void)hipEventDestroy(d->upload_done);
   delete d;
 }
+
+// Host copies of a plan's descriptors, kept until the asynchronous copies
+// from them have run (a host function on the copy stream deletes them).
+template <typename T>
+struct HostDescriptors {
+  std::vector<IPart> parts;
+  std::vector<IStage> stages;
+  std::vector<OpDesc<T>> ops;
+  static void release(void* p) { delete static_cast<HostDescriptors*>(p); }
+};
 
 template <typename T, int RB>
 static hs_status resident_per_cu(int block, size_t lds, int* per_cu) {
@@ -1041,7 +1055,8 @@ static IoOffsets interp_io(const StageDesc& e, const PartDesc& d) {
 // blocking copies; otherwise the stream-ordered allocator and asynchronous
 // copies on `stream`, waited for before returning.
 template <typename T>
-static hs_status upload_plan(Plan* p, int dtype, int dev, DevicePlan** out, hipStream_t stream) {
+static hs_status upload_plan(Plan* p, int dtype, int dev, DevicePlan** out, hipStream_t stream,
+                             const PinnedStaging* pin = nullptr) {
   std::vector<PartDesc> hparts;
   std::vector<IPart> parts;
   std::vector<IStage> stages;
@@ -1095,18 +1110,57 @@ static hs_status upload_plan(Plan* p, int dtype, int dev, DevicePlan** out, hipS
   if (parts.empty()) parts.push_back(IPart{});
   if (stages.empty()) stages.push_back(IStage{});
   if (stream) {
+    // Nothing here waits for the device: the stream may share a hardware
+    // queue with long-running part kernels, and a host wait would hold the
+    // caller (a serving thread) until they drain.  The host copies live
+    // until a host function after the copies deletes them, and launches
+    // elsewhere wait for upload_done on the device.
     dp->async_alloc = true;
     dp->free_stream = stream;
-    HIP_TRY(hipMallocAsync((void**)&dp->parts, parts.size() * sizeof(IPart), stream));
-    HIP_TRY(hipMallocAsync((void**)&dp->stages, stages.size() * sizeof(IStage), stream));
-    HIP_TRY(hipMallocAsync(&dp->ops, ops.size() * sizeof(OpDesc<T>), stream));
-    HIP_TRY(hipMemcpyAsync(dp->parts, parts.data(), parts.size() * sizeof(IPart), hipMemcpyHostToDevice,
-                           stream));
-    HIP_TRY(hipMemcpyAsync(dp->stages, stages.data(), stages.size() * sizeof(IStage),
+    const size_t b_parts = parts.size() * sizeof(IPart), b_stages = stages.size() * sizeof(IStage),
+                 b_ops = ops.size() * sizeof(OpDesc<T>);
+    // pinned staging, when it is free and large enough: the copies are then
+    // plain DMA with nothing to stage on the host
+    const size_t o_stages = (b_parts + 255) & ~size_t(255), o_ops = (o_stages + b_stages + 255) & ~size_t(255);
+    if (pin && pin->ptr && o_ops + b_ops <= pin->bytes && hipEventQuery((hipEvent_t)pin->busy) == hipSuccess) {
+      char* h = static_cast<char*>(pin->ptr);
+      std::memcpy(h, parts.data(), b_parts);
+      std::memcpy(h + o_stages, stages.data(), b_stages);
+      std::memcpy(h + o_ops, ops.data(), b_ops);
+      HIP_TRY(hipMallocAsync((void**)&dp->parts, b_parts, stream));
+      HIP_TRY(hipMallocAsync((void**)&dp->stages, b_stages, stream));
+      HIP_TRY(hipMallocAsync(&dp->ops, b_ops, stream));
+      HIP_TRY(hipMemcpyAsync(dp->parts, h, b_parts, hipMemcpyHostToDevice, stream));
+      HIP_TRY(hipMemcpyAsync(dp->stages, h + o_stages, b_stages, hipMemcpyHostToDevice, stream));
+      HIP_TRY(hipMemcpyAsync(dp->ops, h + o_ops, b_ops, hipMemcpyHostToDevice, stream));
+      HIP_TRY(hipEventRecord((hipEvent_t)pin->busy, stream));  // the staging is free again once this passes
+      HIP_TRY(hipEventCreateWithFlags(&dp->upload_done, hipEventDisableTiming));
+      HIP_TRY(hipEventRecord(dp->upload_done, stream));
+      dp->h_parts = hparts;
+      *out = dp.release();
+      return HS_OK;
+    }
+    auto host = std::make_unique<HostDescriptors<T>>();
+    host->parts = std::move(parts);
+    host->stages = std::move(stages);
+    host->ops = std::move(ops);
+    HIP_TRY(hipMallocAsync((void**)&dp->parts, host->parts.size() * sizeof(IPart), stream));
+    HIP_TRY(hipMallocAsync((void**)&dp->stages, host->stages.size() * sizeof(IStage), stream));
+    HIP_TRY(hipMallocAsync(&dp->ops, host->ops.size() * sizeof(OpDesc<T>), stream));
+    HIP_TRY(hipMemcpyAsync(dp->parts, host->parts.data(), host->parts.size() * sizeof(IPart),
                            hipMemcpyHostToDevice, stream));
-    HIP_TRY(hipMemcpyAsync(dp->ops, ops.data(), ops.size() * sizeof(OpDesc<T>), hipMemcpyHostToDevice,
-                           stream));
-    HIP_TRY(hipStreamSynchronize(stream));  // the host vectors die on return
+    HIP_TRY(hipMemcpyAsync(dp->stages, host->stages.data(), host->stages.size() * sizeof(IStage),
+                           hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(dp->ops, host->ops.data(), host->ops.size() * sizeof(OpDesc<T>),
+                           hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipEventCreateWithFlags(&dp->upload_done, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(dp->upload_done, stream));
+    if (hipLaunchHostFunc(stream, HostDescriptors<T>::release, host.get()) == hipSuccess) {
+      host.release();  // deleted by the host function
+    } else {
+      (void)hipGetLastError();
+      HIP_TRY(hipStreamSynchronize(stream));  // fallback: wait, then free here
+    }
   } else {
     HIP_TRY(hipMalloc(&dp->parts, parts.size() * sizeof(IPart)));
     HIP_TRY(hipMalloc(&dp->stages, stages.size() * sizeof(IStage)));
@@ -1164,19 +1218,32 @@ static hs_status device_plan(State* s, Plan* p, DevicePlan** out) {
   return HS_OK;
 }
 
-hs_status dev_plan_upload_async(Plan* p, hs_dtype dtype, int device, void* stream) {
+hs_status dev_plan_upload_async(Plan* p, hs_dtype dtype, int device, void* stream, const PinnedStaging* pin) {
   HIP_TRY(hipSetDevice(device));
   std::lock_guard<std::mutex> lk(p->mu);
   const int dt = (int)dtype;
   if (p->dev[dt].count(device)) return HS_OK;
   DevicePlan* dp = nullptr;
-  hs_status rc = dt == HS_C64 ? upload_plan<float>(p, dt, device, &dp, (hipStream_t)stream)
-                              : upload_plan<double>(p, dt, device, &dp, (hipStream_t)stream);
+  hs_status rc = dt == HS_C64 ? upload_plan<float>(p, dt, device, &dp, (hipStream_t)stream, pin)
+                              : upload_plan<double>(p, dt, device, &dp, (hipStream_t)stream, pin);
   if (rc) {
     device_plan_free(dp);
     return rc;
   }
   p->dev[dt][device] = dp;
+  return HS_OK;
+}
+
+hs_status dev_plan_stream_wait(Plan* p, hs_dtype dtype, int device, void* stream) {
+  HIP_TRY(hipSetDevice(device));
+  hipEvent_t ev = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(p->mu);
+    auto it = p->dev[(int)dtype].find(device);
+    if (it == p->dev[(int)dtype].end()) return fail(HS_E_STATE, "plan not uploaded for this device");
+    ev = it->second->upload_done;
+  }
+  if (ev) HIP_TRY(hipStreamWaitEvent((hipStream_t)stream, ev, 0));
   return HS_OK;
 }
 

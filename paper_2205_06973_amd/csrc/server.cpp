@@ -8,14 +8,21 @@
 //             request's arrival time (given by the caller on the server
 //             clock, or the time of the call).
 //   prepare   one of a pool of host threads partitions the circuit, compiles
-//             the interpreter descriptors and uploads them with the
+//             the interpreter descriptors and queues their upload with the
 //             stream-ordered allocator on its own stream -- all without the
-//             server lock.
+//             server lock, and without waiting for the copies: a preparing
+//             stream can share a hardware queue with long part kernels, and
+//             a host wait there held small requests behind large ones.
 //   admit     the worker thread admits prepared requests strictly in ticket
 //             order while the bytes of resident states (plus their
 //             descriptors) stay within the budget, allocates the state on the
-//             stream of a pool with the least outstanding work, enqueues
-//             set-basis and one part-pass per part, and records an event.
+//             stream of a pool with the least queued work, makes that
+//             stream wait (on the device) for the descriptor copies, and
+//             enqueues set-basis and the part-passes -- a chunk of parts at a
+//             time, at most two chunks queued, refilled as chunks finish, so
+//             a request admitted behind a large one on the same hardware
+//             queue waits for two chunks, not for the large one's whole
+//             circuit.  An event follows the last part.
 //             Requests admitted while others run overlap with them on the
 //             device.  (Preparation finishes out of order on the host
 //             threads; admitting in that order could let later requests
@@ -57,8 +64,14 @@ struct Request {
   size_t bytes = 0;  // state + plan descriptors
   State st;
   int stream = -1;
-  double work = 0;   // estimated device work: part-passes x state bytes
-  hipEvent_t done = nullptr;
+  hipEvent_t done = nullptr;  // recorded after the last part
+  // parts go to the device a chunk at a time, at most two chunks queued
+  int next_part = 0;                           // first part not yet enqueued
+  hipEvent_t chunk_ev[2] = {nullptr, nullptr};  // recorded after each chunk
+  double chunk_work[2] = {0, 0};
+  int chunk_old = 0;                           // slot of the oldest queued chunk
+  int chunks_out = 0;                          // chunks queued, not seen finished
+  bool launched = false;                       // work was queued on its stream
   // server clock (seconds): arrival, preparation start and end, launch, done
   double t_arrival = 0, t_prep0 = 0, t_prep1 = 0, t_launch = 0, t_done = 0;
   ReqStatus status = RQ_QUEUED;
@@ -68,6 +81,12 @@ struct Request {
 
 constexpr int kPrepThreads = 4;
 constexpr size_t kReadScratch = size_t(64) << 20;  // covers dev_read's largest chunk
+constexpr size_t kPinnedStaging = size_t(8) << 20;  // descriptor staging per preparing thread
+// Parts a request enqueues at a time.  A hardware queue runs its commands
+// in order, so a request admitted behind a large one waits for what the
+// large one has queued: at most two chunks, a few milliseconds, instead of
+// hundreds of part-passes.
+constexpr int kChunkParts = 8;
 
 }  // namespace
 
@@ -81,6 +100,7 @@ struct hs_server_ {
   std::vector<hipStream_t> streams;
   std::vector<double> load;  // estimated outstanding work per stream
   std::vector<hipStream_t> prep_streams;
+  std::vector<PinnedStaging> pins;  // one per preparing thread
   hipStream_t read_stream = nullptr;
   void* read_scratch = nullptr;  // persistent staging of hs_server_read
   std::mutex read_mu;
@@ -107,7 +127,7 @@ size_t plan_bytes(const Plan& p, hs_dtype dt) {
 }
 
 // Partition, compile and upload one request (no server lock held).
-hs_status prepare(hs_server_* sv, Request* r, hipStream_t stream) {
+hs_status prepare(hs_server_* sv, Request* r, hipStream_t stream, const PinnedStaging* pin) {
   const std::vector<Gate>& gs = r->gates;
   std::vector<int32_t> part;
   const Dag dag = build_dag(gs);
@@ -126,8 +146,7 @@ hs_status prepare(hs_server_* sv, Request* r, hipStream_t stream) {
   r->bytes = (size_t(1) << r->n) * amp_bytes(r->dtype) + plan_bytes(*plan, r->dtype);
   if (r->bytes > sv->budget)
     return fail(HS_E_ADMISSION, "request needs %zu bytes, budget is %zu", r->bytes, sv->budget);
-  if (hs_status rc = dev_plan_upload_async(plan.get(), r->dtype, sv->device, stream)) return rc;
-  r->work = (double)plan->parts.size() * (double)((size_t(1) << r->n) * amp_bytes(r->dtype));
+  if (hs_status rc = dev_plan_upload_async(plan.get(), r->dtype, sv->device, stream, pin)) return rc;
   r->plan = std::move(plan);
   r->gates.clear();
   r->gates.shrink_to_fit();
@@ -146,7 +165,7 @@ void prep_main(hs_server_* sv, int idx) {
     r->status = RQ_PREPARING;
     lk.unlock();
     r->t_prep0 = now_s();
-    const hs_status rc = prepare(sv, r, stream);
+    const hs_status rc = prepare(sv, r, stream, &sv->pins[idx]);
     const std::string msg = rc ? hs_last_error() : "";
     r->t_prep1 = now_s();
     lk.lock();
@@ -168,10 +187,49 @@ Request* find(hs_server_* sv, uint64_t t) {
   return it == sv->reqs.end() ? nullptr : it->second;
 }
 
-// Launch everything for an admitted request (called with the lock held;
-// nothing here waits on the device) on the stream with the least
-// outstanding work, so that small requests do not queue behind large ones
-// when another stream is nearly idle.
+// Enqueue the request's next chunk of parts (lock held; nothing waits on the
+// device) and, after the last part, its done event.
+hs_status enqueue_chunk(hs_server_* sv, Request* r) {
+  hipStream_t s = sv->streams[r->stream];
+  const int P = (int)r->plan->parts.size();
+  const int first = r->next_part, last = std::min(P, first + kChunkParts);
+  for (int i = first; i < last; ++i)
+    if (hs_status rc = dev_run_part(&r->st, r->plan.get(), i)) return rc;
+  r->next_part = last;
+  const int slot = (r->chunk_old + r->chunks_out) & 1;
+  if (hipEventRecord(r->chunk_ev[slot], s) != hipSuccess) return fail(HS_E_HIP, "event record failed");
+  r->chunk_work[slot] = (double)(last - first) * (double)r->st.bytes;
+  sv->load[r->stream] += r->chunk_work[slot];
+  r->chunks_out++;
+  if (last == P) {
+    hipError_t e = hipEventCreateWithFlags(&r->done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(r->done, s);
+    if (e != hipSuccess) return fail(HS_E_HIP, "event: %s", hipGetErrorString(e));
+  }
+  return HS_OK;
+}
+
+// Chunks of a running request that have finished leave the stream's load;
+// new ones are queued while fewer than two are outstanding.
+hs_status feed(hs_server_* sv, Request* r, bool* progress) {
+  while (r->chunks_out > 0 && hipEventQuery(r->chunk_ev[r->chunk_old]) == hipSuccess) {
+    sv->load[r->stream] -= r->chunk_work[r->chunk_old];
+    r->chunk_old ^= 1;
+    r->chunks_out--;
+    *progress = true;
+  }
+  while (r->next_part < (int)r->plan->parts.size() && r->chunks_out < 2) {
+    if (hs_status rc = enqueue_chunk(sv, r)) return rc;
+    *progress = true;
+  }
+  return HS_OK;
+}
+
+// Start an admitted request (called with the lock held; nothing here waits
+// on the device) on the stream with the least queued work, so that small
+// requests do not queue behind large ones when another stream is nearly
+// idle: the state, a wait for the descriptor copies, set-basis and the
+// first chunks of parts.
 hs_status launch(hs_server_* sv, Request* r) {
   int best = 0;
   for (int i = 1; i < (int)sv->streams.size(); ++i)
@@ -184,20 +242,35 @@ hs_status launch(hs_server_* sv, Request* r) {
   r->st.device = sv->device;
   r->st.stream = s;
   r->st.owned = true;
+  r->launched = true;
   hipError_t e = hipMallocAsync(&r->st.ptr, r->st.bytes, s);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     r->st.ptr = nullptr;
     return fail(HS_E_NOMEM, "hipMallocAsync(%zu): %s", r->st.bytes, hipGetErrorString(e));
   }
+  for (hipEvent_t& ev : r->chunk_ev)
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
+      return fail(HS_E_HIP, "event create failed");
+  // the descriptors were copied on a preparing stream: wait for them here,
+  // on the device
+  if (hs_status rc = dev_plan_stream_wait(r->plan.get(), r->dtype, sv->device, s)) return rc;
   if (hs_status rc = dev_set_basis(&r->st, r->init)) return rc;
-  for (int i = 0; i < (int)r->plan->parts.size(); ++i)
-    if (hs_status rc = dev_run_part(&r->st, r->plan.get(), i)) return rc;
-  e = hipEventCreateWithFlags(&r->done, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventRecord(r->done, s);
-  if (e != hipSuccess) return fail(HS_E_HIP, "event: %s", hipGetErrorString(e));
-  sv->load[best] += r->work;
-  return HS_OK;
+  bool progress = false;
+  return feed(sv, r, &progress);
+}
+
+// Give back what a failed running request holds (lock held).
+void fail_running(hs_server_* sv, Request* r, hs_status rc) {
+  r->status = RQ_FAILED;
+  r->err = rc;
+  r->err_msg = hs_last_error();
+  for (int c = 0; c < r->chunks_out; ++c) sv->load[r->stream] -= r->chunk_work[(r->chunk_old + c) & 1];
+  r->chunks_out = 0;
+  if (r->st.ptr) (void)hipFreeAsync(r->st.ptr, (hipStream_t)r->st.stream);  // after its queued kernels
+  r->st.ptr = nullptr;
+  sv->cur_bytes -= r->bytes;
+  r->t_done = now_s();
 }
 
 void worker_main(hs_server_* sv) {
@@ -205,13 +278,21 @@ void worker_main(hs_server_* sv) {
   std::unique_lock<std::mutex> lk(sv->mu);
   for (;;) {
     bool progress = false;
-    // retire finished requests
+    // feed running requests their next chunks; retire finished ones
     for (size_t i = 0; i < sv->running.size();) {
       Request* r = sv->running[i];
-      if (hipEventQuery(r->done) == hipSuccess) {
+      if (hs_status rc = feed(sv, r, &progress)) {
+        fail_running(sv, r, rc);
+        sv->running[i] = sv->running.back();
+        sv->running.pop_back();
+        progress = true;
+        continue;
+      }
+      if (r->done && hipEventQuery(r->done) == hipSuccess) {
         r->t_done = now_s();
         r->status = RQ_DONE;
-        sv->load[r->stream] -= r->work;
+        for (int c = 0; c < r->chunks_out; ++c) sv->load[r->stream] -= r->chunk_work[(r->chunk_old + c) & 1];
+        r->chunks_out = 0;
         sv->completed++;
         sv->running[i] = sv->running.back();
         sv->running.pop_back();
@@ -239,13 +320,7 @@ void worker_main(hs_server_* sv) {
       r->t_launch = now_s();
       hs_status rc = launch(sv, r);
       if (rc != HS_OK) {
-        r->status = RQ_FAILED;
-        r->err = rc;
-        r->err_msg = hs_last_error();
-        if (r->st.ptr) (void)hipFreeAsync(r->st.ptr, (hipStream_t)r->st.stream);
-        r->st.ptr = nullptr;
-        sv->cur_bytes -= r->bytes;
-        r->t_done = now_s();
+        fail_running(sv, r, rc);
       } else {
         r->status = RQ_RUNNING;
         sv->running.push_back(r);
@@ -279,11 +354,15 @@ void worker_main(hs_server_* sv) {
 
 // Free a request's device memory and handles; no lock held.
 void drop_request_memory(hs_server_* sv, std::unique_ptr<Plan> plan, void* state,
-                         hipStream_t stream, hipEvent_t ev) {
+                         hipStream_t stream, const std::vector<hipEvent_t>& events, bool drain) {
   (void)hipSetDevice(sv->device);
+  // a request that failed with parts queued: they may still read the
+  // descriptors, which are freed on another stream (rare; waits here)
+  if (drain && stream) (void)hipStreamSynchronize(stream);
   if (state) (void)hipFreeAsync(state, stream);
   plan.reset();  // descriptors: hipFreeAsync on the preparing stream
-  if (ev) (void)hipEventDestroy(ev);
+  for (hipEvent_t ev : events)
+    if (ev) (void)hipEventDestroy(ev);
 }
 
 }  // namespace
@@ -305,6 +384,10 @@ hs_status hs_server_create(size_t budget_bytes, int num_streams, hs_server* out)
   auto cleanup = [&]() {
     for (hipStream_t s : sv->streams) (void)hipStreamDestroy(s);
     for (hipStream_t s : sv->prep_streams) (void)hipStreamDestroy(s);
+    for (PinnedStaging& p : sv->pins) {
+      if (p.ptr) (void)hipHostFree(p.ptr);
+      if (p.busy) (void)hipEventDestroy((hipEvent_t)p.busy);
+    }
     if (sv->read_stream) (void)hipStreamDestroy(sv->read_stream);
     if (sv->read_scratch) (void)hipFree(sv->read_scratch);
   };
@@ -324,6 +407,20 @@ hs_status hs_server_create(size_t budget_bytes, int num_streams, hs_server* out)
       return fail(HS_E_HIP, "hipStreamCreate failed");
     }
     sv->prep_streams.push_back(s);
+    // pinned staging for its descriptor copies (without it, copies go from
+    // pageable memory)
+    PinnedStaging p;
+    hipEvent_t ev = nullptr;
+    if (hipHostMalloc(&p.ptr, kPinnedStaging, hipHostMallocDefault) == hipSuccess &&
+        hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) {
+      p.bytes = kPinnedStaging;
+      p.busy = ev;
+    } else {
+      (void)hipGetLastError();
+      if (p.ptr) (void)hipHostFree(p.ptr);
+      p = PinnedStaging{};
+    }
+    sv->pins.push_back(p);
   }
   if (!new_stream(&sv->read_stream)) {
     cleanup();
@@ -457,7 +554,8 @@ hs_status hs_server_release(hs_server sv, uint64_t ticket) {
   std::unique_ptr<Plan> plan;
   void* state = nullptr;
   hipStream_t stream = nullptr;
-  hipEvent_t ev = nullptr;
+  std::vector<hipEvent_t> events;
+  bool drain = false;
   {
     std::lock_guard<std::mutex> lk(sv->mu);
     Request* r = find(sv, ticket);
@@ -470,15 +568,19 @@ hs_status hs_server_release(hs_server sv, uint64_t ticket) {
       r->st.ptr = nullptr;
       sv->cur_bytes -= r->bytes;
     }
-    ev = r->done;
-    r->done = nullptr;
+    if (r->status == RQ_FAILED && r->launched) {
+      drain = true;
+      stream = (hipStream_t)r->st.stream;
+    }
+    events = {r->done, r->chunk_ev[0], r->chunk_ev[1]};
+    r->done = r->chunk_ev[0] = r->chunk_ev[1] = nullptr;
     plan = std::move(r->plan);
     r->status = RQ_RELEASED;
     sv->cv.notify_all();
   }
   // a finished request's kernels are complete: the frees are stream-ordered
   // and wait for nothing on the device
-  drop_request_memory(sv, std::move(plan), state, stream, ev);
+  drop_request_memory(sv, std::move(plan), state, stream, events, drain);
   return HS_OK;
 }
 
@@ -507,7 +609,8 @@ hs_status hs_server_destroy(hs_server sv) {
   for (auto& kv : sv->reqs) {
     Request* r = kv.second;
     if (r->st.ptr) (void)hipFreeAsync(r->st.ptr, (hipStream_t)r->st.stream);
-    if (r->done) (void)hipEventDestroy(r->done);
+    for (hipEvent_t ev : {r->done, r->chunk_ev[0], r->chunk_ev[1]})
+      if (ev) (void)hipEventDestroy(ev);
     delete r;  // plan descriptors: hipFreeAsync on the preparing stream
   }
   for (hipStream_t s : sv->streams) {
@@ -521,6 +624,10 @@ hs_status hs_server_destroy(hs_server sv) {
   (void)hipStreamSynchronize(sv->read_stream);
   (void)hipStreamDestroy(sv->read_stream);
   if (sv->read_scratch) (void)hipFree(sv->read_scratch);
+  for (PinnedStaging& p : sv->pins) {  // every copy from them has run
+    if (p.ptr) (void)hipHostFree(p.ptr);
+    if (p.busy) (void)hipEventDestroy((hipEvent_t)p.busy);
+  }
   delete sv;
   return HS_OK;
 }

@@ -120,3 +120,27 @@ def test_admission_follows_ticket_order_under_a_tight_budget():
     assert stats["completed"] == len(tickets)
     assert stats["cur_bytes"] == 0 and stats["peak_bytes"] <= (7 << 20) // 2
     srv.close()
+
+
+def test_small_request_overtakes_a_large_one_on_the_same_stream():
+    """Parts go to the device a chunk at a time, at most two chunks queued a
+    request: on a single stream, a one-part request admitted right behind a
+    request of some 200 parts finishes long before it, and both states
+    are right."""
+    srv = hisv.Server(num_streams=1)
+    nb, big = wl.layered28(7, n=16, layers=150)
+    ns, small = wl.layered28(8, n=10, layers=3)
+    print("[case] one stream: a large request, then a small one", flush=True)
+    tb = srv.submit(nb, big, "c128", 0, 6, "closure")
+    ts = srv.submit(ns, small, "c128", 0, 10, "closure")
+    srv.wait(tb, timeout_ms=60000)
+    srv.wait(ts, timeout_ms=60000)
+    q_b, prep_b, adm_b, dev_b = srv.timing(tb)
+    q_s, prep_s, adm_s, dev_s = srv.timing(ts)
+    assert dev_s < 0.25 * dev_b, (dev_s, dev_b)
+    for t, (n, gates) in ((tb, (nb, big)), (ts, (ns, small))):
+        got = srv.amplitudes(t, 0, 1 << n)
+        want = sv.simulate(n, gates)
+        assert np.max(np.abs(got - want)) <= 1e-12
+        srv.release(t)
+    srv.close()
