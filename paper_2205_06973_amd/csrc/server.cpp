@@ -256,6 +256,12 @@ hs_status launch(hs_server_* sv, Request* r) {
   // on the device
   if (hs_status rc = dev_plan_stream_wait(r->plan.get(), r->dtype, sv->device, s)) return rc;
   if (hs_status rc = dev_set_basis(&r->st, r->init)) return rc;
+  if (r->plan->parts.empty()) {  // no gates: set-basis is the whole request
+    hipError_t e2 = hipEventCreateWithFlags(&r->done, hipEventDisableTiming);
+    if (e2 == hipSuccess) e2 = hipEventRecord(r->done, s);
+    if (e2 != hipSuccess) return fail(HS_E_HIP, "event: %s", hipGetErrorString(e2));
+    return HS_OK;
+  }
   bool progress = false;
   return feed(sv, r, &progress);
 }

@@ -144,3 +144,16 @@ def test_small_request_overtakes_a_large_one_on_the_same_stream():
         assert np.max(np.abs(got - want)) <= 1e-12
         srv.release(t)
     srv.close()
+
+
+def test_empty_circuit_request():
+    """A request with no gates is its basis state (no parts to launch)."""
+    srv = hisv.Server(num_streams=2)
+    t = srv.submit(9, [], "c64", 5, 9, "closure")
+    srv.wait(t, timeout_ms=30000)
+    got = srv.amplitudes(t, 0, 1 << 9)
+    want = np.zeros(1 << 9, dtype=np.complex128)
+    want[5] = 1
+    np.testing.assert_array_equal(got, want)
+    srv.release(t)
+    srv.close()
