@@ -173,7 +173,9 @@ hs_status hs_device_count(int* out);
  * of the plain kernel, -1 = the measured best for the width and precision.
  * Host side: "host_threads" (0..64, default 0 = up to 8 as the host has
  * them) = threads a CLOSURE beam search may use; its plans are the same
- * for every value.  A "spec_"
+ * for every value.  "serve_chunk" (1..4096, default 8) = part-passes a
+ * serving request queues at a time (two chunks at most), read when a
+ * request is launched.  A "spec_"
  * prefix on a key sets it for the specialized kernels (PART_SPEC) instead of
  * the interpreter kernel ("contig" has no prefix: it applies to both).
  * HS_E_ARG for an unknown key or value. */

@@ -52,6 +52,7 @@ static bool g_fuse2[2] = {true, false};        // [specialized]
 // persistent grid, -1 = the measured best per width and precision
 static int g_fused_shape = -1;
 static int g_host_threads = 0;
+static int g_serve_chunk = 8;
 
 int fused_launch_shape() {
   std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -61,6 +62,11 @@ int fused_launch_shape() {
 int host_threads() {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   return g_host_threads;
+}
+
+int serve_chunk_parts() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return g_serve_chunk;
 }
 
 CompileOptions default_options(hs_dtype dtype, bool spec) {
@@ -199,6 +205,9 @@ hs_status hs_tune(const char* key, int value) {
   } else if (k == "fused_shape" && !spec) {
     CHECK_ARG(value >= -1 && value <= 2, "fused_shape must be -1, 0, 1 or 2");
     g_fused_shape = value;
+  } else if (k == "serve_chunk" && !spec) {
+    CHECK_ARG(value >= 1 && value <= 4096, "serve_chunk must be 1..4096");
+    g_serve_chunk = value;
   } else if (k == "host_threads" && !spec) {
     CHECK_ARG(value >= 0 && value <= 64, "host_threads must be 0..64");
     g_host_threads = value;

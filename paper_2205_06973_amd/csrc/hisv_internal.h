@@ -70,6 +70,8 @@ int partition_greedy(const std::vector<Gate>& gates, const Dag& dag, int k, uint
 // hs_tune("host_threads"): threads a partition search may use (0 = up to 8,
 // as the host has them).
 int host_threads();
+// hs_tune("serve_chunk"): parts a serving request enqueues at a time.
+int serve_chunk_parts();
 int partition_closure(const std::vector<Gate>& gates, const Dag& dag, int k, int width,
                       std::vector<int32_t>* part, uint64_t pad = 0);
 // Exact validity check; returns "" when valid, else the first violation.

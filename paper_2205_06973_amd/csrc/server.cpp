@@ -16,7 +16,7 @@
 //   admit     the worker thread admits prepared requests strictly in ticket
 //             order while the bytes of resident states (plus their
 //             descriptors) stay within the budget, allocates the state on the
-//             stream of a pool with the least queued work, makes that
+//             stream of a pool with the least unfinished work, makes that
 //             stream wait (on the device) for the descriptor copies, and
 //             enqueues set-basis and the part-passes -- a chunk of parts at a
 //             time, at most two chunks queued, refilled as chunks finish, so
@@ -71,6 +71,8 @@ struct Request {
   double chunk_work[2] = {0, 0};
   int chunk_old = 0;                           // slot of the oldest queued chunk
   int chunks_out = 0;                          // chunks queued, not seen finished
+  int chunk_parts = 8;                         // parts a chunk
+  double remaining = 0;                        // its work not seen finished (stream load)
   bool launched = false;                       // work was queued on its stream
   // server clock (seconds): arrival, preparation start and end, launch, done
   double t_arrival = 0, t_prep0 = 0, t_prep1 = 0, t_launch = 0, t_done = 0;
@@ -82,11 +84,11 @@ struct Request {
 constexpr int kPrepThreads = 4;
 constexpr size_t kReadScratch = size_t(64) << 20;  // covers dev_read's largest chunk
 constexpr size_t kPinnedStaging = size_t(8) << 20;  // descriptor staging per preparing thread
-// Parts a request enqueues at a time.  A hardware queue runs its commands
-// in order, so a request admitted behind a large one waits for what the
-// large one has queued: at most two chunks, a few milliseconds, instead of
-// hundreds of part-passes.
-constexpr int kChunkParts = 8;
+// Parts a request enqueues at a time (hs_tune "serve_chunk", default 8,
+// read at launch).  A hardware queue runs its commands in order, so a
+// request admitted behind a large one waits for what the large one has
+// queued: at most two chunks, a few milliseconds, instead of hundreds of
+// part-passes.
 
 }  // namespace
 
@@ -192,14 +194,13 @@ Request* find(hs_server_* sv, uint64_t t) {
 hs_status enqueue_chunk(hs_server_* sv, Request* r) {
   hipStream_t s = sv->streams[r->stream];
   const int P = (int)r->plan->parts.size();
-  const int first = r->next_part, last = std::min(P, first + kChunkParts);
+  const int first = r->next_part, last = std::min(P, first + r->chunk_parts);
   for (int i = first; i < last; ++i)
     if (hs_status rc = dev_run_part(&r->st, r->plan.get(), i)) return rc;
   r->next_part = last;
   const int slot = (r->chunk_old + r->chunks_out) & 1;
   if (hipEventRecord(r->chunk_ev[slot], s) != hipSuccess) return fail(HS_E_HIP, "event record failed");
   r->chunk_work[slot] = (double)(last - first) * (double)r->st.bytes;
-  sv->load[r->stream] += r->chunk_work[slot];
   r->chunks_out++;
   if (last == P) {
     hipError_t e = hipEventCreateWithFlags(&r->done, hipEventDisableTiming);
@@ -214,6 +215,7 @@ hs_status enqueue_chunk(hs_server_* sv, Request* r) {
 hs_status feed(hs_server_* sv, Request* r, bool* progress) {
   while (r->chunks_out > 0 && hipEventQuery(r->chunk_ev[r->chunk_old]) == hipSuccess) {
     sv->load[r->stream] -= r->chunk_work[r->chunk_old];
+    r->remaining -= r->chunk_work[r->chunk_old];
     r->chunk_old ^= 1;
     r->chunks_out--;
     *progress = true;
@@ -226,15 +228,18 @@ hs_status feed(hs_server_* sv, Request* r, bool* progress) {
 }
 
 // Start an admitted request (called with the lock held; nothing here waits
-// on the device) on the stream with the least queued work, so that small
-// requests do not queue behind large ones when another stream is nearly
-// idle: the state, a wait for the descriptor copies, set-basis and the
-// first chunks of parts.
+// on the device) on the stream with the least unfinished work (all parts of
+// its requests, queued or not), so that requests spread over the streams:
+// the state, a wait for the descriptor copies, set-basis and the first
+// chunks of parts.
 hs_status launch(hs_server_* sv, Request* r) {
   int best = 0;
   for (int i = 1; i < (int)sv->streams.size(); ++i)
     if (sv->load[i] < sv->load[best]) best = i;
   r->stream = best;
+  r->chunk_parts = serve_chunk_parts();
+  r->remaining = (double)r->plan->parts.size() * (double)((size_t(1) << r->n) * amp_bytes(r->dtype));
+  sv->load[best] += r->remaining;
   hipStream_t s = sv->streams[best];
   r->st.n = r->n;
   r->st.dtype = r->dtype;
@@ -271,7 +276,8 @@ void fail_running(hs_server_* sv, Request* r, hs_status rc) {
   r->status = RQ_FAILED;
   r->err = rc;
   r->err_msg = hs_last_error();
-  for (int c = 0; c < r->chunks_out; ++c) sv->load[r->stream] -= r->chunk_work[(r->chunk_old + c) & 1];
+  if (r->stream >= 0) sv->load[r->stream] -= r->remaining;
+  r->remaining = 0;
   r->chunks_out = 0;
   if (r->st.ptr) (void)hipFreeAsync(r->st.ptr, (hipStream_t)r->st.stream);  // after its queued kernels
   r->st.ptr = nullptr;
@@ -297,7 +303,8 @@ void worker_main(hs_server_* sv) {
       if (r->done && hipEventQuery(r->done) == hipSuccess) {
         r->t_done = now_s();
         r->status = RQ_DONE;
-        for (int c = 0; c < r->chunks_out; ++c) sv->load[r->stream] -= r->chunk_work[(r->chunk_old + c) & 1];
+        sv->load[r->stream] -= r->remaining;
+        r->remaining = 0;
         r->chunks_out = 0;
         sv->completed++;
         sv->running[i] = sv->running.back();
