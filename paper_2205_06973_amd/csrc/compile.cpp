@@ -530,17 +530,18 @@ namespace hisv {
 // Relative cost of a part on the interpreter kernel (one HBM sweep of the
 // state = 1), fitted to per-part timings of 30-qubit states (random,
 // layered and dressed-pair circuits; 820 parts, mean |log error| 0.05): a
-// smooth maximum of the sweep (+0.03 / 0.02 per LDS re-layout, complex64 /
-// complex128) and the vector-ALU work -- 0.005 / 0.004 sweep per flop per
-// amplitude (Sec. III.A's counting) plus 0.03 per register op for the
-// interpreter's dispatch and register copies.  Used by AUTO only.
+// smooth maximum of the sweep (+0.04 / 0.02 per LDS re-layout, complex64 /
+// complex128) and the vector-ALU work -- 0.0065 / 0.005 sweep per flop per
+// amplitude (Sec. III.A's counting), plus 0.005 per register op for
+// complex128 (the dispatch; the register ops no longer copy the sub-state
+// back).  Used by AUTO only.
 double lds_part_cost(const CompiledPart& cp, hs_dtype dt) {
   static const double flops[OP_NUM] = {14, 6, 6, 3, 0, 0, 0.5, 1.5, 0, 30};
   const bool f32 = dt == HS_C64;
-  const double mem = 1.0 + (f32 ? 0.03 : 0.02) * cp.lds_round_trips;
+  const double mem = 1.0 + (f32 ? 0.04 : 0.02) * cp.lds_round_trips;
   double f = 0;
   for (const HostOp& op : cp.ops) f += flops[op.kind];
-  const double alu = (f32 ? 0.005 : 0.004) * f + 0.03 * (double)cp.ops.size();
+  const double alu = (f32 ? 0.0065 : 0.005) * f + (f32 ? 0.0 : 0.005) * (double)cp.ops.size();
   return std::cbrt(mem * mem * mem + alu * alu * alu);
 }
 
