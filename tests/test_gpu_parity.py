@@ -104,7 +104,8 @@ def test_layered_20_k6(dtype, mode):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-@pytest.mark.parametrize("mode,strategy", [("part_lds", "dfs"), ("part_spec", "dagp")])
+@pytest.mark.parametrize("mode,strategy", [("part_lds", "dfs"), ("part_spec", "dagp"),
+                                           ("part_lds", "closure"), ("part_spec", "closure")])
 def test_qft_closed_form_18(dtype, mode, strategy):
     n = 18
     x = wl.random_basis_index(n, 5)
@@ -210,7 +211,8 @@ def test_errors_through_the_abi():
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-@pytest.mark.parametrize("n,strategy", [(12, "dfs"), (14, "nat"), (17, "dagp"), (18, "dfs")])
+@pytest.mark.parametrize("n,strategy", [(12, "dfs"), (14, "nat"), (17, "dagp"), (18, "dfs"),
+                                        (16, "closure"), (18, "greedy")])
 @pytest.mark.parametrize("mode", ["part_lds", "part_spec"])
 def test_multilevel_parity(n, strategy, mode, dtype):
     """Multi-level plans: parts fill the widest tile (14 / 13 qubits with padding)."""
@@ -243,7 +245,7 @@ def test_multilevel_qft_closed_form(dtype):
 
 @pytest.mark.parametrize("dtype,tile", [("c64", 14), ("c128", 13)])
 @pytest.mark.parametrize("lds_kib", [64, 16])
-@pytest.mark.parametrize("n,strategy", [(15, "dfs"), (18, "dagp")])
+@pytest.mark.parametrize("n,strategy", [(15, "dfs"), (18, "dagp"), (17, "closure")])
 def test_split_relayout_parity(n, strategy, dtype, tile, lds_kib):
     """Widest tiles, with LDS re-layouts run in 2 (64 KiB limit) or 4 (16 KiB)
     rounds over a quarter or half of the tile."""
