@@ -418,12 +418,17 @@ typedef struct hs_server_* hs_server;
 
 /* A server owns a pool of `num_streams` HIP streams on the current device,
  * four host threads that prepare requests (partition, compile, upload the
- * kernel descriptors) and a worker thread that admits, launches and retires
- * them.  Requests are admitted while the device bytes of resident states
- * (plus their descriptors) stay within `budget_bytes` (0 = free device
- * memory at creation minus a 4 GiB reserve); several requests are in flight
- * on the device at once.  A prepared request's descriptors (a few KiB per
- * part) are on the device before it is admitted. */
+ * kernel descriptors from 8 MiB of pinned staging each) and a worker thread
+ * that admits, launches and retires them.  Requests are admitted in ticket
+ * order while the device bytes of resident states (plus their descriptors)
+ * stay within `budget_bytes` (0 = free device memory at creation minus a
+ * 4 GiB reserve); several requests are in flight on the device at once.
+ * A request's descriptor copies (a few KiB per part) are queued before it is
+ * admitted, and its stream waits for them on the device; its part-passes
+ * are queued a chunk at a time (hs_tune "serve_chunk"), at most two chunks
+ * outstanding, so later requests on the same hardware queue are not held
+ * behind all of them.  Returns HS_E_HIP / HS_E_NOMEM if streams or buffers
+ * cannot be created. */
 hs_status hs_server_create(size_t budget_bytes, int num_streams, hs_server* out);
 
 /* The server clock (seconds, monotonic) against which arrival times and
@@ -431,8 +436,9 @@ hs_status hs_server_create(size_t budget_bytes, int num_streams, hs_server* out)
 hs_status hs_server_clock(hs_server sv, double* seconds);
 
 /* Queue a circuit (copied and validated here) to be partitioned with limit
- * k by `strategy` (DFS and GREEDY with 16 trials, CLOSURE with beam width 1), simulated from
- * |init_basis> in `dtype`, and kept resident until released.  `arrival_s`
+ * k by `strategy` (DFS and GREEDY with 16 trials, CLOSURE with beam
+ * width 1), simulated from |init_basis> in `dtype`, and kept resident until
+ * released.  `arrival_s`
  * is the request's arrival time on the server clock, where its latency
  * starts (negative: the time of this call; HS_E_ARG if it lies after the
  * call).  Returns a ticket.  HS_E_ADMISSION if the state alone can never fit
