@@ -339,6 +339,112 @@ def test_greedy_not_below_brute_force(seed):
 
 # ---- closure partitioner -----------------------------------------------------------
 
+def _closure_reference(n, gates, k, pad=0):
+    """The plain closure rule (beam width 1), written out: a part is the
+    closure of a qubit set Q from the front; Q grows from the padding by the
+    frontier gate whose qubits give the closure with the most two-qubit
+    gates (fewer qubits, then the earlier frontier gate, on ties), then one
+    qubit of Q (lowest first, never a padding qubit) is exchanged for one of
+    the frontier's (lowest first) while that count grows.  The frontier is
+    listed as the library lists it: ready gates in index order, then the
+    gates the closure frees, in the order a depth-first walk frees them."""
+    G = len(gates)
+    qs = [{g[1]} | ({g[2]} if g[2] >= 0 else set()) for g in gates]
+    mask = [sum(1 << q for q in x) for x in qs]
+    weight = [1 if len(x) > 1 else 0 for x in qs]
+    last, pred, succ = {}, [[] for _ in gates], [[] for _ in gates]
+    for j, x in enumerate(qs):
+        for q in sorted(x):
+            i = last.get(q)
+            if i is not None and j not in succ[i]:
+                succ[i].append(j)
+                pred[j].append(i)
+            last[q] = j
+    placed = [False] * G
+    part = [-1] * G
+    pc = lambda v: bin(v).count("1")  # noqa: E731
+
+    def evaluate(Q, ready):
+        stack = [i for i in ready if not mask[i] & ~Q]
+        front = [i for i in ready if mask[i] & ~Q]
+        tin, w, take = {}, 0, []
+        while stack:
+            i = stack.pop()
+            w += weight[i]
+            take.append(i)
+            for t in succ[i]:
+                if t not in tin:
+                    tin[t] = sum(not placed[p] for p in pred[t])
+                tin[t] -= 1
+                if tin[t] == 0:
+                    (front if mask[t] & ~Q else stack).append(t)
+        return w, take, front
+
+    def score(Q, ready):
+        return (evaluate(Q, ready)[0] << 8) - pc(Q)
+
+    def grow(Q, ready):
+        while True:
+            best, best_s = Q, None
+            for f in evaluate(Q, ready)[2]:
+                c = Q | mask[f]
+                if c == Q or pc(c) > k:
+                    continue
+                sc = score(c, ready)
+                if best_s is None or sc > best_s:
+                    best, best_s = c, sc
+            if best == Q:
+                return Q
+            Q = best
+
+    def improve(Q, ready):
+        cur = evaluate(Q, ready)[0]
+        for _ in range(4 * k):
+            inn = 0
+            for f in evaluate(Q, ready)[2]:
+                inn |= mask[f]
+            inn &= ~Q
+            moved = False
+            for qo in [1 << b for b in range(64) if (Q & ~pad) >> b & 1]:
+                for qi in [1 << b for b in range(64) if inn >> b & 1]:
+                    w = evaluate((Q & ~qo) | qi, ready)[0]
+                    if w > cur:
+                        Q, cur, moved = (Q & ~qo) | qi, w, True
+                        break
+                if moved:
+                    break
+            if not moved:
+                return Q
+        return Q
+
+    pid = 0
+    while not all(placed):
+        ready = [i for i in range(G) if not placed[i] and all(placed[p] for p in pred[i])]
+        seeds = []
+        for f in evaluate(pad, ready)[2]:
+            c = pad | mask[f]
+            if c != pad and pc(c) <= k and c not in [s_[1] for s_ in seeds]:
+                seeds.append((score(c, ready), c))
+        seeds.sort(key=lambda s_: -s_[0])  # stable: ties keep front order
+        Q = improve(grow(seeds[0][1] if seeds else pad, ready), ready)
+        for i in evaluate(Q, ready)[1]:
+            placed[i] = True
+            part[i] = pid
+        pid += 1
+    return part
+
+
+@pytest.mark.parametrize("name,make", CIRCUITS)
+@pytest.mark.parametrize("k", [2, 3, 5, 7])
+def test_closure_plain_rule_matches_reference(name, make, k):
+    n, gates = make()
+    got = hisv.Plan.partition(hisv.Circuit(n, gates), k, "closure", seed=0, trials=1)
+    assert got.part_of_gate().tolist() == _closure_reference(n, gates, k)
+    if k >= 5:  # multi-level: qubits 0..2 in every part
+        got = hisv.Plan.partition_multilevel(hisv.Circuit(n, gates), k, 3, "closure", seed=0, trials=1)
+        assert got.part_of_gate().tolist() == _closure_reference(n, gates, k, pad=0b111)
+
+
 @pytest.mark.parametrize("name,make", CIRCUITS)
 @pytest.mark.parametrize("k", [2, 3, 5, 7])
 def test_closure_valid_and_deterministic(name, make, k):
