@@ -789,3 +789,18 @@ def test_auto_choice_follows_the_cost_model():
     q = hisv.Plan.partition(hisv.Circuit(n, light), 7, "greedy", seed=0, trials=8)
     for dt in ("c64", "c128"):
         assert q.auto_choice(dt).sum() <= q.num_parts // 4
+
+
+def test_tune_rejects_out_of_range_values():
+    """Every tuning key checks its range (HS_E_ARG), and unknown keys are
+    refused; valid values are accepted and restored."""
+    bad = [("serve_chunk", 0), ("serve_chunk", 5000), ("host_threads", -1), ("host_threads", 65),
+           ("fused_shape", 3), ("contig", 9), ("min_tile", 17), ("rb_c128", 4), ("spec_rb_c64", 6),
+           ("spec_lds_limit_kib", 8), ("grid", 65), ("xcd", 2), ("no_such_key", 1)]
+    for key, value in bad:
+        with pytest.raises(hisv.HisvError) as e:
+            hisv.hs_tune(key, value)
+        assert e.value.code == "HS_E_ARG", key
+    for key, value, default in [("serve_chunk", 32, 8), ("host_threads", 2, 0), ("fused_shape", 2, -1)]:
+        hisv.hs_tune(key, value)
+        hisv.hs_tune(key, default)
