@@ -6,6 +6,7 @@
     python -m paper_2205_06973_amd.profiling mfma <counters.csv> <stats.csv> <out.txt> "<command>"
     python -m paper_2205_06973_amd.profiling valu <counters.csv> <stats.csv> <out.txt> "<command>"
     python -m paper_2205_06973_amd.profiling waits <counters.csv> <stats.csv> <out.txt> "<command>"
+    python -m paper_2205_06973_amd.profiling issue <counters_a.csv> <counters_b.csv> <out.txt> "<command>"
     python -m paper_2205_06973_amd.profiling runs <kernel_trace.csv> <bench.json> <out.txt> "<command>" \
         [--kernel K] [--per-case N]
     python -m paper_2205_06973_amd.profiling kernel_traffic <fetch.csv> <write.csv> <stats.csv> <out.txt> \
@@ -23,6 +24,10 @@ SQ_VALU_MFMA_BUSY_CYCLES GRBM_GUI_ACTIVE` run and the matching kernel-trace
 stats: per matrix-core kernel, flops per dispatch (MOPS x 512), achieved
 TFLOP/s over the traced average duration, and the busy fraction of the SIMDs'
 matrix cores (GRBM_GUI_ACTIVE is summed over the 8 XCDs; 1024 SIMDs).
+`valu`, `waits` and `issue` summarise vector-ALU, wait-state and issue
+counters the same way; `runs` splits a kernel trace into per-size runs of a
+probe; `kernel_traffic` gives calibrated bytes per dispatch for every sweep
+kernel of a run.
 """
 
 from __future__ import annotations
