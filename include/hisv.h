@@ -471,7 +471,9 @@ hs_status hs_server_latency(hs_server sv, uint64_t ticket, double* seconds);
 hs_status hs_server_timing(hs_server sv, uint64_t ticket, double* out4);
 
 /* Free a finished request's device memory (its bytes return to the budget).
- * Stream-ordered frees: no device-wide wait. */
+ * Stream-ordered frees: no device-wide wait.  Waits for hs_server_read calls
+ * on the same ticket that are copying when it is called; reads that start
+ * after it fail with HS_E_STATE. */
 hs_status hs_server_release(hs_server sv, uint64_t ticket);
 
 /* Counters: requests completed, peak admitted bytes, current admitted bytes,

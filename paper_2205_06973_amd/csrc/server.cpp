@@ -74,6 +74,7 @@ struct Request {
   int chunk_parts = 8;                         // parts a chunk
   double remaining = 0;                        // its work not seen finished (stream load)
   bool launched = false;                       // work was queued on its stream
+  int readers = 0;                             // hs_server_read calls copying its state
   // server clock (seconds): arrival, preparation start and end, launch, done
   double t_arrival = 0, t_prep0 = 0, t_prep1 = 0, t_launch = 0, t_done = 0;
   ReqStatus status = RQ_QUEUED;
@@ -519,24 +520,34 @@ hs_status hs_server_poll(hs_server sv, uint64_t ticket, int* done) {
 hs_status hs_server_read(hs_server sv, uint64_t ticket, uint64_t first, uint64_t count, double* out) {
   if (!sv || (!out && count)) return fail(HS_E_ARG, "null argument");
   State view;
+  Request* reader = nullptr;
   {
     std::lock_guard<std::mutex> lk(sv->mu);
     Request* r = find(sv, ticket);
     if (!r) return fail(HS_E_ARG, "unknown ticket");
+    if (r->status == RQ_RELEASED) return fail(HS_E_STATE, "ticket was released");
     if (r->status != RQ_DONE) return fail(HS_E_STATE, "ticket is not finished");
     const uint64_t N = uint64_t(1) << r->n;
     if (first > N || count > N - first) return fail(HS_E_ARG, "range outside the state");
+    if (!count) return HS_OK;
     view = r->st;
+    reader = r;
+    r->readers++;  // hs_server_release waits for this read before freeing the state
   }
-  if (!count) return HS_OK;
-  // read on a stream of its own (the request's kernels have finished),
-  // staged through the server's persistent buffer
-  std::lock_guard<std::mutex> rl(sv->read_mu);
-  view.stream = sv->read_stream;
-  view.owned = false;
-  view.scratch = sv->read_scratch;
-  view.scratch_bytes = kReadScratch;
-  return dev_read(&view, first, count, out, false);
+  hs_status rc;
+  {
+    // read on a stream of its own (the request's kernels have finished),
+    // staged through the server's persistent buffer
+    std::lock_guard<std::mutex> rl(sv->read_mu);
+    view.stream = sv->read_stream;
+    view.owned = false;
+    view.scratch = sv->read_scratch;
+    view.scratch_bytes = kReadScratch;
+    rc = dev_read(&view, first, count, out, false);
+  }
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (--reader->readers == 0) sv->cv.notify_all();
+  return rc;
 }
 
 hs_status hs_server_latency(hs_server sv, uint64_t ticket, double* seconds) {
@@ -570,9 +581,12 @@ hs_status hs_server_release(hs_server sv, uint64_t ticket) {
   std::vector<hipEvent_t> events;
   bool drain = false;
   {
-    std::lock_guard<std::mutex> lk(sv->mu);
+    std::unique_lock<std::mutex> lk(sv->mu);
     Request* r = find(sv, ticket);
     if (!r) return fail(HS_E_ARG, "unknown ticket");
+    // reads of its state still copying finish first (a read that starts
+    // later finds the ticket released)
+    sv->cv.wait(lk, [&] { return r->readers == 0; });
     if (r->status == RQ_RELEASED) return HS_OK;
     if (r->status != RQ_DONE && r->status != RQ_FAILED) return fail(HS_E_STATE, "ticket is not finished");
     if (r->status == RQ_DONE) {

@@ -157,3 +157,46 @@ def test_empty_circuit_request():
     np.testing.assert_array_equal(got, want)
     srv.release(t)
     srv.close()
+
+
+def test_release_waits_for_reads_in_flight():
+    """Reads of a finished request running on other threads while it is
+    released: each one either returns the whole state unchanged or fails
+    with HS_E_STATE (the ticket was released first); release returns after
+    the reads that had started, and later reads fail."""
+    import threading
+    srv = hisv.Server(num_streams=2)
+    n, gates = wl.layered28(11, n=20, layers=4)
+    t = srv.submit(n, gates, "c128", 0, 6, "closure")
+    srv.wait(t, timeout_ms=60000)
+    ref = srv.amplitudes(t, 0, 1 << n)
+    want = sv.simulate(n, gates)
+    assert np.max(np.abs(ref - want)) <= 1e-12
+    print("[case] 20-qubit request: 2 reader threads racing a release", flush=True)
+    results, errors = [], []
+    start = threading.Event()
+
+    def reader():
+        start.wait()
+        for _ in range(8):
+            try:
+                results.append(srv.amplitudes(t, 0, 1 << n))
+            except hisv.HisvError as e:
+                errors.append(e)
+
+    threads = [threading.Thread(target=reader) for _ in range(2)]
+    for th in threads:
+        th.start()
+    start.set()
+    srv.release(t)
+    for th in threads:
+        th.join(timeout=60)
+        assert not th.is_alive()
+    assert len(results) + len(errors) == 16
+    for got in results:
+        np.testing.assert_array_equal(got, ref)
+    for e in errors:
+        assert e.code == "HS_E_STATE" and "released" in str(e), str(e)
+    with pytest.raises(hisv.HisvError, match="released"):
+        srv.amplitudes(t, 0, 16)
+    srv.close()
