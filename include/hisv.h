@@ -52,8 +52,10 @@ typedef enum {
   HS_E_HIP = 6,            /* a HIP runtime call failed (message has the HIP error)   */
   HS_E_BAD_PARTITION = 7,  /* a plan failed exact validation                          */
   HS_E_STATE = 8,          /* wrong object state (e.g. reading an unfinished ticket)  */
-  HS_E_UNSUPPORTED = 9     /* a valid request this build does not handle (e.g. a part
+  HS_E_UNSUPPORTED = 9,    /* a valid request this build does not handle (e.g. a part
                               wider than the largest kernel tile)                     */
+  HS_E_INTERNAL = 10       /* an unexpected host-side failure (e.g. a host thread could
+                              not be started); the message names it                   */
 } hs_status;
 
 typedef enum { HS_C64 = 0, HS_C128 = 1 } hs_dtype;

@@ -4,7 +4,9 @@
 #include <stdint.h>
 
 #include <complex>
+#include <exception>
 #include <map>
+#include <new>
 #include <memory>
 #include <mutex>
 #include <thread>
@@ -21,6 +23,23 @@ using cd = std::complex<double>;
 // ---- errors ---------------------------------------------------------------
 hs_status fail(hs_status code, const char* fmt, ...);
 void clear_error();
+
+// No exception crosses the C boundary or ends a library thread: each entry
+// point and each thread body runs inside guarded(), which returns a failed
+// allocation as HS_E_NOMEM and any other exception (a thread that could not
+// be started, ...) as HS_E_INTERNAL.
+template <class F>
+hs_status guarded(F&& body) noexcept {
+  try {
+    return body();
+  } catch (const std::bad_alloc&) {
+    return fail(HS_E_NOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(HS_E_INTERNAL, "%s", e.what());
+  } catch (...) {
+    return fail(HS_E_INTERNAL, "unexpected exception");
+  }
+}
 
 // ---- gates (Sec. II.A) ----------------------------------------------------
 struct Gate {

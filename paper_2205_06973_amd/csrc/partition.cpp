@@ -14,6 +14,7 @@
 #include <climits>
 #include <atomic>
 #include <memory>
+#include <stdexcept>
 #include <thread>
 
 #include "hisv_internal.h"
@@ -491,11 +492,14 @@ int partition_closure(const std::vector<Gate>& gates, const Dag& dag, int k, int
     }
   };
 
-  if (T == 1) {
+  auto alone = [&]() {
     while (!done) {
       expand(0);
       select();
     }
+  };
+  if (T == 1) {
+    alone();
   } else {
     // a spinning barrier: a level's work is a fraction of a millisecond,
     // about what waking a sleeping thread costs
@@ -514,19 +518,54 @@ int partition_closure(const std::vector<Gate>& gates, const Dag& dag, int k, int
         }
       }
     } bar(T);
+    // an exception on any thread ends the search for all of them (after the
+    // level's barrier) and is raised again on the calling thread
+    std::atomic<int> failed{HS_OK};
     auto team = [&](int t) {
       for (;;) {
-        expand(t);
+        hs_status rc = guarded([&] {
+          expand(t);
+          return HS_OK;
+        });
+        if (rc != HS_OK) failed.store(rc);
         bar.wait();
-        if (t == 0) select();
+        if (t == 0) {
+          if (failed.load() == HS_OK && (rc = guarded([&] {
+                                           select();
+                                           return HS_OK;
+                                         })) != HS_OK)
+            failed.store(rc);
+          if (failed.load() != HS_OK) done = true;
+        }
         bar.wait();
         if (done) return;
       }
     };
+    // the helpers start only once all of them exist; if one cannot be
+    // started, the others leave and the search runs on this thread alone
+    std::atomic<int> go{0};
     std::vector<std::thread> pool;
-    for (int t = 1; t < T; ++t) pool.emplace_back(team, t);
-    team(0);
-    for (auto& th : pool) th.join();
+    pool.reserve(T - 1);
+    try {
+      for (int t = 1; t < T; ++t)
+        pool.emplace_back([&, t] {
+          while (go.load(std::memory_order_acquire) == 0) std::this_thread::yield();
+          if (go.load(std::memory_order_acquire) > 0) team(t);
+        });
+    } catch (...) {
+      go.store(-1, std::memory_order_release);
+      for (auto& th : pool) th.join();
+      pool.clear();
+    }
+    if (pool.size() + 1 == (size_t)T) {
+      go.store(1, std::memory_order_release);
+      team(0);
+      for (auto& th : pool) th.join();
+      if (failed.load() == HS_E_NOMEM) throw std::bad_alloc();
+      if (failed.load() != HS_OK) throw std::runtime_error("closure search failed on a host thread");
+    } else {
+      alone();
+    }
   }
   if (result < 0) return partition_nat(gates, k, part, pad);
   if (B > 1) {  // never more parts than the plain rule

@@ -168,18 +168,20 @@ void prep_main(hs_server_* sv, int idx) {
     r->status = RQ_PREPARING;
     lk.unlock();
     r->t_prep0 = now_s();
-    const hs_status rc = prepare(sv, r, stream, &sv->pins[idx]);
-    const std::string msg = rc ? hs_last_error() : "";
+    hs_status rc = guarded([&] { return prepare(sv, r, stream, &sv->pins[idx]); });
     r->t_prep1 = now_s();
     lk.lock();
+    if (rc == HS_OK) rc = guarded([&] {
+      sv->ready.emplace(r->ticket, r);
+      return HS_OK;
+    });
     if (rc) {
       r->status = RQ_FAILED;
       r->err = rc;
-      r->err_msg = msg;
+      r->err_msg = hs_last_error();  // this thread's message
       r->t_done = r->t_prep1;
     } else {
       r->status = RQ_READY;
-      sv->ready.emplace(r->ticket, r);
     }
     sv->cv.notify_all();
   }
@@ -294,7 +296,7 @@ void worker_main(hs_server_* sv) {
     // feed running requests their next chunks; retire finished ones
     for (size_t i = 0; i < sv->running.size();) {
       Request* r = sv->running[i];
-      if (hs_status rc = feed(sv, r, &progress)) {
+      if (hs_status rc = guarded([&] { return feed(sv, r, &progress); })) {
         fail_running(sv, r, rc);
         sv->running[i] = sv->running.back();
         sv->running.pop_back();
@@ -332,12 +334,15 @@ void worker_main(hs_server_* sv) {
       sv->cur_bytes += r->bytes;
       sv->peak_bytes = std::max(sv->peak_bytes, sv->cur_bytes);
       r->t_launch = now_s();
-      hs_status rc = launch(sv, r);
+      hs_status rc = guarded([&] { return launch(sv, r); });
+      if (rc == HS_OK) rc = guarded([&] {
+        sv->running.push_back(r);
+        return HS_OK;
+      });
       if (rc != HS_OK) {
         fail_running(sv, r, rc);
       } else {
         r->status = RQ_RUNNING;
-        sv->running.push_back(r);
         sv->peak_inflight = std::max(sv->peak_inflight, (int)sv->running.size());
       }
       progress = true;
@@ -384,279 +389,319 @@ void drop_request_memory(hs_server_* sv, std::unique_ptr<Plan> plan, void* state
 extern "C" {
 
 hs_status hs_server_create(size_t budget_bytes, int num_streams, hs_server* out) {
-  if (!out) return fail(HS_E_ARG, "null output");
-  if (num_streams < 1 || num_streams > 64) return fail(HS_E_ARG, "num_streams %d", num_streams);
-  auto sv = std::make_unique<hs_server_>();
-  if (hipGetDevice(&sv->device) != hipSuccess) return fail(HS_E_HIP, "no HIP device");
-  size_t free_b = 0, total_b = 0;
-  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return fail(HS_E_HIP, "hipMemGetInfo failed");
-  const size_t reserve = size_t(4) << 30;
-  sv->budget = budget_bytes ? budget_bytes : (free_b > reserve ? free_b - reserve : free_b / 2);
-  auto new_stream = [](hipStream_t* s) {
-    return hipStreamCreateWithFlags(s, hipStreamNonBlocking) == hipSuccess;
-  };
-  auto cleanup = [&]() {
-    for (hipStream_t s : sv->streams) (void)hipStreamDestroy(s);
-    for (hipStream_t s : sv->prep_streams) (void)hipStreamDestroy(s);
-    for (PinnedStaging& p : sv->pins) {
-      if (p.ptr) (void)hipHostFree(p.ptr);
-      if (p.busy) (void)hipEventDestroy((hipEvent_t)p.busy);
+  return guarded([&]() -> hs_status {
+    if (!out) return fail(HS_E_ARG, "null output");
+    if (num_streams < 1 || num_streams > 64) return fail(HS_E_ARG, "num_streams %d", num_streams);
+    auto sv = std::make_unique<hs_server_>();
+    if (hipGetDevice(&sv->device) != hipSuccess) return fail(HS_E_HIP, "no HIP device");
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return fail(HS_E_HIP, "hipMemGetInfo failed");
+    const size_t reserve = size_t(4) << 30;
+    sv->budget = budget_bytes ? budget_bytes : (free_b > reserve ? free_b - reserve : free_b / 2);
+    auto new_stream = [](hipStream_t* s) {
+      return hipStreamCreateWithFlags(s, hipStreamNonBlocking) == hipSuccess;
+    };
+    auto cleanup = [&]() {
+      for (hipStream_t s : sv->streams) (void)hipStreamDestroy(s);
+      for (hipStream_t s : sv->prep_streams) (void)hipStreamDestroy(s);
+      for (PinnedStaging& p : sv->pins) {
+        if (p.ptr) (void)hipHostFree(p.ptr);
+        if (p.busy) (void)hipEventDestroy((hipEvent_t)p.busy);
+      }
+      if (sv->read_stream) (void)hipStreamDestroy(sv->read_stream);
+      if (sv->read_scratch) (void)hipFree(sv->read_scratch);
+    };
+    for (int i = 0; i < num_streams; ++i) {
+      hipStream_t s;
+      if (!new_stream(&s)) {
+        cleanup();
+        return fail(HS_E_HIP, "hipStreamCreate failed");
+      }
+      sv->streams.push_back(s);
+      sv->load.push_back(0);
     }
-    if (sv->read_stream) (void)hipStreamDestroy(sv->read_stream);
-    if (sv->read_scratch) (void)hipFree(sv->read_scratch);
-  };
-  for (int i = 0; i < num_streams; ++i) {
-    hipStream_t s;
-    if (!new_stream(&s)) {
+    for (int i = 0; i < kPrepThreads; ++i) {
+      hipStream_t s;
+      if (!new_stream(&s)) {
+        cleanup();
+        return fail(HS_E_HIP, "hipStreamCreate failed");
+      }
+      sv->prep_streams.push_back(s);
+      // pinned staging for its descriptor copies (without it, copies go from
+      // pageable memory)
+      PinnedStaging p;
+      hipEvent_t ev = nullptr;
+      if (hipHostMalloc(&p.ptr, kPinnedStaging, hipHostMallocDefault) == hipSuccess &&
+          hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) {
+        p.bytes = kPinnedStaging;
+        p.busy = ev;
+      } else {
+        (void)hipGetLastError();
+        if (p.ptr) (void)hipHostFree(p.ptr);
+        p = PinnedStaging{};
+      }
+      sv->pins.push_back(p);
+    }
+    if (!new_stream(&sv->read_stream)) {
       cleanup();
       return fail(HS_E_HIP, "hipStreamCreate failed");
     }
-    sv->streams.push_back(s);
-    sv->load.push_back(0);
-  }
-  for (int i = 0; i < kPrepThreads; ++i) {
-    hipStream_t s;
-    if (!new_stream(&s)) {
-      cleanup();
-      return fail(HS_E_HIP, "hipStreamCreate failed");
-    }
-    sv->prep_streams.push_back(s);
-    // pinned staging for its descriptor copies (without it, copies go from
-    // pageable memory)
-    PinnedStaging p;
-    hipEvent_t ev = nullptr;
-    if (hipHostMalloc(&p.ptr, kPinnedStaging, hipHostMallocDefault) == hipSuccess &&
-        hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) {
-      p.bytes = kPinnedStaging;
-      p.busy = ev;
-    } else {
+    if (hipMalloc(&sv->read_scratch, kReadScratch) != hipSuccess) {
       (void)hipGetLastError();
-      if (p.ptr) (void)hipHostFree(p.ptr);
-      p = PinnedStaging{};
+      sv->read_scratch = nullptr;
+      cleanup();
+      return fail(HS_E_NOMEM, "read staging buffer of %zu bytes", kReadScratch);
     }
-    sv->pins.push_back(p);
-  }
-  if (!new_stream(&sv->read_stream)) {
-    cleanup();
-    return fail(HS_E_HIP, "hipStreamCreate failed");
-  }
-  if (hipMalloc(&sv->read_scratch, kReadScratch) != hipSuccess) {
-    (void)hipGetLastError();
-    sv->read_scratch = nullptr;
-    cleanup();
-    return fail(HS_E_NOMEM, "read staging buffer of %zu bytes", kReadScratch);
-  }
-  hs_server_* raw = sv.release();
-  raw->worker = std::thread(worker_main, raw);
-  for (int i = 0; i < kPrepThreads; ++i) raw->preppers.emplace_back(prep_main, raw, i);
-  *out = raw;
-  return HS_OK;
+    hs_server_* raw = sv.get();
+    try {
+      raw->worker = std::thread(worker_main, raw);
+      for (int i = 0; i < kPrepThreads; ++i) raw->preppers.emplace_back(prep_main, raw, i);
+    } catch (const std::exception& e) {  // a thread could not be started: stop the others
+      {
+        std::lock_guard<std::mutex> lk(raw->mu);
+        raw->stop = true;
+        raw->cv.notify_all();
+      }
+      for (auto& t : raw->preppers)
+        if (t.joinable()) t.join();
+      if (raw->worker.joinable()) raw->worker.join();
+      cleanup();
+      return fail(HS_E_INTERNAL, "server threads: %s", e.what());
+    }
+    *out = sv.release();
+    return HS_OK;
+  });
 }
 
 hs_status hs_server_clock(hs_server sv, double* seconds) {
-  if (!sv || !seconds) return fail(HS_E_ARG, "null argument");
-  *seconds = now_s();
-  return HS_OK;
+  return guarded([&]() -> hs_status {
+    if (!sv || !seconds) return fail(HS_E_ARG, "null argument");
+    *seconds = now_s();
+    return HS_OK;
+  });
 }
 
 hs_status hs_server_submit(hs_server sv, int n, const hs_gate* gates, size_t count, hs_dtype dtype,
                            uint64_t init_basis, int k, hs_strategy strategy, double arrival_s,
                            uint64_t* ticket) {
-  const double t_call = now_s();
-  if (!sv || !ticket || (!gates && count)) return fail(HS_E_ARG, "null argument");
-  if (n < 1 || n > 40) return fail(HS_E_ARG, "n = %d outside [1, 40]", n);
-  if (dtype != HS_C64 && dtype != HS_C128) return fail(HS_E_ARG, "bad dtype");
-  if (init_basis >= (uint64_t(1) << n)) return fail(HS_E_ARG, "basis index outside the state");
-  if (k < 1) return fail(HS_E_ARG, "k = %d < 1", k);
-  if (strategy < HS_PART_NAT || strategy > HS_PART_CLOSURE)
-    return fail(HS_E_ARG, "unknown strategy %d", (int)strategy);
-  if (arrival_s > t_call) return fail(HS_E_ARG, "arrival time lies in the future");
-  auto r = std::make_unique<Request>();
-  r->n = n;
-  r->k = k;
-  r->dtype = dtype;
-  r->strategy = strategy;
-  r->init = init_basis;
-  r->t_arrival = arrival_s >= 0 ? arrival_s : t_call;
-  r->gates.reserve(count);
-  for (size_t i = 0; i < count; ++i)
-    if (hs_status rc = expand_gate(n, gates[i], &r->gates)) return rc;
-  for (const Gate& g : r->gates)
-    if (g.arity() > k) return fail(HS_E_ARITY_GT_K, "gate wider than k = %d", k);
-  const size_t state_bytes = (size_t(1) << n) * amp_bytes(dtype);
-  if (state_bytes > sv->budget)
-    return fail(HS_E_ADMISSION, "state needs %zu bytes, budget is %zu", state_bytes, sv->budget);
-  std::lock_guard<std::mutex> lk(sv->mu);
-  r->ticket = sv->next_ticket++;
-  *ticket = r->ticket;
-  sv->reqs[r->ticket] = r.get();
-  sv->prep_queue.push_back(r.release());
-  sv->cv.notify_all();
-  return HS_OK;
+  return guarded([&]() -> hs_status {
+    const double t_call = now_s();
+    if (!sv || !ticket || (!gates && count)) return fail(HS_E_ARG, "null argument");
+    if (n < 1 || n > 40) return fail(HS_E_ARG, "n = %d outside [1, 40]", n);
+    if (dtype != HS_C64 && dtype != HS_C128) return fail(HS_E_ARG, "bad dtype");
+    if (init_basis >= (uint64_t(1) << n)) return fail(HS_E_ARG, "basis index outside the state");
+    if (k < 1) return fail(HS_E_ARG, "k = %d < 1", k);
+    if (strategy < HS_PART_NAT || strategy > HS_PART_CLOSURE)
+      return fail(HS_E_ARG, "unknown strategy %d", (int)strategy);
+    if (arrival_s > t_call) return fail(HS_E_ARG, "arrival time lies in the future");
+    auto r = std::make_unique<Request>();
+    r->n = n;
+    r->k = k;
+    r->dtype = dtype;
+    r->strategy = strategy;
+    r->init = init_basis;
+    r->t_arrival = arrival_s >= 0 ? arrival_s : t_call;
+    r->gates.reserve(count);
+    for (size_t i = 0; i < count; ++i)
+      if (hs_status rc = expand_gate(n, gates[i], &r->gates)) return rc;
+    for (const Gate& g : r->gates)
+      if (g.arity() > k) return fail(HS_E_ARITY_GT_K, "gate wider than k = %d", k);
+    const size_t state_bytes = (size_t(1) << n) * amp_bytes(dtype);
+    if (state_bytes > sv->budget)
+      return fail(HS_E_ADMISSION, "state needs %zu bytes, budget is %zu", state_bytes, sv->budget);
+    std::lock_guard<std::mutex> lk(sv->mu);
+    r->ticket = sv->next_ticket++;  // a ticket lost to a failed insert is skipped at admission
+    sv->reqs[r->ticket] = r.get();
+    try {
+      sv->prep_queue.push_back(r.get());
+    } catch (...) {
+      sv->reqs.erase(r->ticket);
+      throw;
+    }
+    *ticket = r.release()->ticket;
+    sv->cv.notify_all();
+    return HS_OK;
+  });
 }
 
 hs_status hs_server_wait(hs_server sv, uint64_t ticket, int64_t timeout_ms) {
-  if (!sv) return fail(HS_E_ARG, "null server");
-  std::unique_lock<std::mutex> lk(sv->mu);
-  Request* r = find(sv, ticket);
-  if (!r) return fail(HS_E_ARG, "unknown ticket %llu", (unsigned long long)ticket);
-  auto ready = [&] { return r->status == RQ_DONE || r->status == RQ_FAILED || r->status == RQ_RELEASED; };
-  if (timeout_ms < 0) sv->cv.wait(lk, ready);
-  else if (!sv->cv.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready))
-    return fail(HS_E_STATE, "ticket %llu not finished", (unsigned long long)ticket);
-  if (r->status == RQ_FAILED) return fail(r->err, "request failed: %s", r->err_msg.c_str());
-  return HS_OK;
+  return guarded([&]() -> hs_status {
+    if (!sv) return fail(HS_E_ARG, "null server");
+    std::unique_lock<std::mutex> lk(sv->mu);
+    Request* r = find(sv, ticket);
+    if (!r) return fail(HS_E_ARG, "unknown ticket %llu", (unsigned long long)ticket);
+    auto ready = [&] { return r->status == RQ_DONE || r->status == RQ_FAILED || r->status == RQ_RELEASED; };
+    if (timeout_ms < 0) sv->cv.wait(lk, ready);
+    else if (!sv->cv.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready))
+      return fail(HS_E_STATE, "ticket %llu not finished", (unsigned long long)ticket);
+    if (r->status == RQ_FAILED) return fail(r->err, "request failed: %s", r->err_msg.c_str());
+    return HS_OK;
+  });
 }
 
 hs_status hs_server_poll(hs_server sv, uint64_t ticket, int* done) {
-  if (!sv || !done) return fail(HS_E_ARG, "null argument");
-  std::lock_guard<std::mutex> lk(sv->mu);
-  Request* r = find(sv, ticket);
-  if (!r) return fail(HS_E_ARG, "unknown ticket");
-  *done = (r->status == RQ_DONE || r->status == RQ_FAILED) ? 1 : 0;
-  return HS_OK;
-}
-
-hs_status hs_server_read(hs_server sv, uint64_t ticket, uint64_t first, uint64_t count, double* out) {
-  if (!sv || (!out && count)) return fail(HS_E_ARG, "null argument");
-  State view;
-  Request* reader = nullptr;
-  {
+  return guarded([&]() -> hs_status {
+    if (!sv || !done) return fail(HS_E_ARG, "null argument");
     std::lock_guard<std::mutex> lk(sv->mu);
     Request* r = find(sv, ticket);
     if (!r) return fail(HS_E_ARG, "unknown ticket");
-    if (r->status == RQ_RELEASED) return fail(HS_E_STATE, "ticket was released");
-    if (r->status != RQ_DONE) return fail(HS_E_STATE, "ticket is not finished");
-    const uint64_t N = uint64_t(1) << r->n;
-    if (first > N || count > N - first) return fail(HS_E_ARG, "range outside the state");
-    if (!count) return HS_OK;
-    view = r->st;
-    reader = r;
-    r->readers++;  // hs_server_release waits for this read before freeing the state
-  }
-  hs_status rc;
-  {
-    // read on a stream of its own (the request's kernels have finished),
-    // staged through the server's persistent buffer
-    std::lock_guard<std::mutex> rl(sv->read_mu);
-    view.stream = sv->read_stream;
-    view.owned = false;
-    view.scratch = sv->read_scratch;
-    view.scratch_bytes = kReadScratch;
-    rc = dev_read(&view, first, count, out, false);
-  }
-  std::lock_guard<std::mutex> lk(sv->mu);
-  if (--reader->readers == 0) sv->cv.notify_all();
-  return rc;
+    *done = (r->status == RQ_DONE || r->status == RQ_FAILED) ? 1 : 0;
+    return HS_OK;
+  });
+}
+
+hs_status hs_server_read(hs_server sv, uint64_t ticket, uint64_t first, uint64_t count, double* out) {
+  return guarded([&]() -> hs_status {
+    if (!sv || (!out && count)) return fail(HS_E_ARG, "null argument");
+    State view;
+    Request* reader = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(sv->mu);
+      Request* r = find(sv, ticket);
+      if (!r) return fail(HS_E_ARG, "unknown ticket");
+      if (r->status == RQ_RELEASED) return fail(HS_E_STATE, "ticket was released");
+      if (r->status != RQ_DONE) return fail(HS_E_STATE, "ticket is not finished");
+      const uint64_t N = uint64_t(1) << r->n;
+      if (first > N || count > N - first) return fail(HS_E_ARG, "range outside the state");
+      if (!count) return HS_OK;
+      view = r->st;
+      reader = r;
+      r->readers++;  // hs_server_release waits for this read before freeing the state
+    }
+    hs_status rc;
+    {
+      // read on a stream of its own (the request's kernels have finished),
+      // staged through the server's persistent buffer
+      std::lock_guard<std::mutex> rl(sv->read_mu);
+      view.stream = sv->read_stream;
+      view.owned = false;
+      view.scratch = sv->read_scratch;
+      view.scratch_bytes = kReadScratch;
+      rc = dev_read(&view, first, count, out, false);
+    }
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (--reader->readers == 0) sv->cv.notify_all();
+    return rc;
+  });
 }
 
 hs_status hs_server_latency(hs_server sv, uint64_t ticket, double* seconds) {
-  if (!sv || !seconds) return fail(HS_E_ARG, "null argument");
-  std::lock_guard<std::mutex> lk(sv->mu);
-  Request* r = find(sv, ticket);
-  if (!r) return fail(HS_E_ARG, "unknown ticket");
-  if (r->status != RQ_DONE && r->status != RQ_RELEASED) return fail(HS_E_STATE, "ticket is not finished");
-  *seconds = r->t_done - r->t_arrival;
-  return HS_OK;
+  return guarded([&]() -> hs_status {
+    if (!sv || !seconds) return fail(HS_E_ARG, "null argument");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    Request* r = find(sv, ticket);
+    if (!r) return fail(HS_E_ARG, "unknown ticket");
+    if (r->status != RQ_DONE && r->status != RQ_RELEASED) return fail(HS_E_STATE, "ticket is not finished");
+    *seconds = r->t_done - r->t_arrival;
+    return HS_OK;
+  });
 }
 
 hs_status hs_server_timing(hs_server sv, uint64_t ticket, double* out4) {
-  if (!sv || !out4) return fail(HS_E_ARG, "null argument");
-  std::lock_guard<std::mutex> lk(sv->mu);
-  Request* r = find(sv, ticket);
-  if (!r) return fail(HS_E_ARG, "unknown ticket");
-  if (r->status != RQ_DONE && r->status != RQ_RELEASED) return fail(HS_E_STATE, "ticket is not finished");
-  out4[0] = r->t_prep0 - r->t_arrival;
-  out4[1] = r->t_prep1 - r->t_prep0;
-  out4[2] = r->t_launch - r->t_prep1;
-  out4[3] = r->t_done - r->t_launch;
-  return HS_OK;
+  return guarded([&]() -> hs_status {
+    if (!sv || !out4) return fail(HS_E_ARG, "null argument");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    Request* r = find(sv, ticket);
+    if (!r) return fail(HS_E_ARG, "unknown ticket");
+    if (r->status != RQ_DONE && r->status != RQ_RELEASED) return fail(HS_E_STATE, "ticket is not finished");
+    out4[0] = r->t_prep0 - r->t_arrival;
+    out4[1] = r->t_prep1 - r->t_prep0;
+    out4[2] = r->t_launch - r->t_prep1;
+    out4[3] = r->t_done - r->t_launch;
+    return HS_OK;
+  });
 }
 
 hs_status hs_server_release(hs_server sv, uint64_t ticket) {
-  if (!sv) return fail(HS_E_ARG, "null server");
-  std::unique_ptr<Plan> plan;
-  void* state = nullptr;
-  hipStream_t stream = nullptr;
-  std::vector<hipEvent_t> events;
-  bool drain = false;
-  {
-    std::unique_lock<std::mutex> lk(sv->mu);
-    Request* r = find(sv, ticket);
-    if (!r) return fail(HS_E_ARG, "unknown ticket");
-    // reads of its state still copying finish first (a read that starts
-    // later finds the ticket released)
-    sv->cv.wait(lk, [&] { return r->readers == 0; });
-    if (r->status == RQ_RELEASED) return HS_OK;
-    if (r->status != RQ_DONE && r->status != RQ_FAILED) return fail(HS_E_STATE, "ticket is not finished");
-    if (r->status == RQ_DONE) {
-      state = r->st.ptr;
-      stream = (hipStream_t)r->st.stream;
-      r->st.ptr = nullptr;
-      sv->cur_bytes -= r->bytes;
+  return guarded([&]() -> hs_status {
+    if (!sv) return fail(HS_E_ARG, "null server");
+    std::unique_ptr<Plan> plan;
+    void* state = nullptr;
+    hipStream_t stream = nullptr;
+    std::vector<hipEvent_t> events;
+    bool drain = false;
+    {
+      std::unique_lock<std::mutex> lk(sv->mu);
+      Request* r = find(sv, ticket);
+      if (!r) return fail(HS_E_ARG, "unknown ticket");
+      // reads of its state still copying finish first (a read that starts
+      // later finds the ticket released)
+      sv->cv.wait(lk, [&] { return r->readers == 0; });
+      if (r->status == RQ_RELEASED) return HS_OK;
+      if (r->status != RQ_DONE && r->status != RQ_FAILED) return fail(HS_E_STATE, "ticket is not finished");
+      if (r->status == RQ_DONE) {
+        state = r->st.ptr;
+        stream = (hipStream_t)r->st.stream;
+        r->st.ptr = nullptr;
+        sv->cur_bytes -= r->bytes;
+      }
+      if (r->status == RQ_FAILED && r->launched) {
+        drain = true;
+        stream = (hipStream_t)r->st.stream;
+      }
+      events = {r->done, r->chunk_ev[0], r->chunk_ev[1]};
+      r->done = r->chunk_ev[0] = r->chunk_ev[1] = nullptr;
+      plan = std::move(r->plan);
+      r->status = RQ_RELEASED;
+      sv->cv.notify_all();
     }
-    if (r->status == RQ_FAILED && r->launched) {
-      drain = true;
-      stream = (hipStream_t)r->st.stream;
-    }
-    events = {r->done, r->chunk_ev[0], r->chunk_ev[1]};
-    r->done = r->chunk_ev[0] = r->chunk_ev[1] = nullptr;
-    plan = std::move(r->plan);
-    r->status = RQ_RELEASED;
-    sv->cv.notify_all();
-  }
-  // a finished request's kernels are complete: the frees are stream-ordered
-  // and wait for nothing on the device
-  drop_request_memory(sv, std::move(plan), state, stream, events, drain);
-  return HS_OK;
+    // a finished request's kernels are complete: the frees are stream-ordered
+    // and wait for nothing on the device
+    drop_request_memory(sv, std::move(plan), state, stream, events, drain);
+    return HS_OK;
+  });
 }
 
 hs_status hs_server_stats(hs_server sv, uint64_t* completed, uint64_t* peak_bytes, uint64_t* cur_bytes,
                           int* peak_inflight) {
-  if (!sv) return fail(HS_E_ARG, "null server");
-  std::lock_guard<std::mutex> lk(sv->mu);
-  if (completed) *completed = sv->completed;
-  if (peak_bytes) *peak_bytes = sv->peak_bytes;
-  if (cur_bytes) *cur_bytes = sv->cur_bytes;
-  if (peak_inflight) *peak_inflight = sv->peak_inflight;
-  return HS_OK;
+  return guarded([&]() -> hs_status {
+    if (!sv) return fail(HS_E_ARG, "null server");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (completed) *completed = sv->completed;
+    if (peak_bytes) *peak_bytes = sv->peak_bytes;
+    if (cur_bytes) *cur_bytes = sv->cur_bytes;
+    if (peak_inflight) *peak_inflight = sv->peak_inflight;
+    return HS_OK;
+  });
 }
 
 hs_status hs_server_destroy(hs_server sv) {
-  if (!sv) return HS_OK;
-  {
-    std::lock_guard<std::mutex> lk(sv->mu);
-    sv->stop = true;
-    sv->cv.notify_all();
-  }
-  for (auto& t : sv->preppers)
-    if (t.joinable()) t.join();
-  if (sv->worker.joinable()) sv->worker.join();
-  (void)hipSetDevice(sv->device);
-  for (auto& kv : sv->reqs) {
-    Request* r = kv.second;
-    if (r->st.ptr) (void)hipFreeAsync(r->st.ptr, (hipStream_t)r->st.stream);
-    for (hipEvent_t ev : {r->done, r->chunk_ev[0], r->chunk_ev[1]})
-      if (ev) (void)hipEventDestroy(ev);
-    delete r;  // plan descriptors: hipFreeAsync on the preparing stream
-  }
-  for (hipStream_t s : sv->streams) {
-    (void)hipStreamSynchronize(s);
-    (void)hipStreamDestroy(s);
-  }
-  for (hipStream_t s : sv->prep_streams) {
-    (void)hipStreamSynchronize(s);
-    (void)hipStreamDestroy(s);
-  }
-  (void)hipStreamSynchronize(sv->read_stream);
-  (void)hipStreamDestroy(sv->read_stream);
-  if (sv->read_scratch) (void)hipFree(sv->read_scratch);
-  for (PinnedStaging& p : sv->pins) {  // every copy from them has run
-    if (p.ptr) (void)hipHostFree(p.ptr);
-    if (p.busy) (void)hipEventDestroy((hipEvent_t)p.busy);
-  }
-  delete sv;
-  return HS_OK;
+  return guarded([&]() -> hs_status {
+    if (!sv) return HS_OK;
+    {
+      std::lock_guard<std::mutex> lk(sv->mu);
+      sv->stop = true;
+      sv->cv.notify_all();
+    }
+    for (auto& t : sv->preppers)
+      if (t.joinable()) t.join();
+    if (sv->worker.joinable()) sv->worker.join();
+    (void)hipSetDevice(sv->device);
+    for (auto& kv : sv->reqs) {
+      Request* r = kv.second;
+      if (r->st.ptr) (void)hipFreeAsync(r->st.ptr, (hipStream_t)r->st.stream);
+      for (hipEvent_t ev : {r->done, r->chunk_ev[0], r->chunk_ev[1]})
+        if (ev) (void)hipEventDestroy(ev);
+      delete r;  // plan descriptors: hipFreeAsync on the preparing stream
+    }
+    for (hipStream_t s : sv->streams) {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+    }
+    for (hipStream_t s : sv->prep_streams) {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+    }
+    (void)hipStreamSynchronize(sv->read_stream);
+    (void)hipStreamDestroy(sv->read_stream);
+    if (sv->read_scratch) (void)hipFree(sv->read_scratch);
+    for (PinnedStaging& p : sv->pins) {  // every copy from them has run
+      if (p.ptr) (void)hipHostFree(p.ptr);
+      if (p.busy) (void)hipEventDestroy((hipEvent_t)p.busy);
+    }
+    delete sv;
+    return HS_OK;
+  });
 }
 
 }  // extern "C"

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libhisv.so")
 HS_OK = 0
 STATUS = {0: "HS_OK", 1: "HS_E_ARG", 2: "HS_E_QUBIT_RANGE", 3: "HS_E_ARITY_GT_K",
           4: "HS_E_NOMEM", 5: "HS_E_ADMISSION", 6: "HS_E_HIP", 7: "HS_E_BAD_PARTITION",
-          8: "HS_E_STATE", 9: "HS_E_UNSUPPORTED"}
+          8: "HS_E_STATE", 9: "HS_E_UNSUPPORTED", 10: "HS_E_INTERNAL"}
 DTYPES = {"c64": 0, "c128": 1}
 KINDS = {"h": 0, "x": 1, "y": 2, "z": 3, "s": 4, "t": 5, "rx": 6, "ry": 7, "rz": 8,
          "p": 9, "u3": 10, "cx": 11, "cz": 12, "cp": 13, "swap": 14, "ccx": 15, "cswap": 16}

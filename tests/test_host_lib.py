@@ -804,3 +804,82 @@ def test_tune_rejects_out_of_range_values():
     for key, value, default in [("serve_chunk", 32, 8), ("host_threads", 2, 0), ("fused_shape", 2, -1)]:
         hisv.hs_tune(key, value)
         hisv.hs_tune(key, default)
+
+
+_NOMEM_SCRIPT = r"""
+import ctypes as C, resource, sys
+sys.path.insert(0, sys.argv[1])
+from paper_2205_06973_amd import hisv
+L = hisv.lib()
+count = 4_000_000                      # 160 MB of gates once copied into the library
+arr = (hisv.hs_gate * count)()         # H (kind 0) on qubit 0, allocated before the cap
+assert C.sizeof(hisv.hs_gate) == 40
+import numpy as np
+np.frombuffer(arr, dtype=np.int32).reshape(count, 10)[:, 2] = -1  # q1: none
+h = C.c_void_p()
+page = resource.getpagesize()
+vm = int(open("/proc/self/statm").read().split()[0]) * page
+soft, hard = resource.getrlimit(resource.RLIMIT_AS)
+resource.setrlimit(resource.RLIMIT_AS, (vm + (48 << 20), hard))
+rc = L.hs_circuit_load(30, arr, C.c_size_t(count), C.byref(h))
+msg = L.hs_last_error()
+resource.setrlimit(resource.RLIMIT_AS, (soft, hard))
+print("capped", hisv.STATUS[rc], C.cast(msg, C.c_char_p).value.decode())
+rc = L.hs_circuit_load(30, arr, C.c_size_t(count), C.byref(h))
+print("uncapped", hisv.STATUS[rc])
+L.hs_circuit_destroy(h)
+"""
+
+
+def test_allocation_failure_is_a_status_not_an_abort():
+    """No C++ exception crosses the C boundary: a host allocation that fails
+    inside the library (address space capped in a child process) comes back
+    as HS_E_NOMEM, and the same call succeeds once memory is there."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, "-c", _NOMEM_SCRIPT, ROOT], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = r.stdout.splitlines()
+    assert lines[0].startswith("capped HS_E_NOMEM host allocation failed"), r.stdout
+    assert lines[1] == "uncapped HS_OK", r.stdout
+
+
+def test_status_names_match_the_header():
+    with open(os.path.join(ROOT, "include", "hisv.h")) as f:
+        text = f.read()
+    pairs = re.findall(r"^\s*(HS_(?:OK|E_\w+))\s*=\s*(\d+)", text, re.M)
+    assert {int(v): k for k, v in pairs} == hisv.STATUS
+
+
+_NO_THREADS_SCRIPT = r"""
+import ctypes as C, resource, sys
+sys.path.insert(0, sys.argv[1])
+import numpy as np
+from paper_2205_06973_amd import hisv
+from paper_2205_06973_amd import workloads as wl
+n, gates = wl.layered28(4, n=14, layers=12)
+c = hisv.Circuit(n, gates)
+free = hisv.Plan.partition(c, 5, "closure", seed=0, trials=16).part_of_gate()
+page = resource.getpagesize()
+vm = int(open("/proc/self/statm").read().split()[0]) * page
+soft, hard = resource.getrlimit(resource.RLIMIT_AS)
+resource.setrlimit(resource.RLIMIT_AS, (vm + (6 << 20), hard))  # no room for an 8 MiB thread stack
+try:
+    capped = hisv.Plan.partition(c, 5, "closure", seed=0, trials=16).part_of_gate()
+finally:
+    resource.setrlimit(resource.RLIMIT_AS, (soft, hard))
+print("same" if np.array_equal(free, capped) else "different", len(set(free.tolist())))
+"""
+
+
+def test_closure_beam_runs_alone_when_threads_cannot_start():
+    """The beam's helper threads cannot be started (address space capped in
+    a child process below one thread stack): the search runs on the calling
+    thread and returns the same partition."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, "-c", _NO_THREADS_SCRIPT, ROOT], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stdout.split()[0] == "same", r.stdout
