@@ -241,7 +241,8 @@ hs_status hs_circuit_destroy(hs_circuit c);
  * trials > 1 searches a beam of that many partial partitions (on up to 8
  * host threads; the result does not depend on their number).
  * Parts are numbered in a topological order of the part-graph.
- * HS_E_ARITY_GT_K if a gate is wider than k; HS_E_ARG if k < 1. */
+ * HS_E_ARITY_GT_K if a gate is wider than k; HS_E_ARG if k < 1, trials < 1
+ * (DFS, GREEDY, CLOSURE) or a CLOSURE beam wider than 65536. */
 hs_status hs_partition(hs_circuit c, int k, hs_strategy strategy, uint64_t seed,
                        int trials, hs_plan* out);
 

@@ -378,6 +378,10 @@ hs_status hs_circuit_destroy(hs_circuit c) {
 
 // ---- plans -------------------------------------------------------------------
 
+// CLOSURE keeps up to `trials` partial partitions and their expansions: a
+// bound on the beam keeps a mistyped width from reserving gigabytes.
+constexpr int kMaxBeam = 65536;
+
 hs_status hs_partition(hs_circuit c, int k, hs_strategy strategy, uint64_t seed, int trials,
                        hs_plan* out) {
   return guarded([&]() -> hs_status {
@@ -399,7 +403,8 @@ hs_status hs_partition(hs_circuit c, int k, hs_strategy strategy, uint64_t seed,
         partition_greedy(c->gates, dag, k, seed, trials, &part);
         break;
       case HS_PART_CLOSURE:
-        CHECK_ARG(trials >= 1, "CLOSURE needs trials >= 1");
+        CHECK_ARG(trials >= 1 && trials <= kMaxBeam, "CLOSURE beam width %d outside [1, %d]", trials,
+                  kMaxBeam);
         partition_closure(c->gates, dag, k, trials, &part);
         break;
       default: return fail(HS_E_ARG, "unknown strategy %d", (int)strategy);
@@ -439,7 +444,8 @@ hs_status hs_partition_multilevel(hs_circuit c, int tile_qubits, int pad_qubits,
         partition_greedy(c->gates, dag, tile_qubits, seed, trials, &part, pad);
         break;
       case HS_PART_CLOSURE:
-        CHECK_ARG(trials >= 1, "CLOSURE needs trials >= 1");
+        CHECK_ARG(trials >= 1 && trials <= kMaxBeam, "CLOSURE beam width %d outside [1, %d]", trials,
+                  kMaxBeam);
         partition_closure(c->gates, dag, tile_qubits, trials, &part, pad);
         break;
       default: return fail(HS_E_ARG, "unknown strategy %d", (int)strategy);

@@ -883,3 +883,19 @@ def test_closure_beam_runs_alone_when_threads_cannot_start():
                        text=True, timeout=120)
     assert r.returncode == 0, r.stderr[-2000:]
     assert r.stdout.split()[0] == "same", r.stdout
+
+
+def test_partition_rejects_bad_trials():
+    """trials < 1 for the strategies that use it, and a CLOSURE beam wider
+    than 65,536, are argument errors (the beam is allocated up front)."""
+    n, gates = wl.random34(0, n=10, num_gates=40)
+    c = hisv.Circuit(n, gates)
+    for strategy in ("dfs", "greedy", "closure"):
+        with pytest.raises(hisv.HisvError) as e:
+            hisv.Plan.partition(c, 4, strategy, seed=0, trials=0)
+        assert e.value.code == "HS_E_ARG"
+    for call in (lambda t: hisv.Plan.partition(c, 4, "closure", trials=t),
+                 lambda t: hisv.Plan.partition_multilevel(c, 6, 2, "closure", trials=t)):
+        with pytest.raises(hisv.HisvError, match="beam width 65537"):
+            call(65537)
+        assert call(2).num_parts >= 1
